@@ -1,0 +1,107 @@
+"""Meta-solvers (oracle): eq. 3 of §3.1.1 and the Krylov variant of §3.1.2.
+
+Relaxation meta-solver (eq. 3): a cycle is M1 = ``n_r`` relaxation sweeps
+(damped Jacobi or red-black Gauss-Seidel) followed by M2 = one DeepONet
+correction computed from the residual after the sweeps.  Reading: the
+network is applied after sweeps n_r, 2 n_r, ...; the relative residual is
+checked after every correction (or every n_r sweeps without a network);
+the count is in sweeps.
+
+Krylov preconditioner (§3.1.2 with App. C): M(r) is eq. 3 started from
+z = 0 on A z = r, i.e. ``n_r`` smoother sweeps, then the residual
+r1 = r - A z and z <- z + M2 r1 with the linear trunk-basis M2.  Because the
+sweep count is fixed and M2 is linear, M is a fixed linear operator and is
+used as a right preconditioner.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import operator as op
+from . import krylov
+from . import deeponet as don
+from .coarse import CoarseSpace
+
+JACOBI, RBGS = "jacobi", "rbgs"
+
+
+def sweep(kind, u, f, s, mask, omega):
+    if kind == JACOBI:
+        return op.jacobi_sweep(u, f, s, mask, omega)
+    if kind == RBGS:
+        return op.rbgs_sweep(u, f, s, mask, omega)
+    raise ValueError(kind)
+
+
+def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, correction=None,
+                    history=None):
+    """eq. 3 with M1 = nn_every sweeps and M2 = ``correction(r)`` (or none).
+
+    Returns (u, info)."""
+    u = np.array(u0, dtype=np.complex128)
+    fn = np.linalg.norm(f)
+    count = 0
+    ncorr = 0
+    status = krylov.NOT_CONVERGED
+    while count < max_sweeps:
+        cyc = min(nn_every, max_sweeps - count) if nn_every > 0 else max_sweeps - count
+        for _ in range(cyc):
+            u = sweep(kind, u, f, s, mask, omega)
+            count += 1
+        r = op.residual(u, f, s, mask)
+        if correction is not None and nn_every > 0 and cyc == nn_every:
+            u = u + correction(r)
+            ncorr += 1
+            r = op.residual(u, f, s, mask)
+        rel = np.linalg.norm(r) / fn if fn > 0 else 0.0
+        if history is not None:
+            history.append(rel)
+        if not np.isfinite(rel):
+            status = krylov.NONFINITE
+            break
+        if rel <= tol:
+            status = krylov.CONVERGED
+            break
+    rel = np.linalg.norm(op.residual(u, f, s, mask)) / fn if fn > 0 else 0.0
+    return u, dict(status=status, iters=count, rel_res=rel, corrections=ncorr)
+
+
+def deeponet_correction(s_field, mask, T, net):
+    """M2 of eq. 3: the DeepONet acting on the residual."""
+    def corr(r):
+        return don.infer(r, mask, T, net["branch"], net["head"], net["p"], net["branch_grid"],
+                         k=net.get("k"), k_input=net.get("k_input", False), act=net.get("act", "tanh"))
+    return corr
+
+
+def krylov_preconditioner(s, mask, smoother, n_r, omega, coarse: CoarseSpace | None):
+    """M(r): n_r sweeps from zero, then the coarse correction of the residual."""
+    shape = np.shape(s)
+
+    def M(v):
+        r = v.reshape(shape)
+        z = np.zeros(shape, dtype=np.complex128)
+        for _ in range(n_r):
+            z = sweep(smoother, z, r, s, mask, omega)
+        if coarse is not None:
+            r1 = r - op.apply(z, s, mask)
+            z = z + coarse.m2(r1)
+        return z.ravel()
+    return M
+
+
+def krylov_meta(kind, f, u0, s, mask, restart, tol, max_iters, precond=None, history=None):
+    """GMRES(m) or BiCGStab on A u = f, right-preconditioned by ``precond``."""
+    shape = np.shape(f)
+
+    def A(v):
+        return op.apply(v.reshape(shape), s, mask).ravel()
+    ff = np.asarray(f, dtype=np.complex128).ravel()
+    u0f = np.asarray(u0, dtype=np.complex128).ravel()
+    if kind == "gmres":
+        u, info = krylov.gmres(A, ff, u0f, restart, tol, max_iters, M=precond, history=history)
+    elif kind == "bicgstab":
+        u, info = krylov.bicgstab(A, ff, u0f, tol, max_iters, M=precond, history=history)
+    else:
+        raise ValueError(kind)
+    return u.reshape(shape), info
