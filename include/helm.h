@@ -1,0 +1,244 @@
+/*
+ * helm.h -- C ABI of libhelm, a GPU library for the DeepONet meta-solvers of
+ * Helmholtz scattering problems (Lee, Liu, Zou, Kahana, Turkel, Ranade, Pathak,
+ * Karniadakis: "Fast meta-solvers for 3D complex-shape scatterers using neural
+ * operators trained on a non-scattering problem", arXiv 2405.12380).
+ *
+ * Problem (§2, eq. 1, finite-difference form on a uniform grid):
+ *     -Delta_h u - k^2 (1 + i alpha) u = f   on unmasked nodes,  u = 0 on the scatterer.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Grid     : n[a] interior nodes on axis a (x = 0, y = 1, z = 2); spacing
+ *            h_a = 1/(n[a]+1); node i sits at (i+1) h_a; the layer of nodes just
+ *            outside the box is a zero ghost layer.  dim = 2 uses n[0], n[1]
+ *            (n[2] is ignored and taken as 1).
+ * Layout   : fields are contiguous arrays of n = n[0]*n[1]*n[2] nodes in x-fastest
+ *            order, p = i + n[0]*(j + n[1]*l).  A complex field is interleaved
+ *            (re, im): complex64 = 2 x float, complex128 = 2 x double.  The op's
+ *            dtype fixes the dtype of every field passed to it.
+ * Pointers : unless stated otherwise, field pointers are HIP device pointers owned
+ *            by the caller; they must not alias each other unless stated.
+ * Streams  : `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *            Work is enqueued on it; calls documented as synchronous wait for it.
+ * Errors   : every call returns a helm_status.  0 = success; 1 = the result is
+ *            valid but the iteration did not reach its tolerance; negative values
+ *            are errors.  Argument errors (HELM_E_INVAL) are detected before any
+ *            work is enqueued and leave every output untouched.  The text of the
+ *            last error on the calling thread is returned by helm_last_error().
+ * Threads  : an op or a network may be used by one thread / stream at a time.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HELM_OK = 0,
+  HELM_NOT_CONVERGED = 1,
+  HELM_E_INVAL = -1,     /* malformed argument; nothing was enqueued            */
+  HELM_E_NOMEM = -2,     /* device allocation failed                            */
+  HELM_E_HIP = -3,       /* a HIP runtime call failed                           */
+  HELM_E_BREAKDOWN = -4, /* BiCGStab rho, r_hat^H v or omega became exactly 0   */
+  HELM_E_NONFINITE = -5, /* a residual norm became Inf or NaN                   */
+  HELM_E_SINGULAR = -6   /* the coarse matrix or a Gram factor lost rank        */
+} helm_status;
+
+typedef enum { HELM_C64 = 1, HELM_C128 = 2 } helm_dtype;
+
+typedef struct {
+  int dim;  /* 2 or 3 */
+  int n[3]; /* interior nodes per axis, each >= 3 */
+} helm_grid;
+
+typedef struct helm_op_s* helm_op;
+typedef struct don_s* don_net;
+
+/* relaxation kinds for helm_relax and the smoother of meta_solve */
+enum { HELM_JACOBI = 0, HELM_RBGS = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* Operator                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Build the discrete operator of §2 eq. 1 on grid g:
+ *   (A x)_p = sum_a (1/h_a^2) [(x_p - x_{p-e_a}) + (x_p - x_{p+e_a})] - s_p x_p,
+ *   s_p = ksq_p (1 + i alpha_p),                                     (mask_p = 0)
+ *   (A x)_p = x_p                                                    (mask_p != 0)
+ * where ghost and masked neighbours contribute 0 (the Dirichlet scatterer of
+ * §2 is eliminated symmetrically, so A is complex symmetric).
+ * ksq, alpha: device arrays of n doubles (k^2 and the sponge damping alpha >= 0).
+ * mask: device array of n bytes, nonzero on scatterer nodes.
+ * The inputs are copied; the call is synchronous on `stream`.
+ * Errors: HELM_E_INVAL for a NULL pointer, dim not 2/3, n[a] < 3, a node count
+ * beyond 2^31, or an unknown dtype. */
+helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, const double* alpha,
+                       const uint8_t* mask, void* stream, helm_op* out);
+
+/* Replace k^2 (device array of n doubles, same alpha and mask).  Invalidates the
+ * cached coarse space.  Synchronous. */
+helm_status helm_set_ksq(helm_op op, const double* ksq, void* stream);
+
+/* Release an op and its device memory.  NULL is ignored. */
+void helm_destroy(helm_op op);
+
+/* Number of grid nodes of an op (0 for NULL). */
+size_t helm_size(helm_op op);
+
+/* y = A x (§2 eq. 1 as above).  x, y: complex fields; must not alias.  Async. */
+helm_status helm_apply(helm_op op, const void* x, void* y, void* stream);
+
+/* r = f - A u (the residual of eq. 2).  If rnorm is non-NULL the call waits for
+ * the stream and stores ||r||_2 there (host double).  r must not alias f or u. */
+helm_status helm_residual(helm_op op, const void* f, const void* u, void* r, double* rnorm,
+                          void* stream);
+
+/* `sweeps` relaxation steps of eq. 2 on A u = f, in place on u (§3.1.1):
+ *   HELM_JACOBI: u <- u + omega D^{-1}(f - A u), D = diag(A)
+ *                (D_p = sum_a 2/h_a^2 - s_p; 1 on masked nodes);
+ *   HELM_RBGS  : the same update applied to the nodes with (i+j+l) even, then
+ *                to the odd ones using the new even values (red-black
+ *                Gauss-Seidel; SOR when omega != 1).
+ * Async.  Uses op-owned scratch memory. */
+helm_status helm_relax(helm_op op, int kind, double omega, int sweeps, const void* f, void* u,
+                       void* stream);
+
+/* Krylov inner products (synchronous): out[0] + i out[1] = sum conj(x_p) y_p. */
+helm_status helm_dot(helm_op op, const void* x, const void* y, double out[2], void* stream);
+/* ||x||_2 (synchronous). */
+helm_status helm_nrm2(helm_op op, const void* x, double* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* DeepONet (App. B architecture, App. C trunk matrix)                      */
+/* ------------------------------------------------------------------------ */
+
+enum { DON_TANH = 0, DON_RELU = 1, DON_LEAKY = 2 };
+/* Output heads.  SPLIT_OUTPUT: the branch emits 2p values b, and
+ *   N(r) = T b[0:p] + i T b[p:2p]   (the head of App. B);
+ * SPLIT_INPUT: the branch emits p values and is applied to Re and Im of the
+ * input separately, N(r) = T branch(Re r) + i T branch(Im r). */
+enum { DON_SPLIT_OUTPUT = 0, DON_SPLIT_INPUT = 1 };
+enum { DON_TRUNK = 0, DON_FULL = 1 };
+
+typedef struct {
+  int n_branch;        /* number of widths in branch_w (layers + 1)                 */
+  const int* branch_w; /* widths, input first.  Input = 2*prod(branch_grid) (+1 if
+                          k_input) for SPLIT_OUTPUT, prod(branch_grid) for SPLIT_INPUT */
+  int n_trunk;         /* number of widths in trunk_w                                  */
+  const int* trunk_w;  /* widths; trunk_w[0] = grid dim, last = p                     */
+  int act;             /* hidden-layer activation (DON_TANH, ...); last layers linear */
+  int head;            /* DON_SPLIT_OUTPUT or DON_SPLIT_INPUT                          */
+  int p;               /* number of trunk basis functions, 1..128                      */
+  int branch_grid[3];  /* grid the branch samples its input on (z = 1 in 2D)          */
+  int k_input;         /* 1: the wave number is appended to the branch input          */
+} don_desc;
+
+/* Upload a network.  Wb = host pointers to W0, b0, W1, b1, ... for the branch
+ * layers followed by the trunk layers; W_l is row-major (fan_in x fan_out) so that
+ * a layer computes h' = act(h W + b).  Weights are stored in the dtype's real
+ * precision (float for HELM_C64, double for HELM_C128).  Synchronous. */
+helm_status deeponet_load(helm_dtype dt, const don_desc* d, const double* const* Wb, don_net* out);
+void deeponet_free(don_net net);
+
+/* DON_TRUNK: out = T, the n x p trunk matrix [T]_ij = T_j(x_i) at the op's node
+ *            coordinates x_i (App. C), row-major, real (float or double per dtype).
+ * DON_FULL : out = du = s N(r/s) with s = ||r||_2/sqrt(n) (du = 0 if r = 0), set to
+ *            0 on masked nodes: the network correction M2 of eq. 3.  r and out
+ *            are complex fields; the branch samples r/s on branch_grid (identity
+ *            when it equals the op's grid, multilinear with zero ghosts otherwise).
+ * k is the wave number fed to the branch when k_input is set.  Async. */
+helm_status deeponet_infer(don_net net, helm_op op, int mode, const void* r, double k, void* out,
+                           void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Meta-solvers (§3.1.1 eq. 3; §3.1.2 with the trunk basis of App. C)       */
+/* ------------------------------------------------------------------------ */
+
+enum { META_JACOBI = 0, META_GS = 1, META_GMRES = 2, META_BICGSTAB = 3 };
+
+typedef struct {
+  int kind;        /* META_*                                                        */
+  int restart;     /* GMRES(m): m >= 1                                              */
+  double tol;      /* stop when ||f - A u||_2 <= tol ||f||_2 (tol >= 0)             */
+  int max_iters;   /* Arnoldi steps / BiCGStab iterations / relaxation sweeps       */
+  int smoother;    /* HELM_JACOBI or HELM_RBGS                                      */
+  int n_r;         /* sweeps per cycle (relaxation) or per preconditioner (Krylov)  */
+  double omega;    /* relaxation weight                                             */
+  int nn_every;    /* relaxation kinds: network correction after every nn_every sweeps */
+  int p_used;      /* Krylov kinds with a network: trunk columns used (1..p)        */
+  double k;        /* wave number passed to a network with k_input                  */
+  double* history; /* optional host array of max_iters+1 relative residuals, or NULL */
+} meta_opts;
+
+typedef struct {
+  int iters, matvecs, precond_apps, converged, rank_used, history_len;
+  double rel_res;     /* true ||f - A u||_2 / ||f||_2 at exit                         */
+  double setup_ms;    /* coarse-space construction time (0 when cached)               */
+  double solve_ms;    /* iteration time                                               */
+  double cond_Ac_est; /* 1-norm condition estimate of the coarse matrix               */
+} meta_stats;
+
+/* Solve A u = f.
+ *   META_JACOBI / META_GS: eq. 3 with M1 = nn_every smoother sweeps and M2 = the
+ *     network correction (DON_FULL) when net != NULL; plain relaxation otherwise.
+ *   META_GMRES / META_BICGSTAB: right-preconditioned GMRES(restart) with CGS2, or
+ *     BiCGStab, on the true relative residual.  With net != NULL the
+ *     preconditioner is M(r) = eq. 3 from z = 0: n_r smoother sweeps on A z = r,
+ *     then z += Q A_c^{-1} Q^T (r - A z) where Q spans the first p_used masked
+ *     trunk columns (QR with positive diag R; columns whose remaining norm is at
+ *     most tau times the largest column norm are dropped, tau = 1e-7 (C128),
+ *     1e-5 (C64)) and A_c = Q^T A Q (App. C).  With net == NULL, M = I.
+ * u holds u0 on entry and the last iterate on exit (also when not converged).
+ * The coarse space is cached on the op, keyed by (net, p_used, k^2 version).
+ * Synchronous.  Returns HELM_OK, HELM_NOT_CONVERGED, HELM_E_BREAKDOWN,
+ * HELM_E_NONFINITE, HELM_E_SINGULAR or an argument/HIP error. */
+helm_status meta_solve(helm_op op, don_net net, const meta_opts* o, const void* f, void* u,
+                       meta_stats* st, void* stream);
+
+/* z = M(r), the Krylov preconditioner that meta_solve would use for opts o
+ * (M = the n_r smoother sweeps alone when net is NULL).  Builds or reuses the
+ * coarse space.  r, z: complex fields, no aliasing.  Synchronous. */
+helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void* r, void* z,
+                         void* stream);
+
+/* Inspect the cached coarse space for (net, o->p_used): rank, and optionally the
+ * coarse matrix A_c (host, rank x rank complex128, row-major, interleaved, capacity
+ * `ac_cap` complex entries) and Q (device, n x rank, row-major, real in the dtype's
+ * precision, capacity `q_cap` elements).  Synchronous. */
+helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* rank, double* Ac,
+                             size_t ac_cap, void* Q, size_t q_cap, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement hook                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Kernel classes timed by the hook. */
+enum { HELM_KP_STENCIL = 0,   /* apply / residual / Jacobi / red-black sweeps      */
+       HELM_KP_MULTIDOT = 1,  /* GMRES multi-dot V^H w                              */
+       HELM_KP_MULTIAXPY = 2, /* GMRES multi-axpy w -= V h and V y                  */
+       HELM_KP_QT = 3,        /* coarse restriction Q^T r (per-block partials)      */
+       HELM_KP_SKINNY = 4 };  /* prolongation z += Q c and the DeepONet synthesis   */
+
+/* Enable (1) or disable (0) per-kernel timing for the whole process, clearing
+ * earlier records (waits for the device).  While enabled, each launch of a timed
+ * kernel is bracketed by two HIP events on its stream, and the algorithmic bytes
+ * that launch must move (reads + writes of its operands, each once) are recorded. */
+helm_status helm_kprof_enable(int on);
+/* Totals since the last enable for one kernel class: launches, summed
+ * event-measured duration (ms) and summed algorithmic bytes.  Waits for the
+ * recorded events. */
+helm_status helm_kprof_read(int kind, int* count, double* total_ms, double* total_bytes);
+
+/* Text for a status code / the calling thread's last error message. */
+const char* helm_strerror(helm_status s);
+const char* helm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

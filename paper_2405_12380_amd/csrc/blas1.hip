@@ -1,0 +1,455 @@
+// Krylov vector kernels: deterministic two-stage reductions (complex inner
+// products <x, y> = sum conj(x_i) y_i, norms, the GMRES multi-dot V^H w) and
+// the vector updates of GMRES/BiCGStab, all accumulating in fp64.
+//
+// Reductions run on a fixed grid whose size depends only on n, every block
+// writes its partial to a fixed slot, and the second stage sums the partials
+// in index order: results are bitwise reproducible run to run.
+#include "common.h"
+#include "internal.h"
+#include "prof.h"
+
+namespace helm {
+
+static constexpr int RED_MAXB = 1024;
+
+int red_nblocks(size_t n) {
+  size_t nb = (n + 255) / 256;
+  if (nb > RED_MAXB) nb = RED_MAXB;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part, int nparts, int width,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int w = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[(size_t)b * width + w];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[w] = acc;
+}
+
+void reduce_cols(const double* part, int nparts, int width, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_cols, dim3(width), dim3(256), 0, st, part, nparts, width, out);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_dot_part(size_t n, const cplx_t<S>* __restrict__ x,
+                                                  const cplx_t<S>* __restrict__ y, double* __restrict__ part) {
+  __shared__ double sh[32];
+  double2 acc = czero();
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    acc = cadd(acc, cconjmul(ldc(x, e), ldc(y, e)));
+  acc = block_sum2(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = acc.x;
+    part[2 * blockIdx.x + 1] = acc.y;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_nrm2_part(size_t n, const cplx_t<S>* __restrict__ x,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = ldc(x, e);
+    acc += v.x * v.x + v.y * v.y;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <typename S>
+void dot_part(size_t n, const void* x, const void* y, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_dot_part<S>), dim3(red_nblocks(n)), dim3(256), 0, st, n, (const C*)x, (const C*)y, part);
+}
+template <typename S>
+void nrm2_part(size_t n, const void* x, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_nrm2_part<S>), dim3(red_nblocks(n)), dim3(256), 0, st, n, (const C*)x, part);
+}
+
+// ---- multi-dot --------------------------------------------------------------
+// Each thread keeps E elements of w in registers; for every basis vector the
+// 64-lane partial is formed with shuffles and parked in LDS; one barrier at
+// the end combines the four wavefronts.  At most MD_CHUNK vectors per launch.
+static constexpr int MD_CHUNK = 64;
+
+static int md_elems(size_t n) {
+  if (n <= (size_t)1 << 20) return 1;
+  if (n <= (size_t)1 << 21) return 2;
+  if (n <= (size_t)1 << 22) return 4;
+  return 8;
+}
+int multidot_nblocks(size_t n) {
+  const int E = md_elems(n);
+  return (int)((n + 256 * (size_t)E - 1) / (256 * (size_t)E));
+}
+
+template <typename S, int E>
+__global__ __launch_bounds__(256) void k_multidot(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int i0,
+                                                  int nv, int stride, const cplx_t<S>* __restrict__ w,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[4][2 * MD_CHUNK];
+  const size_t base = (size_t)blockIdx.x * 256 * E + threadIdx.x;
+  double2 wv[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const size_t e = base + (size_t)k * 256;
+    wv[k] = e < n ? ldc(w, e) : czero();
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = 0; i < nv; ++i) {
+    const cplx_t<S>* Vi = V + (size_t)(i0 + i) * ldv;
+    double2 acc = czero();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const size_t e = base + (size_t)k * 256;
+      if (e < n) acc = cadd(acc, cconjmul(ldc(Vi, e), wv[k]));
+    }
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (lane == 0) {
+      sh[wave][2 * i] = acc.x;
+      sh[wave][2 * i + 1] = acc.y;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * nv; t += blockDim.x)
+    part[(size_t)blockIdx.x * stride + 2 * i0 + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+}
+
+template <typename S>
+void multidot_part(size_t n, const void* V, size_t ldv, int nv, const void* w, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  const int nb = multidot_nblocks(n);
+  const int E = md_elems(n);
+  kprof_begin(st);
+  for (int i0 = 0; i0 < nv; i0 += MD_CHUNK) {
+    const int c = nv - i0 < MD_CHUNK ? nv - i0 : MD_CHUNK;
+#define MD_L(EE)                                                                                              \
+  hipLaunchKernelGGL((k_multidot<S, EE>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, i0, c, 2 * nv,       \
+                     (const C*)w, part)
+    if (E == 1) MD_L(1);
+    else if (E == 2) MD_L(2);
+    else if (E == 4) MD_L(4);
+    else MD_L(8);
+#undef MD_L
+  }
+  kprof_end(KP_MULTIDOT, (double)n * 2 * sizeof(S) * (nv + 1), st);
+}
+
+// ---- multi-axpy -------------------------------------------------------------
+template <typename S, bool NORM>
+__global__ __launch_bounds__(256) void k_multi_axpy(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
+                                                    const double* __restrict__ coef, double sgn,
+                                                    const cplx_t<S>* base, cplx_t<S>* out,
+                                                    double* __restrict__ part) {
+  __shared__ double sh[16];
+  double nrm = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double2 acc = czero();
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+      const double2 v0 = ldc(V + (size_t)i * ldv, e), v1 = ldc(V + (size_t)(i + 1) * ldv, e);
+      const double2 v2 = ldc(V + (size_t)(i + 2) * ldv, e), v3 = ldc(V + (size_t)(i + 3) * ldv, e);
+      acc = cadd(acc, cmul(v0, make_double2(coef[2 * i], coef[2 * i + 1])));
+      acc = cadd(acc, cmul(v1, make_double2(coef[2 * i + 2], coef[2 * i + 3])));
+      acc = cadd(acc, cmul(v2, make_double2(coef[2 * i + 4], coef[2 * i + 5])));
+      acc = cadd(acc, cmul(v3, make_double2(coef[2 * i + 6], coef[2 * i + 7])));
+    }
+    for (; i < nv; ++i) acc = cadd(acc, cmul(ldc(V + (size_t)i * ldv, e), make_double2(coef[2 * i], coef[2 * i + 1])));
+    double2 r = base ? ldc(base, e) : czero();
+    r.x += sgn * acc.x;
+    r.y += sgn * acc.y;
+    stc(out, e, r);
+    if (NORM) nrm += r.x * r.x + r.y * r.y;
+  }
+  if (NORM) {
+    nrm = block_sum(nrm, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = nrm;
+  }
+}
+
+template <typename S>
+void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef, double sgn, const void* base,
+                void* out, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  const int nb = red_nblocks(n);
+  kprof_begin(st);
+  if (part)
+    hipLaunchKernelGGL((k_multi_axpy<S, true>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, coef, sgn,
+                       (const C*)base, (C*)out, part);
+  else
+    hipLaunchKernelGGL((k_multi_axpy<S, false>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, coef, sgn,
+                       (const C*)base, (C*)out, part);
+  kprof_end(KP_MULTIAXPY, (double)n * 2 * sizeof(S) * (nv + (base ? 1 : 0) + 1), st);
+}
+
+// ---- simple vector kernels ----------------------------------------------------
+#define GRID_STRIDE(e) \
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+
+static int ew_blocks(size_t n) {
+  size_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+template <typename S>
+__global__ void k_scale_dev(size_t n, const cplx_t<S>* x, const double* scal, cplx_t<S>* y) {
+  const double a = scal[0];
+  GRID_STRIDE(e) stc(y, e, cscale(ldc(x, e), a));
+}
+template <typename S>
+__global__ void k_scale_host(size_t n, const cplx_t<S>* x, double a, cplx_t<S>* y) {
+  GRID_STRIDE(e) stc(y, e, cscale(ldc(x, e), a));
+}
+template <typename S>
+__global__ void k_add_inplace(size_t n, const cplx_t<S>* __restrict__ x, cplx_t<S>* __restrict__ y) {
+  GRID_STRIDE(e) stc(y, e, cadd(ldc(y, e), ldc(x, e)));
+}
+template <typename S>
+__global__ void k_copy(size_t n, const cplx_t<S>* __restrict__ x, cplx_t<S>* __restrict__ y) {
+  GRID_STRIDE(e) y[e] = x[e];
+}
+template <typename S>
+__global__ void k_zero(size_t n, cplx_t<S>* __restrict__ x) {
+  GRID_STRIDE(e) stc(x, e, czero());
+}
+template <typename S>
+__global__ void k_axpy_dev(size_t n, const cplx_t<S>* __restrict__ x, cplx_t<S>* __restrict__ y,
+                           const double* __restrict__ a) {
+  const double2 av = make_double2(a[0], a[1]);
+  GRID_STRIDE(e) stc(y, e, cadd(ldc(y, e), cmul(av, ldc(x, e))));
+}
+
+template <typename S>
+void scale_dev(size_t n, const void* x, const double* scal, void* y, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_scale_dev<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (const C*)x, scal, (C*)y);
+}
+template <typename S>
+void scale_host(size_t n, const void* x, double a, void* y, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_scale_host<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (const C*)x, a, (C*)y);
+}
+template <typename S>
+void add_inplace(size_t n, const void* x, void* y, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_add_inplace<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (const C*)x, (C*)y);
+}
+template <typename S>
+void copy_vec(size_t n, const void* x, void* y, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_copy<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (const C*)x, (C*)y);
+}
+template <typename S>
+void zero_vec(size_t n, void* x, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_zero<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (C*)x);
+}
+template <typename S>
+void axpy_dev(size_t n, const void* x, void* y, const double* a, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_axpy_dev<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (const C*)x, (C*)y, a);
+}
+
+// ---- BiCGStab ------------------------------------------------------------------
+template <typename S>
+__global__ void k_bicg_p(size_t n, const cplx_t<S>* __restrict__ r, const cplx_t<S>* __restrict__ v,
+                         cplx_t<S>* __restrict__ p, const BiState* __restrict__ bs, int first) {
+  if (bs->flag) return;
+  const double2 beta = make_double2(bs->beta[0], bs->beta[1]);
+  const double2 om = make_double2(bs->omega[0], bs->omega[1]);
+  GRID_STRIDE(e) {
+    const double2 re = ldc(r, e);
+    if (first) {
+      stc(p, e, re);
+    } else {
+      const double2 t = csub(ldc(p, e), cmul(om, ldc(v, e)));
+      stc(p, e, cadd(re, cmul(beta, t)));
+    }
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_bicg_s(size_t n, const cplx_t<S>* __restrict__ r,
+                                                const cplx_t<S>* __restrict__ v, cplx_t<S>* __restrict__ s,
+                                                const BiState* __restrict__ bs, double* __restrict__ part) {
+  __shared__ double sh[16];
+  const double2 al = make_double2(bs->alpha[0], bs->alpha[1]);
+  double nrm = 0.0;
+  GRID_STRIDE(e) {
+    const double2 q = csub(ldc(r, e), cmul(al, ldc(v, e)));
+    stc(s, e, q);
+    nrm += q.x * q.x + q.y * q.y;
+  }
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = nrm;
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_two_dot(size_t n, const cplx_t<S>* __restrict__ t,
+                                                 const cplx_t<S>* __restrict__ s, double* __restrict__ part) {
+  __shared__ double sh[32];
+  double2 ts = czero();
+  double tt = 0.0;
+  GRID_STRIDE(e) {
+    const double2 te = ldc(t, e);
+    ts = cadd(ts, cconjmul(te, ldc(s, e)));
+    tt += te.x * te.x + te.y * te.y;
+  }
+  ts = block_sum2(ts, sh);
+  tt = block_sum(tt, sh);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = ts.x;
+    part[3 * blockIdx.x + 1] = ts.y;
+    part[3 * blockIdx.x + 2] = tt;
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_bicg_update(size_t n, const cplx_t<S>* __restrict__ ph,
+                                                     const cplx_t<S>* __restrict__ shat,
+                                                     const cplx_t<S>* __restrict__ s, const cplx_t<S>* __restrict__ t,
+                                                     const cplx_t<S>* __restrict__ rhat, cplx_t<S>* __restrict__ u,
+                                                     cplx_t<S>* __restrict__ r, const BiState* __restrict__ bs,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[32];
+  if (bs->flag) return;  // breakdown flagged on the device: leave u and r as they are
+  const double2 al = make_double2(bs->alpha[0], bs->alpha[1]);
+  const double2 om = make_double2(bs->omega[0], bs->omega[1]);
+  double rr = 0.0;
+  double2 rho = czero();
+  GRID_STRIDE(e) {
+    const double2 ue = cadd(ldc(u, e), cadd(cmul(al, ldc(ph, e)), cmul(om, ldc(shat, e))));
+    stc(u, e, ue);
+    const double2 re = csub(ldc(s, e), cmul(om, ldc(t, e)));
+    stc(r, e, re);
+    rr += re.x * re.x + re.y * re.y;
+    rho = cadd(rho, cconjmul(ldc(rhat, e), re));
+  }
+  rr = block_sum(rr, sh);
+  rho = block_sum2(rho, sh);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = rr;
+    part[3 * blockIdx.x + 1] = rho.x;
+    part[3 * blockIdx.x + 2] = rho.y;
+  }
+}
+
+template <typename S>
+void bicg_p(size_t n, const void* r, const void* v, void* p, const BiState* bs, int first, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_bicg_p<S>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (const C*)r, (const C*)v, (C*)p, bs,
+                     first);
+}
+template <typename S>
+void bicg_s(size_t n, const void* r, const void* v, void* s, const BiState* bs, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_bicg_s<S>), dim3(red_nblocks(n)), dim3(256), 0, st, n, (const C*)r, (const C*)v, (C*)s, bs,
+                     part);
+}
+template <typename S>
+void two_dot_part(size_t n, const void* t, const void* s, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_two_dot<S>), dim3(red_nblocks(n)), dim3(256), 0, st, n, (const C*)t, (const C*)s, part);
+}
+template <typename S>
+void bicg_update(size_t n, const void* ph, const void* sh, const void* s, const void* t, const void* rhat, void* u,
+                 void* r, const BiState* bs, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  hipLaunchKernelGGL((k_bicg_update<S>), dim3(red_nblocks(n)), dim3(256), 0, st, n, (const C*)ph, (const C*)sh,
+                     (const C*)s, (const C*)t, (const C*)rhat, (C*)u, (C*)r, bs, part);
+}
+
+__device__ static bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+__global__ void k_bicg_scalar(int step, BiState* bs, const double* red) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (step == BI_RHO) {
+    const double2 rho = make_double2(red[0], red[1]);
+    if (!finite2(rho)) {
+      bs->flag = -5;
+      return;
+    }
+    if (rho.x == 0.0 && rho.y == 0.0) {
+      bs->flag = -4;
+      return;
+    }
+    const double2 rho0 = make_double2(bs->rho0[0], bs->rho0[1]);
+    const double2 al = make_double2(bs->alpha[0], bs->alpha[1]);
+    const double2 om = make_double2(bs->omega[0], bs->omega[1]);
+    const double2 beta = cmul(cdiv(rho, rho0), cdiv(al, om));
+    bs->beta[0] = beta.x;
+    bs->beta[1] = beta.y;
+    bs->rho[0] = rho.x;
+    bs->rho[1] = rho.y;
+  } else if (step == BI_ALPHA) {
+    const double2 den = make_double2(red[0], red[1]);
+    if (!finite2(den)) {
+      bs->flag = -5;
+      return;
+    }
+    if (den.x == 0.0 && den.y == 0.0) {
+      bs->flag = -4;
+      return;
+    }
+    const double2 al = cdiv(make_double2(bs->rho[0], bs->rho[1]), den);
+    bs->alpha[0] = al.x;
+    bs->alpha[1] = al.y;
+  } else if (step == BI_SS) {
+    bs->ss = sqrt(red[0]);
+  } else if (step == BI_OMEGA) {
+    const double2 ts = make_double2(red[0], red[1]);
+    const double tt = red[2];
+    double2 om = czero();
+    if (tt != 0.0) om = make_double2(ts.x / tt, ts.y / tt);
+    if (!finite2(om)) {
+      bs->flag = -5;
+      return;
+    }
+    if (om.x == 0.0 && om.y == 0.0) {
+      bs->flag = -4;
+      return;
+    }
+    bs->omega[0] = om.x;
+    bs->omega[1] = om.y;
+  } else if (step == BI_RR) {
+    bs->rr = sqrt(red[0]);
+    bs->rho0[0] = bs->rho[0];
+    bs->rho0[1] = bs->rho[1];
+  }
+}
+
+void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st) {
+  hipLaunchKernelGGL(k_bicg_scalar, dim3(1), dim3(64), 0, st, step, bs, red);
+}
+
+#define HELM_INST(S)                                                                                           \
+  template void dot_part<S>(size_t, const void*, const void*, double*, hipStream_t);                           \
+  template void nrm2_part<S>(size_t, const void*, double*, hipStream_t);                                       \
+  template void multidot_part<S>(size_t, const void*, size_t, int, const void*, double*, hipStream_t);         \
+  template void multi_axpy<S>(size_t, const void*, size_t, int, const double*, double, const void*, void*,     \
+                              double*, hipStream_t);                                                           \
+  template void scale_dev<S>(size_t, const void*, const double*, void*, hipStream_t);                          \
+  template void scale_host<S>(size_t, const void*, double, void*, hipStream_t);                                \
+  template void add_inplace<S>(size_t, const void*, void*, hipStream_t);                                       \
+  template void copy_vec<S>(size_t, const void*, void*, hipStream_t);                                          \
+  template void zero_vec<S>(size_t, void*, hipStream_t);                                                       \
+  template void axpy_dev<S>(size_t, const void*, void*, const double*, hipStream_t);                           \
+  template void bicg_p<S>(size_t, const void*, const void*, void*, const BiState*, int, hipStream_t);          \
+  template void bicg_s<S>(size_t, const void*, const void*, void*, const BiState*, double*, hipStream_t);      \
+  template void two_dot_part<S>(size_t, const void*, const void*, double*, hipStream_t);                       \
+  template void bicg_update<S>(size_t, const void*, const void*, const void*, const void*, const void*, void*, \
+                               void*, const BiState*, double*, hipStream_t);
+HELM_INST(double)
+HELM_INST(float)
+#undef HELM_INST
+
+}  // namespace helm

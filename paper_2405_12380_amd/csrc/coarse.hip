@@ -1,0 +1,427 @@
+// Trunk-basis coarse space of App. C and its per-application correction.
+//
+// Setup (once per network, p_used and k^2): P = first p_used trunk columns with
+// scatterer rows zeroed; CholeskyQR2 with column dropping, Q = P S1 S2 with
+// Q^T Q = I and positive diag(R); B = (L - diag(Re s)) Q by a batched real
+// stencil; A_c = Q^T B - i Q^T diag(Im s) Q (= Q^T A Q); A_c^{-1} by
+// Gauss-Jordan with partial pivoting.
+//
+// Correction z += Q A_c^{-1} Q^T r1 (HBM-bound skinny products):
+//   k_qt_part   per-block partials of Q^T r1: lanes own columns {l, l+64},
+//               wavefronts stride over rows, one coalesced 2 x 512 B row read
+//               per wavefront step;
+//   k_ainv      c = A_c^{-1} y, one workgroup per row of A_c^{-1};
+//   k_skinny    y_i = sum_j Q_ij c_j: lanes own columns, four rows per step,
+//               reduced with an 11-shuffle butterfly that leaves row rho's
+//               (re, im) in lane 16 rho.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "dense.h"
+#include "internal.h"
+#include "lib.h"
+#include "prof.h"
+
+namespace helm {
+
+static constexpr int QT_MAXB = 512;
+
+int qt_nblocks(size_t n) {
+  size_t nb = (n + 511) / 512;
+  if (nb > QT_MAXB) nb = QT_MAXB;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+template <typename T> __device__ __forceinline__ double ldq(const T* q, size_t i) { return (double)q[i]; }
+
+// part[b][2j + {0,1}] = sum_{i in block b} Q_ij x_i  (complex x, real Q, j < r <= 128)
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_qt_part(size_t n, int r, const T* __restrict__ Q,
+                                                 const cplx_t<S>* __restrict__ x, size_t rows_per_block,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t i0 = (size_t)blockIdx.x * rows_per_block;
+  const size_t i1 = min(n, i0 + rows_per_block);
+  const int c0 = lane, c1 = lane + 64;
+  const bool u0 = c0 < r, u1 = c1 < r;
+  double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+  size_t i = i0 + wave;
+  for (; i + 12 < i1; i += 16) {
+    double q0[4], q1[4];
+    double2 xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t ii = i + 4 * u;
+      xv[u] = ldc(x, ii);
+      q0[u] = u0 ? ldq(Q, ii * r + c0) : 0.0;
+      q1[u] = u1 ? ldq(Q, ii * r + c1) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0r += q0[u] * xv[u].x;
+      a0i += q0[u] * xv[u].y;
+      a1r += q1[u] * xv[u].x;
+      a1i += q1[u] * xv[u].y;
+    }
+  }
+  for (; i < i1; i += 4) {
+    const double2 xv = ldc(x, i);
+    const double q0 = u0 ? ldq(Q, i * r + c0) : 0.0;
+    const double q1 = u1 ? ldq(Q, i * r + c1) : 0.0;
+    a0r += q0 * xv.x;
+    a0i += q0 * xv.y;
+    a1r += q1 * xv.x;
+    a1i += q1 * xv.y;
+  }
+  sh[wave][2 * c0] = a0r;
+  sh[wave][2 * c0 + 1] = a0i;
+  sh[wave][2 * c1] = a1r;
+  sh[wave][2 * c1 + 1] = a1i;
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * r; e += blockDim.x)
+    part[(size_t)blockIdx.x * 2 * r + e] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
+}
+
+// c = Ainv y: block j computes row j (r x r complex, row-major)
+__global__ __launch_bounds__(64) void k_ainv(int r, const double* __restrict__ Ainv, const double* __restrict__ y,
+                                             double* __restrict__ c) {
+  const int j = blockIdx.x, l = threadIdx.x;
+  double2 acc = czero();
+  for (int k = l; k < r; k += 64) {
+    const size_t o = 2 * ((size_t)j * r + k);
+    acc = cadd(acc, cmul(make_double2(Ainv[o], Ainv[o + 1]), make_double2(y[2 * k], y[2 * k + 1])));
+  }
+  acc.x = wave_sum(acc.x);
+  acc.y = wave_sum(acc.y);
+  if (l == 0) {
+    c[2 * j] = acc.x;
+    c[2 * j + 1] = acc.y;
+  }
+}
+
+enum { SK_ADD = 0, SK_SYNTH = 1 };
+
+// y_i = sum_j Q_ij c_j (complex c).  SK_ADD: z_i += y_i.  SK_SYNTH: z_i = scal[0] *
+// y_i, or 0 on masked nodes (scal = s of the DeepONet scaling).
+template <typename T, typename S, int MODE>
+__global__ __launch_bounds__(256) void k_skinny(size_t n, int r, const T* __restrict__ Q, const double* __restrict__ c,
+                                                cplx_t<S>* __restrict__ z, const uint8_t* __restrict__ mask,
+                                                const double* __restrict__ scal) {
+  const int lane = threadIdx.x & 63;
+  const size_t wave_g = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6;
+  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  const int c0 = lane, c1 = lane + 64;
+  const double2 cc0 = c0 < r ? make_double2(c[2 * c0], c[2 * c0 + 1]) : czero();
+  const double2 cc1 = c1 < r ? make_double2(c[2 * c1], c[2 * c1 + 1]) : czero();
+  double sc = 1.0;
+  if (MODE == SK_SYNTH) sc = scal[0];
+  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+  for (size_t i = wave_g * 4; i < n; i += nwaves * 4) {
+    double v[8];
+#pragma unroll
+    for (int rho = 0; rho < 4; ++rho) {
+      const size_t ii = i + rho;
+      double q0 = 0.0, q1 = 0.0;
+      if (ii < n) {
+        if (c0 < r) q0 = ldq(Q, ii * r + c0);
+        if (c1 < r) q1 = ldq(Q, ii * r + c1);
+      }
+      v[2 * rho] = q0 * cc0.x + q1 * cc1.x;
+      v[2 * rho + 1] = q0 * cc0.y + q1 * cc1.y;
+    }
+    // butterfly: after step k each lane keeps half of its remaining values
+    double w4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double send = v[4 * (1 - b5) + q];
+      w4[q] = v[4 * b5 + q] + __shfl_xor(send, 32, 64);
+    }
+    double w2[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double send = w4[2 * (1 - b4) + q];
+      w2[q] = w4[2 * b4 + q] + __shfl_xor(send, 16, 64);
+    }
+    double w1;
+    {
+      const double send = w2[1 - b3];
+      w1 = w2[b3] + __shfl_xor(send, 8, 64);
+    }
+    w1 += __shfl_xor(w1, 4, 64);
+    w1 += __shfl_xor(w1, 2, 64);
+    w1 += __shfl_xor(w1, 1, 64);
+    // lane holds value index 4 b5 + 2 b4 + b3 = 2 rho + comp
+    const double other = __shfl_xor(w1, 8, 64);
+    if ((lane & 15) == 0) {
+      const size_t ii = i + 2 * b5 + b4;
+      if (ii < n) {
+        const double2 y = make_double2(w1, other);  // b3 == 0: w1 = re, other = im
+        if (MODE == SK_ADD) {
+          stc(z, ii, cadd(ldc(z, ii), y));
+        } else {
+          stc(z, ii, mask[ii] ? czero() : cscale(y, sc));
+        }
+      }
+    }
+  }
+}
+
+// B = (L - diag(Re s)) Q on real columns (n x r, row-major); masked rows -> 0.
+template <typename S>
+__global__ __launch_bounds__(256) void k_batched_lap(StencilGeom g, int r, const double* __restrict__ Q,
+                                                     const cplx_t<S>* __restrict__ sc, const uint8_t* __restrict__ mask,
+                                                     double* __restrict__ B) {
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const size_t total = n * r;
+  const size_t plane = (size_t)g.nx * g.ny;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = e / r;
+    const int j = (int)(e % r);
+    if (mask[p]) {
+      B[e] = 0.0;
+      continue;
+    }
+    const int i = (int)(p % g.nx), jj = (int)((p / g.nx) % g.ny), l = (int)(p / plane);
+    const double c = Q[e];
+    const double xm = (i > 0 && !mask[p - 1]) ? Q[e - r] : 0.0;
+    const double xp = (i + 1 < g.nx && !mask[p + 1]) ? Q[e + r] : 0.0;
+    const double ym = (jj > 0 && !mask[p - g.nx]) ? Q[e - (size_t)g.nx * r] : 0.0;
+    const double yp = (jj + 1 < g.ny && !mask[p + g.nx]) ? Q[e + (size_t)g.nx * r] : 0.0;
+    double acc = ((c - xm) + (c - xp)) * g.ih2[0];
+    acc = acc + ((c - ym) + (c - yp)) * g.ih2[1];
+    if (g.dim == 3) {
+      const double zm = (l > 0 && !mask[p - plane]) ? Q[e - plane * r] : 0.0;
+      const double zp = (l + 1 < g.nz && !mask[p + plane]) ? Q[e + plane * r] : 0.0;
+      acc = acc + ((c - zm) + (c - zp)) * g.ih2[2];
+    }
+    B[e] = acc - ldc(sc, p).x * c;
+  }
+}
+
+template <typename S>
+__global__ void k_im_s(size_t n, const cplx_t<S>* __restrict__ sc, double* __restrict__ w) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x)
+    w[p] = ldc(sc, p).y;
+}
+
+// P = T[:, :pu] (T: n x p, dtype precision) in fp64 with masked rows zeroed
+template <typename T>
+__global__ void k_mask_cols(size_t n, int p, int pu, const T* __restrict__ Tm, const uint8_t* __restrict__ mask,
+                            double* __restrict__ P) {
+  const size_t total = n * pu;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / pu;
+    const int j = (int)(e % pu);
+    P[e] = mask[i] ? 0.0 : (double)Tm[i * p + j];
+  }
+}
+
+// Qs = (T) Q and Q <- (double) Qs, so the coarse matrix is built from the basis
+// actually stored.
+template <typename T>
+__global__ void k_round_q(size_t total, double* __restrict__ Q, T* __restrict__ Qs) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const T v = (T)Q[e];
+    Qs[e] = v;
+    Q[e] = (double)v;
+  }
+}
+
+__global__ void k_combine_ac(int r2, const double* __restrict__ re, const double* __restrict__ im,
+                             double* __restrict__ Ac) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < r2) {
+    Ac[2 * e] = re[e];
+    Ac[2 * e + 1] = -im[e];
+  }
+}
+
+static unsigned ew_grid(size_t total) {
+  size_t nb = (total + 255) / 256;
+  if (nb > 16384) nb = 16384;
+  if (nb < 1) nb = 1;
+  return (unsigned)nb;
+}
+
+// ---- launchers used by other units ------------------------------------------------
+template <typename T, typename S>
+void qt_partials(size_t n, int r, const T* Q, const void* x, double* part, hipStream_t st) {
+  const int nb = qt_nblocks(n);
+  const size_t rpb = (n + nb - 1) / nb;
+  kprof_begin(st);
+  hipLaunchKernelGGL((k_qt_part<T, S>), dim3(nb), dim3(256), 0, st, n, r, Q, (const cplx_t<S>*)x, rpb, part);
+  kprof_end(KP_QT, (double)n * (sizeof(T) * r + 2 * sizeof(S)), st);
+}
+
+template <typename T, typename S>
+void skinny_apply(size_t n, int r, const T* Q, const double* c, void* z, const uint8_t* mask, const double* scal,
+                  int synth, hipStream_t st) {
+  size_t waves = (n + 3) / 4;
+  size_t nb = (waves + 3) / 4;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  kprof_begin(st);
+  if (synth)
+    hipLaunchKernelGGL((k_skinny<T, S, SK_SYNTH>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Q, c, (cplx_t<S>*)z,
+                       mask, scal);
+  else
+    hipLaunchKernelGGL((k_skinny<T, S, SK_ADD>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Q, c, (cplx_t<S>*)z, mask,
+                       scal);
+  // Q once; z read and written (ADD) or du written and the mask read (SYNTH)
+  kprof_end(KP_SKINNY, (double)n * (sizeof(T) * r + (synth ? 2 * sizeof(S) + 1 : 4 * sizeof(S))), st);
+}
+template void skinny_apply<double, double>(size_t, int, const double*, const double*, void*, const uint8_t*,
+                                           const double*, int, hipStream_t);
+template void skinny_apply<float, float>(size_t, int, const float*, const double*, void*, const uint8_t*,
+                                         const double*, int, hipStream_t);
+
+// ---- setup -----------------------------------------------------------------------
+void coarse_release(helm_op_s* op) {
+  Coarse& c = op->coarse;
+  c.Q.release();
+  c.Ainv.release();
+  c.Ac.release();
+  c.T.release();
+  c.W1.release();
+  c.W2.release();
+  c.small.release();
+  c.qpart.release();
+  c.valid = false;
+  c.T_serial = -1;
+}
+
+template <typename TT, typename S>
+static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, hipStream_t st) {
+  Coarse& c = op->coarse;
+  const size_t n = op->nn;
+  helm_status s;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipEventRecord(e0, st);
+  // trunk matrix at the op's nodes (cached per network)
+  const int p = don_p(net);
+  if (c.T_serial != don_serial(net)) {
+    if ((s = c.T.ensure(n * (size_t)p * sizeof(TT)))) return s;
+    if ((s = don_trunk(net, op, c.T.ptr, st))) return s;
+    c.T_serial = don_serial(net);
+  }
+  const int pu = p_used;
+  if ((s = c.W1.ensure(n * (size_t)pu * sizeof(double)))) return s;
+  if ((s = c.W2.ensure(n * (size_t)pu * sizeof(double)))) return s;
+  const size_t small_doubles = (size_t)gram_nblocks(n) * pu * pu + 10 * (size_t)pu * pu + 4096;
+  if ((s = c.small.ensure(small_doubles * sizeof(double)))) return s;
+  double* part = (double*)c.small.ptr;
+  double* G = part + (size_t)gram_nblocks(n) * pu * pu;
+  double* X = G + (size_t)pu * pu;
+  double* S1 = X + (size_t)pu * pu;
+  double* G2 = S1 + (size_t)pu * pu;
+  double* are = G2 + (size_t)pu * pu;
+  double* aim = are + (size_t)pu * pu;
+  double* gjw = aim + (size_t)pu * pu;  // 4 pu^2
+  int* info = (int*)(gjw + 4 * (size_t)pu * pu);
+  double* cond = (double*)(info + 8);
+  double* P = (double*)c.W1.ptr;
+  double* Q1 = (double*)c.W2.ptr;
+  // P = masked first columns
+  hipLaunchKernelGGL((k_mask_cols<TT>), dim3(ew_grid(n * pu)), dim3(256), 0, st, n, p, pu, (const TT*)c.T.ptr,
+                     op->mask, P);
+  // pass 1: G = P^T P, Cholesky with dropping -> S1 (pu x r)
+  gram(n, pu, P, pu, P, pu, nullptr, part, G, st);
+  const double tau = op->dt == HELM_C128 ? 1e-7 : 1e-5;
+  chol_drop(pu, G, tau * tau, 1, X, S1, info, st);
+  hipError_t e = hipMemcpyAsync(op->host, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "coarse: rank readback");
+  if ((s = sync_stream(st, "coarse: pass 1"))) return s;
+  const int r = ((int*)op->host)[0];
+  c.rank = r;
+  c.p_used = pu;
+  if (r == 0) {
+    c.valid = true;
+    c.cond_est = 0.0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return HELM_OK;
+  }
+  // Q1 = P S1 (n x r)
+  gemm<double>((int)n, r, pu, P, pu, S1, r, nullptr, ACT_NONE, Q1, r, st);
+  // pass 2: G2 = Q1^T Q1, Cholesky without dropping -> S2 (r x r); Q = Q1 S2 into W1
+  gram(n, r, Q1, r, Q1, r, nullptr, part, G2, st);
+  chol_drop(r, G2, 0.0, 0, X, S1, info, st);
+  double* Q = P;  // reuse W1
+  gemm<double>((int)n, r, r, Q1, r, S1, r, nullptr, ACT_NONE, Q, r, st);
+  e = hipMemcpyAsync(op->host, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "coarse: pass 2 readback");
+  if ((s = sync_stream(st, "coarse: pass 2"))) return s;
+  if (((int*)op->host)[1] != 0 || ((int*)op->host)[0] != r)
+    return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", ((int*)op->host)[0], r);
+  // stored basis (dtype precision); Q <- stored values
+  if ((s = c.Q.ensure(n * (size_t)r * sizeof(TT)))) return s;
+  hipLaunchKernelGGL((k_round_q<TT>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (TT*)c.Q.ptr);
+  // B = (L - diag(Re s)) Q into W2; A_c = Q^T B - i Q^T diag(Im s) Q
+  double* Bm = Q1;
+  hipLaunchKernelGGL((k_batched_lap<S>), dim3(ew_grid(n * r)), dim3(256), 0, st, op->geom, r, Q,
+                     (const cplx_t<S>*)op->sc, op->mask, Bm);
+  gram(n, r, Q, r, Bm, r, nullptr, part, are, st);
+  double* wim = Bm;  // B no longer needed: reuse for Im s
+  hipLaunchKernelGGL((k_im_s<S>), dim3(ew_grid(n)), dim3(256), 0, st, n, (const cplx_t<S>*)op->sc, wim);
+  gram(n, r, Q, r, Q, r, wim, part, aim, st);
+  if ((s = c.Ac.ensure(2 * sizeof(double) * r * r)) || (s = c.Ainv.ensure(2 * sizeof(double) * r * r)) ||
+      (s = c.qpart.ensure(sizeof(double) * 2 * (size_t)r * qt_nblocks(n))))
+    return s;
+  hipLaunchKernelGGL(k_combine_ac, dim3((r * r + 255) / 256), dim3(256), 0, st, r * r, are, aim, (double*)c.Ac.ptr);
+  gj_inverse(r, (const double*)c.Ac.ptr, gjw, (double*)c.Ainv.ptr, info, cond, st);
+  e = hipMemcpyAsync(op->host, info, sizeof(int) * 8 + sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "coarse: inverse readback");
+  (void)hipEventRecord(e1, st);
+  if ((s = sync_stream(st, "coarse: inverse"))) return s;
+  if (((int*)op->host)[0] != 0) return fail(HELM_E_SINGULAR, "coarse: A_c is singular (zero pivot)");
+  c.cond_est = *(double*)((int*)op->host + 8);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  c.setup_ms = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.valid = true;
+  return launch_check("coarse setup");
+}
+
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, hipStream_t st) {
+  Coarse& c = op->coarse;
+  if (c.valid && c.net_serial == don_serial(net) && c.p_used == p_used && c.ksq_version == op->ksq_version)
+    return HELM_OK;
+  c.valid = false;
+  helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, st)
+                                      : coarse_build<float, float>(op, net, p_used, st);
+  if (s) return s;
+  c.net_serial = don_serial(net);
+  c.ksq_version = op->ksq_version;
+  return HELM_OK;
+}
+
+template <typename S>
+helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st) {
+  Coarse& c = op->coarse;
+  const int r = c.rank;
+  if (r == 0) return HELM_OK;
+  const size_t n = op->nn;
+  const int nb = qt_nblocks(n);
+  double* part = (double*)c.qpart.ptr;
+  double* y = op->red + 1024;
+  double* cc = op->red + 2048;
+  qt_partials<S, S>(n, r, (const S*)c.Q.ptr, r1, part, st);
+  reduce_rows(part, nb, 2 * (size_t)r, y, 1.0, st);
+  hipLaunchKernelGGL(k_ainv, dim3(r), dim3(64), 0, st, r, (const double*)c.Ainv.ptr, y, cc);
+  skinny_apply<S, S>(n, r, (const S*)c.Q.ptr, cc, z, op->mask, nullptr, 0, st);
+  return launch_check("coarse correction");
+}
+
+template helm_status coarse_correct<double>(helm_op_s*, const void*, void*, hipStream_t);
+template helm_status coarse_correct<float>(helm_op_s*, const void*, void*, hipStream_t);
+
+}  // namespace helm

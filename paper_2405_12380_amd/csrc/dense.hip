@@ -1,0 +1,518 @@
+// Dense kernels: the DeepONet layers (MFMA GEMM with fused bias + activation,
+// split-K GEMV for small batches, the coordinate input layer of the trunk),
+// the tall-skinny Gram products of the trunk-basis setup (MFMA), and
+// one-workgroup factorizations of small matrices (Cholesky with column
+// dropping, triangular inverse, Gauss-Jordan inverse of the complex coarse
+// matrix).
+//
+// MFMA: v_mfma_f64_16x16x4f64 (fp64 path) and v_mfma_f32_16x16x4f32 (fp32
+// path).  For both, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of
+// a 16x4 by 4x16 product.  The accumulator layouts differ: the f32 form holds
+// rows 4 (l / 16) + i in its four registers, the f64 form rows (l / 16) + 4 i;
+// both hold column l % 16.
+#include "common.h"
+#include "dense.h"
+
+namespace helm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { using type = d4; };
+template <> struct Acc<float> { using type = f4; };
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int i);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int i) { return (lane >> 4) + 4 * i; }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int i) { return 4 * (lane >> 4) + i; }
+
+template <typename T>
+__device__ __forceinline__ T activate(T x, int act) {
+  if (act == ACT_TANH) return tanh(x);
+  if (act == ACT_RELU) return x > T(0) ? x : T(0);
+  if (act == ACT_LEAKY) return x > T(0) ? x : T(0.01) * x;
+  return x;
+}
+
+// ---- trunk input layer: h = act(x W + b) at grid-node coordinates --------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_coord_layer(int dim, int nx, int ny, int nz, size_t row0, size_t nrows,
+                                                     const T* __restrict__ W, const T* __restrict__ b, int N,
+                                                     int act, T* __restrict__ out) {
+  const size_t total = nrows * (size_t)N;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / N;
+    const int c = (int)(e % N);
+    const size_t p = row0 + r;
+    const int ix = (int)(p % nx);
+    const int iy = (int)((p / nx) % ny);
+    const int iz = (int)(p / ((size_t)nx * ny));
+    const T xc[3] = {T(ix + 1) / T(nx + 1), T(iy + 1) / T(ny + 1), T(iz + 1) / T(nz + 1)};
+    T acc = xc[0] * W[c];
+    for (int d = 1; d < dim; ++d) acc += xc[d] * W[(size_t)d * N + c];
+    out[e] = activate<T>(acc + b[c], act);
+  }
+}
+
+// ---- MFMA GEMM: C = act(A W + b) ---------------------------------------------
+// A: M x K (lda), W: K x N (ldw), C: M x N (ldc), all row-major.  64x64 tile
+// per workgroup of four wavefronts (32x32 each, 2x2 MFMA tiles), K staged in
+// chunks of 16 through LDS (A stored k-major so MFMA operand reads are
+// conflict-free).
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T* __restrict__ A, size_t lda,
+                                              const T* __restrict__ W, size_t ldw, const T* __restrict__ bias,
+                                              int act, T* __restrict__ C, size_t ldc) {
+  using AccT = typename Acc<T>::type;
+  __shared__ T As[GB_K][GB_M + 1];
+  __shared__ T Ws[GB_K][GB_N + 1];
+  const int nbn = (N + GB_N - 1) / GB_N;
+  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int bm = (int)(lb / nbn) * GB_M, bn = (int)(lb % nbn) * GB_N;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  AccT acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
+    // A tile: 64 rows x 16 k, 4 elements per thread
+    {
+      const int r = t >> 2, kq = (t & 3) * 4;
+      const int gr = bm + r;
+      for (int q = 0; q < 4; ++q) {
+        const int gk = k0 + kq + q;
+        As[kq + q][r] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : T(0);
+      }
+    }
+    // W tile: 16 k x 64 n
+    {
+      const int kk = t >> 4, nq = (t & 15) * 4;
+      const int gk = k0 + kk;
+      for (int q = 0; q < 4; ++q) {
+        const int gn = bn + nq + q;
+        Ws[kk][nq + q] = (gk < K && gn < N) ? W[(size_t)gk * ldw + gn] : T(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GB_K; kk += 4) {
+      T av[2], bv[2];
+      for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wm + a * 16 + (lane & 15)];
+      for (int b = 0; b < 2; ++b) bv[b] = Ws[kk + (lane >> 4)][wn + b * 16 + (lane & 15)];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int i = 0; i < 4; ++i) {
+        const int gr = bm + wm + a * 16 + acc_row<T>(lane, i);
+        const int gc = bn + wn + b * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          T v = acc[a][b][i];
+          if (bias) v += bias[gc];
+          C[(size_t)gr * ldc + gc] = activate<T>(v, act);
+        }
+      }
+}
+
+// ---- small-batch dense layer (GEMV class), split over K ------------------------
+// part[ks][b][n] = sum_{k in split ks} x[b][k] W[k][n]; then finalize adds the
+// splits in order, the bias and the activation.
+constexpr int SK_COLS = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void k_small_part(int B, int N, int K, int ksplit, const T* __restrict__ x,
+                                                    const T* __restrict__ W, double* __restrict__ part) {
+  __shared__ double sh[4][4][SK_COLS];
+  const int ncb = (N + SK_COLS - 1) / SK_COLS;
+  const int cb = blockIdx.x % ncb, ks = blockIdx.x / ncb;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int col = cb * SK_COLS + lane;
+  const int kchunk = (K + ksplit - 1) / ksplit;
+  const int kb = ks * kchunk, ke = min(K, kb + kchunk);
+  double acc[4] = {0, 0, 0, 0};
+  if (col < N)
+    for (int k = kb + grp; k < ke; k += 4) {
+      const double w = (double)W[(size_t)k * N + col];
+      for (int b = 0; b < B; ++b) acc[b] += (double)x[(size_t)b * K + k] * w;
+    }
+  for (int b = 0; b < 4; ++b) sh[grp][b][lane] = acc[b];
+  __syncthreads();
+  if (grp == 0 && col < N)
+    for (int b = 0; b < B; ++b)
+      part[((size_t)ks * B + b) * N + col] = (sh[0][b][lane] + sh[1][b][lane]) + (sh[2][b][lane] + sh[3][b][lane]);
+}
+
+template <typename T>
+__global__ void k_small_final(int B, int N, int ksplit, const double* __restrict__ part, const T* __restrict__ bias,
+                              int act, T* __restrict__ y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * N) return;
+  const int b = e / N, n = e % N;
+  double acc = 0.0;
+  for (int ks = 0; ks < ksplit; ++ks) acc += part[((size_t)ks * B + b) * N + n];
+  T v = (T)acc;
+  if (bias) v += bias[n];
+  y[e] = activate<T>(v, act);
+}
+
+// ---- tall-skinny weighted Gram: C = X^T diag(w) Y (X, Y: n x r, r <= 128) -------
+// Each workgroup reduces a contiguous range of rows into a full 128 x 128 tile
+// (four wavefronts of 64 x 64, 4 x 4 MFMA tiles each); rows are staged 16 at a
+// time through LDS.  part[b] receives the block's r x r partial.
+constexpr int GR_ROWS = 16;
+__global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __restrict__ X, size_t ldx,
+                                              const double* __restrict__ Y, size_t ldy,
+                                              const double* __restrict__ w, size_t rows_per_block,
+                                              double* __restrict__ part) {
+  __shared__ double Xs[GR_ROWS][128 + 1];
+  __shared__ double Ys[GR_ROWS][128 + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wa = (wave >> 1) * 64, wb = (wave & 1) * 64;
+  const size_t i0 = (size_t)blockIdx.x * rows_per_block;
+  const size_t i1 = min(n, i0 + rows_per_block);
+  d4 acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  for (size_t ib = i0; ib < i1; ib += GR_ROWS) {
+    for (int e = t; e < GR_ROWS * 128; e += 256) {
+      const int rr = e >> 7, cc = e & 127;
+      const size_t gi = ib + rr;
+      double xv = 0.0, yv = 0.0;
+      if (gi < i1 && cc < r) {
+        xv = X[gi * ldx + cc];
+        yv = Y[gi * ldy + cc];
+        if (w) yv *= w[gi];
+      }
+      Xs[rr][cc] = xv;
+      Ys[rr][cc] = yv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GR_ROWS; kk += 4) {
+      double av[4], bv[4];
+      for (int a = 0; a < 4; ++a) av[a] = Xs[kk + (lane >> 4)][wa + a * 16 + (lane & 15)];
+      for (int b = 0; b < 4; ++b) bv[b] = Ys[kk + (lane >> 4)][wb + b * 16 + (lane & 15)];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.x * r * r;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int i = 0; i < 4; ++i) {
+        const int ra = wa + a * 16 + acc_row<double>(lane, i);
+        const int cb = wb + b * 16 + (lane & 15);
+        if (ra < r && cb < r) out[(size_t)ra * r + cb] = acc[a][b][i];
+      }
+}
+
+// out[w] = sum_b part[b * width + w] in block order (one thread per w).
+__global__ void k_reduce_rows(const double* __restrict__ part, int nparts, size_t width, double* __restrict__ out,
+                              double scale) {
+  const size_t w = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (w >= width) return;
+  double acc = 0.0;
+  for (int b = 0; b < nparts; ++b) acc += part[(size_t)b * width + w];
+  out[w] = scale * acc;
+}
+
+// ---- one-workgroup Cholesky with column dropping -------------------------------
+// G: p x p (row-major, fp64, overwritten) = P^T P.  Right-looking Cholesky
+// G = R^T R on the upper triangle; a column whose Schur-complement diagonal is
+// <= tau2 * max_j G[j][j] is dropped (its remaining norm is at most tau times
+// the largest column norm), which matches
+// Householder QR that skips such columns.  Outputs: S (p x r row-major) with
+// S[kept[a]][:] = (R1^{-1})[a][:] and zero rows for dropped columns, so that
+// Q = P S has orthonormal columns in exact arithmetic; info[0] = r;
+// info[1] = 1 if a column had to be dropped while allow_drop = 0.
+// G and X (r x r, scratch) live in global memory (L2-resident at these sizes).
+__global__ __launch_bounds__(1024) void k_chol_drop(int p, double* __restrict__ G, double tau2, int allow_drop,
+                                                    double* __restrict__ X, double* __restrict__ S,
+                                                    int* __restrict__ info) {
+  __shared__ int kept[128];
+  __shared__ int s_nk, s_fail;
+  __shared__ double s_piv, s_thr2;
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (t == 0) {
+    s_nk = 0;
+    s_fail = 0;
+    double mx = 0.0;  // largest squared column norm of P
+    for (int j = 0; j < p; ++j) mx = fmax(mx, G[j * p + j]);
+    s_thr2 = tau2 * mx;
+  }
+  __syncthreads();
+  const double thr2 = s_thr2;
+  for (int j = 0; j < p; ++j) {
+    if (t == 0) {
+      const double d = G[j * p + j];
+      if (!(d > thr2)) {
+        s_piv = -1.0;
+        if (!allow_drop) s_fail = 1;
+      } else {
+        s_piv = sqrt(d);
+        kept[s_nk] = j;
+        s_nk = s_nk + 1;
+      }
+    }
+    __syncthreads();
+    const double piv = s_piv;
+    if (piv > 0.0) {
+      for (int c = j + t; c < p; c += nt) G[j * p + c] = (c == j) ? piv : G[j * p + c] / piv;
+      __syncthreads();
+      // trailing update of the upper triangle: G[a][c] -= R[j][a] R[j][c], j < a <= c
+      const int m = p - j - 1;
+      for (int e = t; e < m * m; e += nt) {
+        const int a = j + 1 + e / m, c = j + 1 + e % m;
+        if (c >= a) G[a * p + c] -= G[j * p + a] * G[j * p + c];
+      }
+    }
+    __syncthreads();
+  }
+  const int r = s_nk;
+  // X = R1^{-1} for R1[a][b] = G[kept[a]][kept[b]] (a <= b): back substitution,
+  // one thread per column b of X.
+  for (int e = t; e < r * r; e += nt) X[e] = 0.0;
+  __syncthreads();
+  for (int b = t; b < r; b += nt) {
+    for (int a = b; a >= 0; --a) {
+      double acc = (a == b) ? 1.0 : 0.0;
+      for (int c = a + 1; c <= b; ++c) acc -= G[kept[a] * p + kept[c]] * X[c * r + b];
+      X[a * r + b] = acc / G[kept[a] * p + kept[a]];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < p * r; e += nt) S[e] = 0.0;
+  __syncthreads();
+  for (int e = t; e < r * r; e += nt) {
+    const int a = e / r, b = e % r;
+    S[(size_t)kept[a] * r + b] = X[e];
+  }
+  if (t == 0) {
+    info[0] = r;
+    info[1] = s_fail;
+  }
+}
+
+// ---- Gauss-Jordan inverse of a complex r x r matrix, one workgroup -------------
+// Work array Wk: r x 2r complex (interleaved, row-major) = [A | I]; partial
+// pivoting by largest modulus (lowest index on ties).  Ainv receives the
+// inverse; info[0] = 1 if a pivot was exactly zero or non-finite.
+// cond[0] = ||A||_1 ||A^{-1}||_1.
+__global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __restrict__ A, double* __restrict__ Wk,
+                                                     double* __restrict__ Ainv, int* __restrict__ info,
+                                                     double* __restrict__ cond) {
+  __shared__ double smax[1024];
+  __shared__ int sidx[1024];
+  __shared__ int s_piv;
+  __shared__ double s_anorm;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int w2 = 2 * r;
+  for (int e = t; e < r * w2; e += nt) {
+    const int i = e / w2, c = e % w2;
+    double re, im;
+    if (c < r) {
+      re = A[2 * ((size_t)i * r + c)];
+      im = A[2 * ((size_t)i * r + c) + 1];
+    } else {
+      re = (c - r == i) ? 1.0 : 0.0;
+      im = 0.0;
+    }
+    Wk[2 * (size_t)e] = re;
+    Wk[2 * (size_t)e + 1] = im;
+  }
+  // ||A||_1 = max column sum
+  if (t == 0) s_anorm = 0.0;
+  __syncthreads();
+  for (int c = t; c < r; c += nt) {
+    double sm = 0.0;
+    for (int i = 0; i < r; ++i) sm += hypot(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]);
+    smax[t] = sm;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double mx = 0.0;
+    for (int c = 0; c < r && c < nt; ++c) mx = fmax(mx, smax[c]);
+    s_anorm = mx;
+    info[0] = 0;
+  }
+  __syncthreads();
+  for (int k = 0; k < r; ++k) {
+    // pivot search in column k, rows k..r-1
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + t; i < r; i += nt) {
+      const size_t o = 2 * ((size_t)i * w2 + k);
+      const double v = hypot(Wk[o], Wk[o + 1]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    smax[t] = best;
+    sidx[t] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (t < s) {
+        if (smax[t + s] > smax[t] || (smax[t + s] == smax[t] && sidx[t + s] < sidx[t])) {
+          smax[t] = smax[t + s];
+          sidx[t] = sidx[t + s];
+        }
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      s_piv = sidx[0];
+      if (!(smax[0] > 0.0) || !isfinite(smax[0])) info[0] = 1;
+    }
+    __syncthreads();
+    const int pr = s_piv;
+    if (pr != k)
+      for (int c = t; c < w2; c += nt) {
+        const size_t a = 2 * ((size_t)k * w2 + c), b = 2 * ((size_t)pr * w2 + c);
+        const double x0 = Wk[a], x1 = Wk[a + 1];
+        Wk[a] = Wk[b];
+        Wk[a + 1] = Wk[b + 1];
+        Wk[b] = x0;
+        Wk[b + 1] = x1;
+      }
+    __syncthreads();
+    // scale pivot row
+    const double2 pv = make_double2(Wk[2 * ((size_t)k * w2 + k)], Wk[2 * ((size_t)k * w2 + k) + 1]);
+    __syncthreads();
+    for (int c = t; c < w2; c += nt) {
+      const size_t a = 2 * ((size_t)k * w2 + c);
+      const double2 v = cdiv(make_double2(Wk[a], Wk[a + 1]), pv);
+      Wk[a] = v.x;
+      Wk[a + 1] = v.y;
+    }
+    __syncthreads();
+    // eliminate column k from every other row
+    for (int e = t; e < r * w2; e += nt) {
+      const int i = e / w2, c = e % w2;
+      if (i == k || c == k) continue;
+      const size_t fi = 2 * ((size_t)i * w2 + k);
+      const double2 fct = make_double2(Wk[fi], Wk[fi + 1]);
+      const size_t a = 2 * ((size_t)i * w2 + c), b = 2 * ((size_t)k * w2 + c);
+      const double2 v = csub(make_double2(Wk[a], Wk[a + 1]), cmul(fct, make_double2(Wk[b], Wk[b + 1])));
+      Wk[a] = v.x;
+      Wk[a + 1] = v.y;
+    }
+    __syncthreads();
+    for (int i = t; i < r; i += nt)
+      if (i != k) {
+        const size_t fi = 2 * ((size_t)i * w2 + k);
+        Wk[fi] = 0.0;
+        Wk[fi + 1] = 0.0;
+      }
+    __syncthreads();
+  }
+  for (int e = t; e < r * r; e += nt) {
+    const int i = e / r, c = e % r;
+    const size_t o = 2 * ((size_t)i * w2 + r + c);
+    Ainv[2 * (size_t)e] = Wk[o];
+    Ainv[2 * (size_t)e + 1] = Wk[o + 1];
+  }
+  __syncthreads();
+  for (int c = t; c < r; c += nt) {
+    double sm = 0.0;
+    for (int i = 0; i < r; ++i) sm += hypot(Ainv[2 * ((size_t)i * r + c)], Ainv[2 * ((size_t)i * r + c) + 1]);
+    smax[t] = sm;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double mx = 0.0;
+    for (int c = 0; c < r && c < nt; ++c) mx = fmax(mx, smax[c]);
+    cond[0] = s_anorm * mx;
+  }
+}
+
+// ---- launchers -------------------------------------------------------------------
+template <typename T>
+void coord_layer(int dim, const int n[3], size_t row0, size_t nrows, const T* W, const T* b, int N, int act, T* out,
+                 hipStream_t st) {
+  size_t total = nrows * (size_t)N;
+  size_t nb = (total + 255) / 256;
+  if (nb > 16384) nb = 16384;
+  hipLaunchKernelGGL((k_coord_layer<T>), dim3((unsigned)nb), dim3(256), 0, st, dim, n[0], n[1], n[2], row0, nrows, W, b,
+                     N, act, out);
+}
+
+template <typename T>
+void gemm(int M, int N, int K, const T* A, size_t lda, const T* W, size_t ldw, const T* bias, int act, T* C,
+          size_t ldc, hipStream_t st) {
+  const int nb = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
+  hipLaunchKernelGGL((k_gemm<T>), dim3(nb), dim3(256), 0, st, M, N, K, A, lda, W, ldw, bias, act, C, ldc);
+}
+
+int small_ksplit(int K) {
+  int ks = (K + 255) / 256;
+  if (ks > 64) ks = 64;
+  if (ks < 1) ks = 1;
+  return ks;
+}
+
+template <typename T>
+void dense_small(int B, int N, int K, const T* x, const T* W, const T* bias, int act, T* y, double* part,
+                 hipStream_t st) {
+  const int ks = small_ksplit(K);
+  const int ncb = (N + SK_COLS - 1) / SK_COLS;
+  hipLaunchKernelGGL((k_small_part<T>), dim3(ncb * ks), dim3(256), 0, st, B, N, K, ks, x, W, part);
+  hipLaunchKernelGGL((k_small_final<T>), dim3((B * N + 255) / 256), dim3(256), 0, st, B, N, ks, part, bias, act, y);
+}
+
+int gram_nblocks(size_t n) {
+  size_t nb = (n + 1023) / 1024;
+  if (nb > 256) nb = 256;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+void gram(size_t n, int r, const double* X, size_t ldx, const double* Y, size_t ldy, const double* w, double* part,
+          double* out, hipStream_t st) {
+  const int nb = gram_nblocks(n);
+  size_t rpb = (n + nb - 1) / nb;
+  rpb = (rpb + GR_ROWS - 1) / GR_ROWS * GR_ROWS;
+  hipLaunchKernelGGL(k_gram, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
+  const size_t width = (size_t)r * r;
+  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, part, nb, width, out,
+                     1.0);
+}
+
+void reduce_rows(const double* part, int nparts, size_t width, double* out, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, part, nparts, width, out,
+                     scale);
+}
+
+void chol_drop(int p, double* G, double tau2, int allow_drop, double* X, double* S, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(1024), 0, st, p, G, tau2, allow_drop, X, S, info);
+}
+
+void gj_inverse(int r, const double* A, double* work, double* Ainv, int* info, double* cond, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(1024), 0, st, r, A, work, Ainv, info, cond);
+}
+
+template void coord_layer<double>(int, const int*, size_t, size_t, const double*, const double*, int, int, double*,
+                                  hipStream_t);
+template void coord_layer<float>(int, const int*, size_t, size_t, const float*, const float*, int, int, float*,
+                                 hipStream_t);
+template void gemm<double>(int, int, int, const double*, size_t, const double*, size_t, const double*, int, double*,
+                           size_t, hipStream_t);
+template void gemm<float>(int, int, int, const float*, size_t, const float*, size_t, const float*, int, float*, size_t,
+                          hipStream_t);
+template void dense_small<double>(int, int, int, const double*, const double*, const double*, int, double*, double*,
+                                  hipStream_t);
+template void dense_small<float>(int, int, int, const float*, const float*, const float*, int, float*, double*,
+                                 hipStream_t);
+
+}  // namespace helm

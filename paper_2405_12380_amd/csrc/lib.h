@@ -1,0 +1,147 @@
+// Host-side internals of libhelm: handle layouts, device buffers, error
+// helpers, and the driver entry points shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "helm.h"
+#include "internal.h"
+
+namespace helm {
+
+helm_status fail(helm_status s, const char* fmt, ...);
+helm_status hip_fail(hipError_t e, const char* what);
+helm_status dalloc(void** p, size_t bytes);
+void dfree(void* p);
+helm_status launch_check(const char* what);
+helm_status sync_stream(hipStream_t st, const char* what);
+
+// A growable device allocation (contents are not preserved on growth).
+struct Buffer {
+  void* ptr = nullptr;
+  size_t cap = 0;
+  helm_status ensure(size_t bytes);
+  void release();
+};
+
+// Cached trunk-basis coarse space of one op (App. C).
+struct Coarse {
+  int net_serial = -1;  // network the space was built from
+  int p_used = 0;
+  int ksq_version = -1;
+  bool valid = false;
+  int rank = 0;
+  double cond_est = 0.0;
+  double setup_ms = 0.0;
+  Buffer Q;      // n x rank, real (dtype's precision), row-major
+  Buffer Ainv;   // rank x rank complex128, row-major
+  Buffer Ac;     // rank x rank complex128, row-major (kept for inspection)
+  Buffer T;      // trunk matrix at the op's nodes, n x p (dtype's precision)
+  int T_serial = -1;
+  Buffer W1, W2;  // setup work (n x p_used fp64 each)
+  Buffer small;   // setup work: Gram partials, factors, coarse matrices
+  Buffer qpart;   // per-application partials of Q^T r (own buffer: drivers hold op->part)
+};
+
+}  // namespace helm
+
+struct helm_op_s {
+  int dim = 0;
+  int n[3] = {1, 1, 1};
+  size_t nn = 0;
+  helm_dtype dt = HELM_C128;
+  helm::StencilGeom geom{};
+  void* sc = nullptr;        // s = k^2 (1 + i alpha), complex in the dtype's precision
+  uint8_t* mask = nullptr;   // scatterer indicator
+  double* alpha = nullptr;   // sponge profile (kept to rebuild s after helm_set_ksq)
+  double* red = nullptr;     // small reduced results (device, 4096 doubles)
+  double* host = nullptr;    // pinned host mirror for scalar read-backs (4096 doubles)
+  int ksq_version = 0;
+  helm::Buffer tmp;          // one field: Jacobi ping-pong
+  helm::Buffer part;         // reduction partials
+  helm::Buffer ws;           // solver workspace
+  helm::Coarse coarse;
+};
+
+struct don_s;
+
+namespace helm {
+size_t op_esz(const helm_op_s* op);
+helm_status op_part(helm_op_s* op, size_t doubles, double** out);
+
+// ---- DeepONet (deeponet.hip) ----
+// Validate that `net` can act on `op` (grid dimension, dtype) with p_used columns.
+helm_status check_net_for_op(const don_s* net, const helm_op_s* op, int p_used);
+int don_p(const don_s* net);
+int don_serial(const don_s* net);
+// du = s N(r/s), masked (DON_FULL); async on st
+helm_status don_full(don_s* net, helm_op_s* op, const void* r, double k, void* du, hipStream_t st);
+// T = trunk(node coordinates) into `out` (n x p real, dtype precision); async
+helm_status don_trunk(don_s* net, helm_op_s* op, void* out, hipStream_t st);
+
+// ---- coarse space (coarse.hip) ----
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, hipStream_t st);
+template <typename S>
+helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st);  // z += Q A_c^-1 Q^T r1
+void coarse_release(helm_op_s* op);
+
+// ---- shared driver pieces ----
+template <typename S>
+helm_status residual_norm(helm_op_s* op, const void* f, const void* u, void* r, double* norm, hipStream_t st) {
+  double* part;
+  const int nb = stencil_nblocks(op->geom);
+  helm_status s = op_part(op, (size_t)nb, &part);
+  if (s) return s;
+  stencil_resid<S>(op->geom, op->sc, op->mask, f, u, r, part, st);
+  if (norm) {
+    reduce_cols(part, nb, 1, op->red, st);
+    hipError_t e = hipMemcpyAsync(op->host, op->red, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "residual readback");
+    if ((s = sync_stream(st, "residual"))) return s;
+    *norm = std::sqrt(op->host[0]);
+  }
+  return launch_check("residual");
+}
+
+template <typename S>
+helm_status vec_norm(helm_op_s* op, const void* x, double* out, hipStream_t st) {
+  double* part;
+  const int nb = red_nblocks(op->nn);
+  helm_status s = op_part(op, (size_t)nb, &part);
+  if (s) return s;
+  nrm2_part<S>(op->nn, x, part, st);
+  reduce_cols(part, nb, 1, op->red, st);
+  hipError_t e = hipMemcpyAsync(op->host, op->red, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "norm readback");
+  if ((s = sync_stream(st, "norm"))) return s;
+  *out = std::sqrt(op->host[0]);
+  return HELM_OK;
+}
+
+// `sweeps` relaxation steps in place on u; Jacobi ping-pongs through op->tmp.
+template <typename S>
+helm_status relax(helm_op_s* op, int kind, double omega, int sweeps, const void* f, void* u, hipStream_t st) {
+  if (sweeps <= 0) return HELM_OK;
+  if (kind == HELM_RBGS) {
+    for (int k = 0; k < sweeps; ++k) stencil_rbgs<S>(op->geom, op->sc, op->mask, f, u, omega, st);
+    return launch_check("rbgs");
+  }
+  helm_status s = op->tmp.ensure(op->nn * op_esz(op));
+  if (s) return s;
+  void* a = u;
+  void* b = op->tmp.ptr;
+  for (int k = 0; k < sweeps; ++k) {
+    stencil_jacobi<S>(op->geom, op->sc, op->mask, f, a, b, omega, st);
+    void* t = a;
+    a = b;
+    b = t;
+  }
+  if (a != u) copy_vec<S>(op->nn, a, u, st);
+  return launch_check("jacobi");
+}
+
+}  // namespace helm

@@ -1,0 +1,508 @@
+// Solver drivers and the meta-solver C ABI.
+//
+//  * relaxation meta-solver (eq. 3): cycles of n_r smoother sweeps followed by
+//    one DeepONet correction of the residual;
+//  * restarted GMRES(m) with CGS2 and BiCGStab, right-preconditioned, stopping
+//    on the true relative residual (§3.1.2);
+//  * the Krylov preconditioner M(r) = eq. 3 from z = 0 with the linear
+//    trunk-basis M2 = Q A_c^{-1} Q^T of App. C.
+//
+// The host sequences kernel launches; per iteration it reads back one small
+// status record (residual estimate, breakdown flag) to decide control flow.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "lib.h"
+
+namespace helm {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  void* take(size_t bytes) {
+    void* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  }
+  static size_t need(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+};
+
+struct MetaCtx {
+  const meta_opts* o;
+  don_s* net;
+  bool use_M;  // Krylov: apply the preconditioner (net != NULL)
+  void* r1;    // scratch field for the preconditioner residual
+};
+
+// z = M(v): n_r smoother sweeps on A z = v from z = 0, then the coarse
+// correction z += Q A_c^{-1} Q^T (v - A z).
+template <typename S>
+helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* z, hipStream_t st) {
+  const meta_opts* o = c.o;
+  const size_t n = op->nn;
+  helm_status s;
+  if (o->n_r > 0) {
+    if (o->smoother == HELM_JACOBI) {
+      jacobi_from_zero<S>(n, op->geom.dsum, op->sc, op->mask, v, z, o->omega, st);
+      if (o->n_r > 1) {
+        if ((s = op->tmp.ensure(n * op_esz(op)))) return s;
+        void* a = z;
+        void* b = op->tmp.ptr;
+        for (int k = 1; k < o->n_r; ++k) {
+          stencil_jacobi<S>(op->geom, op->sc, op->mask, v, a, b, o->omega, st);
+          void* t = a;
+          a = b;
+          b = t;
+        }
+        if (a != z) copy_vec<S>(n, a, z, st);
+      }
+    } else {
+      zero_vec<S>(n, z, st);
+      for (int k = 0; k < o->n_r; ++k) stencil_rbgs<S>(op->geom, op->sc, op->mask, v, z, o->omega, st);
+    }
+  } else {
+    zero_vec<S>(n, z, st);
+  }
+  if (c.net) {
+    double* part;
+    if ((s = op_part(op, (size_t)stencil_nblocks(op->geom), &part))) return s;
+    stencil_resid<S>(op->geom, op->sc, op->mask, v, z, c.r1, part, st);
+    if ((s = coarse_correct<S>(op, c.r1, z, st))) return s;
+  }
+  return launch_check("precond");
+}
+
+static helm_status read_host(helm_op_s* op, const void* dev, size_t bytes, hipStream_t st, const char* what) {
+  hipError_t e = hipMemcpyAsync(op->host, dev, bytes, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return sync_stream(st, what);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m), CGS2, right preconditioning
+// ---------------------------------------------------------------------------
+template <typename S>
+helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_stats* out, hipStream_t st) {
+  const meta_opts* o = c.o;
+  const int m = o->restart;
+  const size_t n = op->nn, esz = op_esz(op);
+  const size_t fld = Carve::need(n * esz);
+  const size_t dsm = Carve::need(sizeof(double) * (2 * (size_t)(m + 1) * m + 8 * (size_t)(m + 1) + 64));
+  helm_status s = op->ws.ensure(fld * (size_t)(m + 1 + 3) + dsm + Carve::need(sizeof(GmState)));
+  if (s) return s;
+  Carve cv(op->ws.ptr);
+  char* V = (char*)cv.take(fld * (m + 1));
+  void* z = cv.take(n * esz);
+  void* t = cv.take(n * esz);
+  c.r1 = cv.take(n * esz);
+  double* H = (double*)cv.take(sizeof(double) * 2 * (m + 1) * m);
+  double* g = (double*)cv.take(sizeof(double) * 2 * (m + 1));
+  double* cs = (double*)cv.take(sizeof(double) * (m + 1));
+  double* sn = (double*)cv.take(sizeof(double) * 2 * (m + 1));
+  double* y = (double*)cv.take(sizeof(double) * 2 * (m + 1));
+  double* h1 = (double*)cv.take(sizeof(double) * 2 * (m + 1));
+  double* h2 = (double*)cv.take(sizeof(double) * 2 * (m + 1));
+  double* nrm = (double*)cv.take(sizeof(double) * 8);
+  GmState* gs = (GmState*)cv.take(sizeof(GmState));
+  const size_t ldv = fld / esz;  // elements between basis vectors
+  auto Vj = [&](int j) { return (void*)(V + (size_t)j * fld); };
+
+  const int mdb = multidot_nblocks(n), rdb = red_nblocks(n), stb = stencil_nblocks(op->geom);
+  size_t pneed = (size_t)mdb * 2 * (m + 1);
+  if ((size_t)rdb > pneed) pneed = rdb;
+  if ((size_t)stb > pneed) pneed = stb;
+  double* part;
+  if ((s = op_part(op, pneed, &part))) return s;
+
+  double fn;
+  if ((s = vec_norm<S>(op, f, &fn, st))) return s;
+  if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "gmres: ||f|| is not finite");
+  const double thr = o->tol * fn;
+  int count = 0, matvecs = 0, papps = 0, hlen = 0;
+  helm_status status = HELM_NOT_CONVERGED;
+  double beta = 0.0;
+  for (;;) {
+    // r = f - A u into V_0, beta = ||r||
+    stencil_resid<S>(op->geom, op->sc, op->mask, f, u, Vj(0), part, st);
+    matvecs++;
+    reduce_cols(part, stb, 1, nrm, st);
+    if ((s = read_host(op, nrm, sizeof(double), st, "gmres: residual"))) return s;
+    beta = std::sqrt(op->host[0]);
+    if (o->history && hlen == 0) o->history[hlen++] = fn > 0 ? beta / fn : beta;
+    if (!std::isfinite(beta)) {
+      status = HELM_E_NONFINITE;
+      break;
+    }
+    if (beta <= thr) {
+      status = HELM_OK;
+      break;
+    }
+    if (count >= o->max_iters) break;
+    scale_host<S>(n, Vj(0), 1.0 / beta, Vj(0), st);
+    gmres_init(beta, g, m, st);
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      const void* zj = Vj(j);
+      if (c.use_M) {
+        if ((s = precond_apply<S>(op, c, Vj(j), z, st))) return s;
+        zj = z;
+        papps++;
+      }
+      void* w = Vj(j + 1);
+      stencil_apply<S>(op->geom, op->sc, op->mask, zj, w, st);
+      matvecs++;
+      // CGS2: two classical Gram-Schmidt passes
+      multidot_part<S>(n, V, ldv, j + 1, w, part, st);
+      reduce_cols(part, mdb, 2 * (j + 1), h1, st);
+      multi_axpy<S>(n, V, ldv, j + 1, h1, -1.0, w, w, nullptr, st);
+      multidot_part<S>(n, V, ldv, j + 1, w, part, st);
+      reduce_cols(part, mdb, 2 * (j + 1), h2, st);
+      multi_axpy<S>(n, V, ldv, j + 1, h2, -1.0, w, w, part, st);
+      reduce_cols(part, rdb, 1, nrm, st);
+      arnoldi_finish(j, m, H, g, cs, sn, h1, h2, nrm, gs, st);
+      scale_dev<S>(n, w, &gs->inv_hn, w, st);
+      if ((s = read_host(op, gs, sizeof(GmState), st, "gmres: arnoldi"))) return s;
+      const GmState* hs = (const GmState*)op->host;
+      count++;
+      k = j + 1;
+      if (o->history && hlen <= o->max_iters) o->history[hlen++] = fn > 0 ? hs->gabs / fn : hs->gabs;
+      if (hs->flag) {
+        status = HELM_E_NONFINITE;
+        break;
+      }
+      if (hs->gabs <= thr || count >= o->max_iters || hs->hn == 0.0) break;
+    }
+    if (status == HELM_E_NONFINITE) break;
+    // u += M (V_k y)
+    gmres_backsolve(k, m, H, g, y, st);
+    multi_axpy<S>(n, V, ldv, k, y, 1.0, nullptr, t, nullptr, st);
+    if (c.use_M) {
+      if ((s = precond_apply<S>(op, c, t, z, st))) return s;
+      papps++;
+      add_inplace<S>(n, z, u, st);
+    } else {
+      add_inplace<S>(n, t, u, st);
+    }
+  }
+  if ((s = launch_check("gmres"))) return s;
+  // true final residual
+  double rn;
+  if ((s = residual_norm<S>(op, f, u, Vj(0), &rn, st))) return s;
+  out->iters = count;
+  out->matvecs = matvecs;
+  out->precond_apps = papps;
+  out->rel_res = fn > 0 ? rn / fn : rn;
+  out->history_len = hlen;
+  if (status == HELM_NOT_CONVERGED && rn <= thr) status = HELM_OK;
+  out->converged = status == HELM_OK;
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab, right preconditioning
+// ---------------------------------------------------------------------------
+template <typename S>
+helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_stats* out, hipStream_t st) {
+  const meta_opts* o = c.o;
+  const size_t n = op->nn, esz = op_esz(op);
+  const size_t fld = Carve::need(n * esz);
+  helm_status s = op->ws.ensure(fld * 9 + Carve::need(sizeof(BiState)) + Carve::need(64 * sizeof(double)));
+  if (s) return s;
+  Carve cv(op->ws.ptr);
+  void* r = cv.take(n * esz);
+  void* rh = cv.take(n * esz);
+  void* p = cv.take(n * esz);
+  void* v = cv.take(n * esz);
+  void* sv = cv.take(n * esz);
+  void* t = cv.take(n * esz);
+  void* ph = cv.take(n * esz);
+  void* sh = cv.take(n * esz);
+  c.r1 = cv.take(n * esz);
+  BiState* bs = (BiState*)cv.take(sizeof(BiState));
+  double* red = (double*)cv.take(64 * sizeof(double));
+  const int rdb = red_nblocks(n), stb = stencil_nblocks(op->geom);
+  double* part;
+  if ((s = op_part(op, (size_t)(3 * rdb > stb ? 3 * rdb : stb), &part))) return s;
+  if (!c.use_M) {
+    ph = p;
+    sh = sv;
+  }
+
+  double fn;
+  if ((s = vec_norm<S>(op, f, &fn, st))) return s;
+  if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "bicgstab: ||f|| is not finite");
+  const double thr = o->tol * fn;
+  int count = 0, matvecs = 0, papps = 0, hlen = 0;
+  helm_status status = HELM_NOT_CONVERGED;
+  double rn;
+  if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
+  matvecs++;
+  if (o->history) o->history[hlen++] = fn > 0 ? rn / fn : rn;
+  if (!std::isfinite(rn)) status = HELM_E_NONFINITE;
+  else if (rn <= thr) status = HELM_OK;
+  while (status == HELM_NOT_CONVERGED) {
+    copy_vec<S>(n, r, rh, st);
+    BiState init{};
+    init.rho0[0] = init.alpha[0] = init.omega[0] = 1.0;
+    hipError_t e = hipMemcpyAsync(bs, &init, sizeof init, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "bicgstab: state");
+    // rho for the first iteration of this sweep
+    dot_part<S>(n, rh, r, part, st);
+    reduce_cols(part, rdb, 2, red + 8, st);
+    bool first = true, stopped = false;
+    while (count < o->max_iters) {
+      bicg_scalar(BI_RHO, bs, red + 8, st);
+      bicg_p<S>(n, r, v, p, bs, first ? 1 : 0, st);
+      first = false;
+      if (c.use_M) {
+        if ((s = precond_apply<S>(op, c, p, ph, st))) return s;
+        papps++;
+      }
+      stencil_apply<S>(op->geom, op->sc, op->mask, ph, v, st);
+      matvecs++;
+      dot_part<S>(n, rh, v, part, st);
+      reduce_cols(part, rdb, 2, red, st);
+      bicg_scalar(BI_ALPHA, bs, red, st);
+      bicg_s<S>(n, r, v, sv, bs, part, st);
+      reduce_cols(part, rdb, 1, red + 2, st);
+      bicg_scalar(BI_SS, bs, red + 2, st);
+      count++;
+      if ((s = read_host(op, bs, sizeof(BiState), st, "bicgstab: s"))) return s;
+      BiState hb = *(const BiState*)op->host;
+      if (hb.flag) {
+        status = hb.flag == -4 ? HELM_E_BREAKDOWN : HELM_E_NONFINITE;
+        stopped = true;
+        break;
+      }
+      if (!std::isfinite(hb.ss)) {
+        status = HELM_E_NONFINITE;
+        stopped = true;
+        break;
+      }
+      if (hb.ss <= thr) {
+        axpy_dev<S>(n, ph, u, bs->alpha, st);
+        if (o->history && hlen <= o->max_iters) o->history[hlen++] = hb.ss / fn;
+        break;
+      }
+      if (c.use_M) {
+        if ((s = precond_apply<S>(op, c, sv, sh, st))) return s;
+        papps++;
+      }
+      stencil_apply<S>(op->geom, op->sc, op->mask, sh, t, st);
+      matvecs++;
+      two_dot_part<S>(n, t, sv, part, st);
+      reduce_cols(part, rdb, 3, red + 4, st);
+      bicg_scalar(BI_OMEGA, bs, red + 4, st);
+      bicg_update<S>(n, ph, sh, sv, t, rh, u, r, bs, part, st);
+      reduce_cols(part, rdb, 3, red + 8 - 1, st);  // red[7] = ||r||^2, red[8..9] = r_hat^H r (next rho)
+      bicg_scalar(BI_RR, bs, red + 7, st);
+      if ((s = read_host(op, bs, sizeof(BiState), st, "bicgstab: r"))) return s;
+      hb = *(const BiState*)op->host;
+      if (hb.flag) {
+        status = hb.flag == -4 ? HELM_E_BREAKDOWN : HELM_E_NONFINITE;
+        stopped = true;
+        break;
+      }
+      if (o->history && hlen <= o->max_iters) o->history[hlen++] = hb.rr / fn;
+      if (!std::isfinite(hb.rr)) {
+        status = HELM_E_NONFINITE;
+        stopped = true;
+        break;
+      }
+      if (hb.rr <= thr) break;
+    }
+    if (stopped) break;
+    if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
+    matvecs++;
+    if (!std::isfinite(rn)) status = HELM_E_NONFINITE;
+    else if (rn <= thr) status = HELM_OK;
+    else if (count >= o->max_iters) break;
+  }
+  if ((s = launch_check("bicgstab"))) return s;
+  if ((s = residual_norm<S>(op, f, u, c.r1, &rn, st))) return s;
+  out->iters = count;
+  out->matvecs = matvecs;
+  out->precond_apps = papps;
+  out->rel_res = fn > 0 ? rn / fn : rn;
+  out->history_len = hlen;
+  out->converged = status == HELM_OK;
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// relaxation meta-solver, eq. 3
+// ---------------------------------------------------------------------------
+template <typename S>
+helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_stats* out, hipStream_t st) {
+  const meta_opts* o = c.o;
+  const size_t n = op->nn, esz = op_esz(op);
+  helm_status s = op->ws.ensure(Carve::need(n * esz) * 2);
+  if (s) return s;
+  Carve cv(op->ws.ptr);
+  void* r = cv.take(n * esz);
+  void* du = cv.take(n * esz);
+  const int kind = o->kind == META_JACOBI ? HELM_JACOBI : HELM_RBGS;
+  double fn;
+  if ((s = vec_norm<S>(op, f, &fn, st))) return s;
+  int count = 0, ncorr = 0, hlen = 0, matvecs = 0;
+  helm_status status = HELM_NOT_CONVERGED;
+  double rn = 0.0;
+  while (count < o->max_iters) {
+    int cyc = o->nn_every > 0 ? o->nn_every : o->max_iters - count;
+    if (cyc > o->max_iters - count) cyc = o->max_iters - count;
+    if ((s = relax<S>(op, kind, o->omega, cyc, f, u, st))) return s;
+    count += cyc;
+    matvecs += cyc;
+    if (c.net && o->nn_every > 0 && cyc == o->nn_every) {
+      if ((s = residual_norm<S>(op, f, u, r, nullptr, st))) return s;
+      matvecs++;
+      if ((s = don_full(c.net, op, r, o->k, du, st))) return s;
+      add_inplace<S>(n, du, u, st);
+      ncorr++;
+    }
+    if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
+    matvecs++;
+    const double rel = fn > 0 ? rn / fn : rn;
+    if (o->history && hlen <= o->max_iters) o->history[hlen++] = rel;
+    if (!std::isfinite(rel)) {
+      status = HELM_E_NONFINITE;
+      break;
+    }
+    if (rel <= o->tol) {
+      status = HELM_OK;
+      break;
+    }
+  }
+  if (count == 0) {
+    if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
+    if (rn <= o->tol * fn) status = HELM_OK;
+  }
+  out->iters = count;
+  out->matvecs = matvecs;
+  out->precond_apps = ncorr;
+  out->rel_res = fn > 0 ? rn / fn : rn;
+  out->history_len = hlen;
+  out->converged = status == HELM_OK;
+  return status;
+}
+
+template <typename S>
+helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const void* f, void* u, meta_stats* st_out,
+                          hipStream_t st) {
+  MetaCtx c{o, net, net != nullptr, nullptr};
+  helm_status s;
+  hipEvent_t e0, e1, e2;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipEventCreate(&e2);
+  (void)hipEventRecord(e0, st);
+  if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
+    if ((s = coarse_ensure(op, net, o->p_used, st))) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      (void)hipEventDestroy(e2);
+      return s;
+    }
+    st_out->rank_used = op->coarse.rank;
+    st_out->cond_Ac_est = op->coarse.cond_est;
+  }
+  (void)hipEventRecord(e1, st);
+  if (o->kind == META_GMRES) s = gmres_drive<S>(op, c, f, u, st_out, st);
+  else if (o->kind == META_BICGSTAB) s = bicgstab_drive<S>(op, c, f, u, st_out, st);
+  else s = relax_meta_drive<S>(op, c, f, u, st_out, st);
+  (void)hipEventRecord(e2, st);
+  (void)hipEventSynchronize(e2);
+  float a = 0.f, b = 0.f;
+  (void)hipEventElapsedTime(&a, e0, e1);
+  (void)hipEventElapsedTime(&b, e1, e2);
+  st_out->setup_ms = a;
+  st_out->solve_ms = b;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  return s;
+}
+
+static helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o) {
+  if (!o) return fail(HELM_E_INVAL, "meta: opts is NULL");
+  if (o->kind < META_JACOBI || o->kind > META_BICGSTAB) return fail(HELM_E_INVAL, "meta: unknown kind %d", o->kind);
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HELM_E_INVAL, "meta: tol must be finite and >= 0");
+  if (o->max_iters < 0) return fail(HELM_E_INVAL, "meta: max_iters < 0");
+  if (o->kind == META_GMRES && (o->restart < 1 || o->restart > 1000))
+    return fail(HELM_E_INVAL, "meta: restart must be in [1, 1000]");
+  if (o->smoother != HELM_JACOBI && o->smoother != HELM_RBGS)
+    return fail(HELM_E_INVAL, "meta: unknown smoother %d", o->smoother);
+  if (o->n_r < 0) return fail(HELM_E_INVAL, "meta: n_r < 0");
+  if (!std::isfinite(o->omega)) return fail(HELM_E_INVAL, "meta: omega not finite");
+  if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
+    helm_status s = check_net_for_op(net, op, o->p_used);
+    if (s) return s;
+  }
+  if (net && (o->kind == META_JACOBI || o->kind == META_GS)) {
+    helm_status s = check_net_for_op(net, op, 1);
+    if (s) return s;
+  }
+  return HELM_OK;
+}
+
+}  // namespace helm
+
+using namespace helm;
+
+extern "C" {
+
+helm_status meta_solve(helm_op op, don_net net, const meta_opts* o, const void* f, void* u, meta_stats* st,
+                       void* stream) {
+  if (!op || !f || !u || !st) return fail(HELM_E_INVAL, "meta_solve: NULL argument");
+  if (f == u) return fail(HELM_E_INVAL, "meta_solve: f and u alias");
+  helm_status s = check_opts(op, net, o);
+  if (s) return s;
+  std::memset(st, 0, sizeof *st);
+  hipStream_t hs = (hipStream_t)stream;
+  return op->dt == HELM_C128 ? meta_dispatch<double>(op, net, o, f, u, st, hs)
+                             : meta_dispatch<float>(op, net, o, f, u, st, hs);
+}
+
+helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void* r, void* z, void* stream) {
+  if (!op || !r || !z) return fail(HELM_E_INVAL, "meta_precond: NULL argument");
+  if (r == z) return fail(HELM_E_INVAL, "meta_precond: r and z alias");
+  helm_status s = check_opts(op, net, o);
+  if (s) return s;
+  hipStream_t hs = (hipStream_t)stream;
+  if (net && (s = coarse_ensure(op, net, o->p_used, hs))) return s;
+  const size_t fld = op->nn * op_esz(op);
+  if ((s = op->ws.ensure(fld))) return s;
+  MetaCtx c{o, net, true, op->ws.ptr};
+  s = op->dt == HELM_C128 ? precond_apply<double>(op, c, r, z, hs) : precond_apply<float>(op, c, r, z, hs);
+  if (s) return s;
+  return sync_stream(hs, "meta_precond");
+}
+
+helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* rank, double* Ac, size_t ac_cap,
+                             void* Q, size_t q_cap, void* stream) {
+  if (!op || !net || !o || !rank) return fail(HELM_E_INVAL, "meta_coarse_info: NULL argument");
+  helm_status s = check_net_for_op(net, op, o->p_used);
+  if (s) return s;
+  hipStream_t hs = (hipStream_t)stream;
+  if ((s = coarse_ensure(op, net, o->p_used, hs))) return s;
+  const int r = op->coarse.rank;
+  *rank = r;
+  if (Ac) {
+    if (ac_cap < (size_t)r * r) return fail(HELM_E_INVAL, "meta_coarse_info: Ac capacity %zu < %d", ac_cap, r * r);
+    hipError_t e = hipMemcpyAsync(Ac, op->coarse.Ac.ptr, sizeof(double) * 2 * r * r, hipMemcpyDeviceToHost, hs);
+    if (e != hipSuccess) return hip_fail(e, "meta_coarse_info: Ac");
+  }
+  if (Q) {
+    if (q_cap < op->nn * (size_t)r) return fail(HELM_E_INVAL, "meta_coarse_info: Q capacity too small");
+    const size_t rs = op->dt == HELM_C128 ? sizeof(double) : sizeof(float);
+    hipError_t e = hipMemcpyAsync(Q, op->coarse.Q.ptr, rs * op->nn * r, hipMemcpyDeviceToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "meta_coarse_info: Q");
+  }
+  return sync_stream(hs, "meta_coarse_info");
+}
+
+}  // extern "C"

@@ -1,0 +1,14 @@
+// Per-kernel event timing used by the benchmark (see helm_kprof_* in helm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace helm {
+
+enum { KP_STENCIL = 0, KP_MULTIDOT = 1, KP_MULTIAXPY = 2, KP_QT = 3, KP_SKINNY = 4, KP_COUNT = 5 };
+
+bool kprof_on();
+void kprof_begin(hipStream_t st);
+void kprof_end(int kind, double bytes, hipStream_t st);
+
+}  // namespace helm

@@ -1,0 +1,313 @@
+"""Python binding of libhelm's C ABI (argument marshalling only).
+
+Every function here converts arguments (torch tensors to device pointers,
+Python numbers and lists to C structs), calls the entry point of the same name
+in ``libhelm.so`` and converts the results back.  No step of the numerical
+method runs in Python.  Importing this module fails loudly when the compiled
+library is absent.
+
+torch is imported before the library is loaded so that libhelm binds to the
+HIP runtime already loaded by torch (same SONAME), giving one runtime per
+process; torch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhelm.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"libhelm.so not found at {_LIB_PATH}: build it with "
+                      "`python -m paper_2405_12380_amd.build` (no fallback exists)")
+_lib = C.CDLL(_LIB_PATH)
+
+# ---- constants (mirror include/helm.h) --------------------------------------
+OK, NOT_CONVERGED = 0, 1
+E_INVAL, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_SINGULAR = -1, -2, -3, -4, -5, -6
+C64, C128 = 1, 2
+JACOBI, RBGS = 0, 1
+DON_TANH, DON_RELU, DON_LEAKY = 0, 1, 2
+DON_SPLIT_OUTPUT, DON_SPLIT_INPUT = 0, 1
+DON_TRUNK, DON_FULL = 0, 1
+META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
+
+EXPORTED = ["helm_setup", "helm_set_ksq", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
+            "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
+            "meta_solve", "meta_precond", "meta_coarse_info", "helm_kprof_enable", "helm_kprof_read",
+            "helm_strerror", "helm_last_error"]
+KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY = 0, 1, 2, 3, 4
+KP_NAMES = {KP_STENCIL: "stencil", KP_MULTIDOT: "multidot", KP_MULTIAXPY: "multi_axpy", KP_QT: "qt_part",
+            KP_SKINNY: "skinny_apply"}
+
+
+class HelmGrid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3)]
+
+
+class DonDesc(C.Structure):
+    _fields_ = [("n_branch", C.c_int), ("branch_w", C.POINTER(C.c_int)), ("n_trunk", C.c_int),
+                ("trunk_w", C.POINTER(C.c_int)), ("act", C.c_int), ("head", C.c_int), ("p", C.c_int),
+                ("branch_grid", C.c_int * 3), ("k_input", C.c_int)]
+
+
+class MetaOpts(C.Structure):
+    _fields_ = [("kind", C.c_int), ("restart", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
+                ("smoother", C.c_int), ("n_r", C.c_int), ("omega", C.c_double), ("nn_every", C.c_int),
+                ("p_used", C.c_int), ("k", C.c_double), ("history", C.POINTER(C.c_double))]
+
+
+class MetaStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("matvecs", C.c_int), ("precond_apps", C.c_int), ("converged", C.c_int),
+                ("rank_used", C.c_int), ("history_len", C.c_int), ("rel_res", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("cond_Ac_est", C.c_double)]
+
+
+_vp = C.c_void_p
+_sig = {
+    "helm_setup": (C.c_int, [C.POINTER(HelmGrid), C.c_int, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
+    "helm_set_ksq": (C.c_int, [_vp, _vp, _vp]),
+    "helm_destroy": (None, [_vp]),
+    "helm_size": (C.c_size_t, [_vp]),
+    "helm_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "helm_residual": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "helm_relax": (C.c_int, [_vp, C.c_int, C.c_double, C.c_int, _vp, _vp, _vp]),
+    "helm_dot": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "helm_nrm2": (C.c_int, [_vp, _vp, C.POINTER(C.c_double), _vp]),
+    "deeponet_load": (C.c_int, [C.c_int, C.POINTER(DonDesc), C.POINTER(C.POINTER(C.c_double)), C.POINTER(_vp)]),
+    "deeponet_free": (None, [_vp]),
+    "deeponet_infer": (C.c_int, [_vp, _vp, C.c_int, _vp, C.c_double, _vp, _vp]),
+    "meta_solve": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), _vp, _vp, C.POINTER(MetaStats), _vp]),
+    "meta_precond": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), _vp, _vp, _vp]),
+    "meta_coarse_info": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                   C.c_size_t, _vp, C.c_size_t, _vp]),
+    "helm_kprof_enable": (C.c_int, [C.c_int]),
+    "helm_kprof_read": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "helm_strerror": (C.c_char_p, [C.c_int]),
+    "helm_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.helm_last_error().decode() or _lib.helm_strerror(status).decode()
+        super().__init__(f"{where}: {_lib.helm_strerror(status).decode()} ({status}): {msg}")
+
+
+def _check(status, where, allow=(OK,)):
+    if status not in allow:
+        raise HelmError(status, where)
+    return status
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return _vp(t.data_ptr())
+
+
+def cdtype(dt: int):
+    return torch.complex128 if dt == C128 else torch.complex64
+
+
+def rdtype(dt: int):
+    return torch.float64 if dt == C128 else torch.float32
+
+
+def _dev(a, dtype, device="cuda"):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous().reshape(-1)
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).reshape(-1)
+
+
+class Op:
+    """The discrete Helmholtz operator on a grid (``helm_setup``).
+
+    ``n`` is (nx, ny) or (nx, ny, nz); ``ksq``, ``alpha`` (real) and ``mask``
+    (uint8) are arrays of the field shape or flat, host or device."""
+
+    def __init__(self, n, dtype: int, ksq, alpha, mask, stream=None):
+        self.n = tuple(int(v) for v in n)
+        self.dim = len(self.n)
+        self.dtype = dtype
+        g = HelmGrid(self.dim, (C.c_int * 3)(*(list(self.n) + [1] * (3 - self.dim))))
+        k = _dev(ksq, torch.float64)
+        a = _dev(alpha, torch.float64)
+        m = _dev(mask, torch.uint8)
+        h = _vp()
+        _check(_lib.helm_setup(C.byref(g), dtype, _ptr(k), _ptr(a), _ptr(m), _stream(stream), C.byref(h)),
+               "helm_setup")
+        self.h = h
+        self.size = int(_lib.helm_size(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.helm_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def field(self, a=None):
+        """A device field of this op's complex dtype (zeros, or converted from ``a``)."""
+        if a is None:
+            return torch.zeros(self.size, dtype=cdtype(self.dtype), device="cuda")
+        return _dev(a, cdtype(self.dtype))
+
+    def set_ksq(self, ksq, stream=None):
+        k = _dev(ksq, torch.float64)
+        _check(_lib.helm_set_ksq(self.h, _ptr(k), _stream(stream)), "helm_set_ksq")
+
+    def apply(self, x, y=None, stream=None):
+        y = self.field() if y is None else y
+        _check(_lib.helm_apply(self.h, _ptr(x), _ptr(y), _stream(stream)), "helm_apply")
+        return y
+
+    def residual(self, f, u, r=None, norm=False, stream=None):
+        r = self.field() if r is None else r
+        nv = C.c_double(0.0)
+        _check(_lib.helm_residual(self.h, _ptr(f), _ptr(u), _ptr(r), C.byref(nv) if norm else None,
+                                  _stream(stream)), "helm_residual")
+        return (r, nv.value) if norm else r
+
+    def relax(self, kind: int, omega: float, sweeps: int, f, u, stream=None):
+        _check(_lib.helm_relax(self.h, kind, float(omega), int(sweeps), _ptr(f), _ptr(u), _stream(stream)),
+               "helm_relax")
+        return u
+
+    def dot(self, x, y, stream=None) -> complex:
+        out = (C.c_double * 2)()
+        _check(_lib.helm_dot(self.h, _ptr(x), _ptr(y), out, _stream(stream)), "helm_dot")
+        return complex(out[0], out[1])
+
+    def nrm2(self, x, stream=None) -> float:
+        out = C.c_double(0.0)
+        _check(_lib.helm_nrm2(self.h, _ptr(x), C.byref(out), _stream(stream)), "helm_nrm2")
+        return out.value
+
+
+_ACT = {"tanh": DON_TANH, "relu": DON_RELU, "leaky": DON_LEAKY}
+_HEAD = {"split_output": DON_SPLIT_OUTPUT, "split_input": DON_SPLIT_INPUT}
+
+
+class DeepONet:
+    """A DeepONet uploaded to the device (``deeponet_load``).  ``branch`` and
+    ``trunk`` are lists of (W, b) numpy arrays, W of shape (fan_in, fan_out)."""
+
+    def __init__(self, dtype: int, branch, trunk, p: int, head="split_output", act="tanh", branch_grid=(1, 1, 1),
+                 k_input=False):
+        self.dtype = dtype
+        self.p = int(p)
+        bw = [int(branch[0][0].shape[0])] + [int(W.shape[1]) for W, _ in branch]
+        tw = [int(trunk[0][0].shape[0])] + [int(W.shape[1]) for W, _ in trunk]
+        bg = list(branch_grid) + [1] * (3 - len(branch_grid))
+        self._bw = (C.c_int * len(bw))(*bw)
+        self._tw = (C.c_int * len(tw))(*tw)
+        d = DonDesc(len(bw), self._bw, len(tw), self._tw, _ACT[act], _HEAD[head], self.p,
+                    (C.c_int * 3)(*bg), 1 if k_input else 0)
+        arrays = []
+        for W, b in list(branch) + list(trunk):
+            arrays.append(np.ascontiguousarray(W, dtype=np.float64))
+            arrays.append(np.ascontiguousarray(b, dtype=np.float64))
+        ptrs = (C.POINTER(C.c_double) * len(arrays))(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrays])
+        h = _vp()
+        _check(_lib.deeponet_load(dtype, C.byref(d), ptrs, C.byref(h)), "deeponet_load")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.deeponet_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def trunk(self, op: Op, out=None, stream=None):
+        out = torch.empty(op.size * self.p, dtype=rdtype(self.dtype), device="cuda") if out is None else out
+        _check(_lib.deeponet_infer(self.h, op.h, DON_TRUNK, None, 0.0, _ptr(out), _stream(stream)), "deeponet_infer")
+        return out
+
+    def full(self, op: Op, r, k=0.0, out=None, stream=None):
+        out = op.field() if out is None else out
+        _check(_lib.deeponet_infer(self.h, op.h, DON_FULL, _ptr(r), float(k), _ptr(out), _stream(stream)),
+               "deeponet_infer")
+        return out
+
+
+_KIND = {"jacobi": META_JACOBI, "gs": META_GS, "gmres": META_GMRES, "bicgstab": META_BICGSTAB}
+_SMOOTH = {"jacobi": JACOBI, "rbgs": RBGS}
+
+
+def _opts(kind, restart=50, tol=1e-6, max_iters=20000, smoother="jacobi", n_r=3, omega=0.5, nn_every=25,
+          p_used=None, k=0.0, history=None, net=None):
+    pu = p_used if p_used is not None else (net.p if net is not None else 0)
+    hp = history.ctypes.data_as(C.POINTER(C.c_double)) if history is not None else None
+    return MetaOpts(_KIND[kind] if isinstance(kind, str) else int(kind), int(restart), float(tol), int(max_iters),
+                    _SMOOTH[smoother] if isinstance(smoother, str) else int(smoother), int(n_r), float(omega),
+                    int(nn_every), int(pu), float(k), hp)
+
+
+def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, stream=None, **kw):
+    """Run ``meta_solve``; returns (status, stats dict[, history array]).  u is
+    updated in place.  Status HELM_NOT_CONVERGED is returned, not raised."""
+    hist = np.zeros(int(kw.get("max_iters", 20000)) + 2) if history else None
+    o = _opts(kind, history=hist, net=net, **kw)
+    st = MetaStats()
+    s = _lib.meta_solve(op.h, net.h if net is not None else None, C.byref(o), _ptr(f), _ptr(u), C.byref(st),
+                        _stream(stream))
+    _check(s, "meta_solve", allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    stats = {name: getattr(st, name) for name, _ in MetaStats._fields_}
+    stats["status"] = s
+    if history:
+        return s, stats, hist[: st.history_len].copy()
+    return s, stats
+
+
+def meta_precond(op: Op, net: DeepONet | None, r, z=None, stream=None, **kw):
+    z = op.field() if z is None else z
+    o = _opts("gmres", net=net, **kw)
+    _check(_lib.meta_precond(op.h, net.h if net is not None else None, C.byref(o), _ptr(r), _ptr(z),
+                             _stream(stream)), "meta_precond")
+    return z
+
+
+def coarse_info(op: Op, net: DeepONet, p_used=None, want_q=False, stream=None):
+    """(rank, A_c as a complex numpy array[, Q as a device tensor n x rank])."""
+    o = _opts("gmres", net=net, p_used=p_used)
+    rank = C.c_int(0)
+    _check(_lib.meta_coarse_info(op.h, net.h, C.byref(o), C.byref(rank), None, 0, None, 0, _stream(stream)),
+           "meta_coarse_info")
+    r = rank.value
+    ac = np.zeros(2 * r * r)
+    q = torch.empty(op.size * r, dtype=rdtype(op.dtype), device="cuda") if want_q else None
+    _check(_lib.meta_coarse_info(op.h, net.h, C.byref(o), C.byref(rank), ac.ctypes.data_as(C.POINTER(C.c_double)),
+                                 r * r, _ptr(q), op.size * r if want_q else 0, _stream(stream)), "meta_coarse_info")
+    A = ac.view(np.complex128).reshape(r, r)
+    return (r, A, q) if want_q else (r, A)
+
+
+def kprof_enable(on: bool = True):
+    """Turn per-kernel event timing on (clearing earlier records) or off."""
+    _check(_lib.helm_kprof_enable(1 if on else 0), "helm_kprof_enable")
+
+
+def kprof_read(kind: int):
+    """(launches, total ms, total algorithmic bytes) for one kernel class."""
+    n, ms, by = C.c_int(0), C.c_double(0.0), C.c_double(0.0)
+    _check(_lib.helm_kprof_read(kind, C.byref(n), C.byref(ms), C.byref(by)), "helm_kprof_read")
+    return n.value, ms.value, by.value
