@@ -173,6 +173,9 @@ typedef struct {
   int p_used;      /* Krylov kinds with a network: trunk columns used (1..p)        */
   double k;        /* wave number passed to a network with k_input                  */
   double* history; /* optional host array of max_iters+1 relative residuals, or NULL */
+  int q_fp32;      /* Krylov kinds with a network: store the basis Q in fp32 (C128;
+                      always so for C64).  A_c is then the Galerkin matrix of the
+                      stored basis; halves the bytes of the coarse correction.      */
 } meta_opts;
 
 typedef struct {
@@ -194,7 +197,7 @@ typedef struct {
  *     most tau times the largest column norm are dropped, tau = 1e-7 (C128),
  *     1e-5 (C64)) and A_c = Q^T A Q (App. C).  With net == NULL, M = I.
  * u holds u0 on entry and the last iterate on exit (also when not converged).
- * The coarse space is cached on the op, keyed by (net, p_used, k^2 version).
+ * The coarse space is cached on the op, keyed by (net, p_used, q_fp32, k^2 version).
  * Synchronous.  Returns HELM_OK, HELM_NOT_CONVERGED, HELM_E_BREAKDOWN,
  * HELM_E_NONFINITE, HELM_E_SINGULAR or an argument/HIP error. */
 helm_status meta_solve(helm_op op, don_net net, const meta_opts* o, const void* f, void* u,
@@ -222,7 +225,8 @@ enum { HELM_KP_STENCIL = 0,   /* apply / residual / Jacobi / red-black sweeps   
        HELM_KP_MULTIDOT = 1,  /* GMRES multi-dot V^H w                              */
        HELM_KP_MULTIAXPY = 2, /* GMRES multi-axpy w -= V h and V y                  */
        HELM_KP_QT = 3,        /* coarse restriction Q^T r (per-block partials)      */
-       HELM_KP_SKINNY = 4 };  /* prolongation z += Q c and the DeepONet synthesis   */
+       HELM_KP_SKINNY = 4,    /* prolongation z += Q c and the DeepONet synthesis   */
+       HELM_KP_CGS = 5 };     /* fused CGS pass w -= V h with the partials of V^H w */
 
 /* Enable (1) or disable (0) per-kernel timing for the whole process, clearing
  * earlier records (waits for the device).  While enabled, each launch of a timed

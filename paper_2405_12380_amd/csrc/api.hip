@@ -144,13 +144,15 @@ helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, con
   op->geom = make_geom(g->dim, op->n, 0);
   helm_status s;
   if ((s = dalloc(&op->sc, nn * op_esz(op))) || (s = dalloc((void**)&op->mask, nn)) ||
-      (s = dalloc((void**)&op->alpha, nn * sizeof(double))) ||
+      (s = dalloc((void**)&op->alpha, nn * sizeof(double))) || (s = dalloc((void**)&op->code, nn)) ||
       (s = dalloc((void**)&op->red, 4096 * sizeof(double)))) {
     helm_destroy(op);
     return s;
   }
-  hipError_t e = hipHostMalloc((void**)&op->host, 4096 * sizeof(double), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&op->host, 4096 * sizeof(double), hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&op->host_dev, op->host, 0);
   if (e != hipSuccess) {
+    if (!op->host_dev && op->host) (void)hipHostFree(op->host);
     op->host = nullptr;
     helm_destroy(op);
     return hip_fail(e, "hipHostMalloc");
@@ -163,6 +165,7 @@ helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, con
     helm_destroy(op);
     return hip_fail(e, "helm_setup: mask copy");
   }
+  build_codes(op->geom, op->mask, op->code, st);
   if ((s = sync_stream(st, "helm_setup"))) {
     helm_destroy(op);
     return s;
@@ -187,6 +190,7 @@ void helm_destroy(helm_op op) {
   coarse_release(op);
   dfree(op->sc);
   dfree(op->mask);
+  dfree(op->code);
   dfree(op->alpha);
   dfree(op->red);
   if (op->host) (void)hipHostFree(op->host);
@@ -202,8 +206,8 @@ helm_status helm_apply(helm_op op, const void* x, void* y, void* stream) {
   if (!op || !x || !y) return fail(HELM_E_INVAL, "helm_apply: NULL argument");
   if (x == y) return fail(HELM_E_INVAL, "helm_apply: x and y alias");
   hipStream_t st = (hipStream_t)stream;
-  if (op->dt == HELM_C128) stencil_apply<double>(op->geom, op->sc, op->mask, x, y, st);
-  else stencil_apply<float>(op->geom, op->sc, op->mask, x, y, st);
+  if (op->dt == HELM_C128) stencil_apply<double>(op->geom, op->sc, op->code, x, y, st);
+  else stencil_apply<float>(op->geom, op->sc, op->code, x, y, st);
   return launch_check("helm_apply");
 }
 

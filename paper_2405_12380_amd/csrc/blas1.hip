@@ -73,72 +73,58 @@ void nrm2_part(size_t n, const void* x, double* part, hipStream_t st) {
 }
 
 // ---- multi-dot --------------------------------------------------------------
-// Each thread keeps E elements of w in registers; for every basis vector the
-// 64-lane partial is formed with shuffles and parked in LDS; one barrier at
-// the end combines the four wavefronts.  At most MD_CHUNK vectors per launch.
-static constexpr int MD_CHUNK = 64;
-
-static int md_elems(size_t n) {
-  if (n <= (size_t)1 << 20) return 1;
-  if (n <= (size_t)1 << 21) return 2;
-  if (n <= (size_t)1 << 22) return 4;
-  return 8;
-}
+// Workgroup b owns elements [b C, (b+1) C): w's chunk is staged once in LDS,
+// then each wavefront takes every fourth basis vector and streams its chunk
+// (C/64 independent coalesced loads per lane), reducing once per vector with
+// shuffles.  part[b][2 i + {0,1}] = sum over the chunk of conj(V_i) w.
+static int md_chunk(size_t n) { return n <= ((size_t)1 << 21) ? 512 : 2048; }
 int multidot_nblocks(size_t n) {
-  const int E = md_elems(n);
-  return (int)((n + 256 * (size_t)E - 1) / (256 * (size_t)E));
+  const size_t c = (size_t)md_chunk(n);
+  return (int)((n + c - 1) / c);
 }
 
-template <typename S, int E>
-__global__ __launch_bounds__(256) void k_multidot(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int i0,
-                                                  int nv, int stride, const cplx_t<S>* __restrict__ w,
-                                                  double* __restrict__ part) {
-  __shared__ double sh[4][2 * MD_CHUNK];
-  const size_t base = (size_t)blockIdx.x * 256 * E + threadIdx.x;
-  double2 wv[E];
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const size_t e = base + (size_t)k * 256;
-    wv[k] = e < n ? ldc(w, e) : czero();
+template <typename S, int CH>
+__global__ __launch_bounds__(256) void k_multidot(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
+                                                  const cplx_t<S>* __restrict__ w, double* __restrict__ part) {
+  __shared__ double2 ws[CH];
+  const size_t c0 = (size_t)blockIdx.x * CH;
+  for (int t = threadIdx.x; t < CH; t += 256) {
+    const size_t e = c0 + t;
+    ws[t] = e < n ? ldc(w, e) : czero();
   }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = 0; i < nv; ++i) {
-    const cplx_t<S>* Vi = V + (size_t)(i0 + i) * ldv;
+  const bool full = c0 + CH <= n;
+  for (int i = wave; i < nv; i += 4) {
+    const cplx_t<S>* Vi = V + (size_t)i * ldv + c0;
     double2 acc = czero();
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const size_t e = base + (size_t)k * 256;
-      if (e < n) acc = cadd(acc, cconjmul(ldc(Vi, e), wv[k]));
+      for (int t = 0; t < CH / 64; ++t) acc = cadd(acc, cconjmul(ldc(Vi, lane + 64 * t), ws[lane + 64 * t]));
+    } else {
+      for (int t = 0; t < CH / 64; ++t) {
+        const int el = lane + 64 * t;
+        if (c0 + el < n) acc = cadd(acc, cconjmul(ldc(Vi, el), ws[el]));
+      }
     }
     acc.x = wave_sum(acc.x);
     acc.y = wave_sum(acc.y);
     if (lane == 0) {
-      sh[wave][2 * i] = acc.x;
-      sh[wave][2 * i + 1] = acc.y;
+      part[(size_t)blockIdx.x * 2 * nv + 2 * i] = acc.x;
+      part[(size_t)blockIdx.x * 2 * nv + 2 * i + 1] = acc.y;
     }
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < 2 * nv; t += blockDim.x)
-    part[(size_t)blockIdx.x * stride + 2 * i0 + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
 }
 
 template <typename S>
 void multidot_part(size_t n, const void* V, size_t ldv, int nv, const void* w, double* part, hipStream_t st) {
   using C = cplx_t<S>;
   const int nb = multidot_nblocks(n);
-  const int E = md_elems(n);
   kprof_begin(st);
-  for (int i0 = 0; i0 < nv; i0 += MD_CHUNK) {
-    const int c = nv - i0 < MD_CHUNK ? nv - i0 : MD_CHUNK;
-#define MD_L(EE)                                                                                              \
-  hipLaunchKernelGGL((k_multidot<S, EE>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, i0, c, 2 * nv,       \
-                     (const C*)w, part)
-    if (E == 1) MD_L(1);
-    else if (E == 2) MD_L(2);
-    else if (E == 4) MD_L(4);
-    else MD_L(8);
-#undef MD_L
-  }
+  if (md_chunk(n) == 512)
+    hipLaunchKernelGGL((k_multidot<S, 512>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, (const C*)w, part);
+  else
+    hipLaunchKernelGGL((k_multidot<S, 2048>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, (const C*)w, part);
   kprof_end(KP_MULTIDOT, (double)n * 2 * sizeof(S) * (nv + 1), st);
 }
 
@@ -187,6 +173,93 @@ void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef,
     hipLaunchKernelGGL((k_multi_axpy<S, false>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, coef, sgn,
                        (const C*)base, (C*)out, part);
   kprof_end(KP_MULTIAXPY, (double)n * 2 * sizeof(S) * (nv + (base ? 1 : 0) + 1), st);
+}
+
+// ---- fused CGS pass: w' = w - V h and the partials of V^H w' --------------------
+// One element per thread.  The thread's values of every basis vector are
+// loaded once into registers (all loads independent: up to CG_MAX in flight),
+// w' = w - sum_i V_i h_i is formed and stored, and conj(V_i) w' is reduced
+// over the wavefront (butterfly) and then over the four wavefronts of the
+// block in a fixed order: one pass over V instead of two.
+constexpr int CG_MAX = 52;
+int cgs_fused_max_nv() { return CG_MAX; }
+int cgs_fused_nblocks(size_t n) { return (int)((n + 255) / 256); }
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
+                                                   const double* __restrict__ h, cplx_t<S>* __restrict__ w,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[4][2 * CG_MAX];
+  const size_t e = blockIdx.x * (size_t)256 + threadIdx.x;
+  const bool in = e < n;
+  double2 v[CG_MAX];
+#pragma unroll
+  for (int i = 0; i < CG_MAX; ++i) v[i] = (i < nv && in) ? ldc(V + (size_t)i * ldv, e) : czero();
+  double2 s = czero();
+#pragma unroll
+  for (int i = 0; i < CG_MAX; ++i)
+    if (i < nv) s = cadd(s, cmul(v[i], make_double2(h[2 * i], h[2 * i + 1])));
+  double2 wn = czero();
+  if (in) {
+    wn = csub(ldc(w, e), s);
+    stc(w, e, wn);
+    wn = ldc(w, e);  // the stored (possibly rounded) value enters the inner products
+  }
+  // d_i = conj(V_i) w' for all i, reduced over the wavefront by a
+  // reduce-scatter butterfly: three halving exchanges (xor 32, 16, 8) leave each
+  // lane 13 of the 104 real values summed over 8 lanes, three plain exchanges
+  // (xor 4, 2, 1) finish them; lane 8g then owns values [13g, 13g + 13).
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double x[2 * CG_MAX];
+#pragma unroll
+  for (int i = 0; i < CG_MAX; ++i) {
+    const double2 d = cconjmul(v[i], wn);  // v[i] = 0 beyond nv
+    x[2 * i] = d.x;
+    x[2 * i + 1] = d.y;
+  }
+  const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+  constexpr int H1 = CG_MAX, H2 = CG_MAX / 2, H3 = CG_MAX / 4;  // 52, 26, 13
+#pragma unroll
+  for (int q = 0; q < H1; ++q) {
+    const double keep = b5 ? x[H1 + q] : x[q], send = b5 ? x[q] : x[H1 + q];
+    x[q] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H2; ++q) {
+    const double keep = b4 ? x[H2 + q] : x[q], send = b4 ? x[q] : x[H2 + q];
+    x[q] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H3; ++q) {
+    const double keep = b3 ? x[H3 + q] : x[q], send = b3 ? x[q] : x[H3 + q];
+    x[q] = keep + __shfl_xor(send, 8, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < H3; ++q) {
+    double t = x[q];
+    t += __shfl_xor(t, 4, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 1, 64);
+    x[q] = t;
+  }
+  if ((lane & 7) == 0) {
+    const int g = 4 * b5 + 2 * b4 + b3;
+#pragma unroll
+    for (int q = 0; q < H3; ++q) sh[wave][H3 * g + q] = x[q];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * nv; t += 256)
+    part[(size_t)blockIdx.x * 2 * nv + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+}
+
+template <typename S>
+void cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  const int nb = cgs_fused_nblocks(n);
+  kprof_begin(st);
+  hipLaunchKernelGGL((k_cgs_fused<S>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, h, (C*)w, part);
+  // V once, w read and written
+  kprof_end(KP_CGS, (double)n * 2 * sizeof(S) * (nv + 2), st);
 }
 
 // ---- simple vector kernels ----------------------------------------------------
@@ -437,6 +510,7 @@ void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st) {
   template void multidot_part<S>(size_t, const void*, size_t, int, const void*, double*, hipStream_t);         \
   template void multi_axpy<S>(size_t, const void*, size_t, int, const double*, double, const void*, void*,     \
                               double*, hipStream_t);                                                           \
+  template void cgs_fused<S>(size_t, const void*, size_t, int, const double*, void*, double*, hipStream_t);    \
   template void scale_dev<S>(size_t, const void*, const double*, void*, hipStream_t);                          \
   template void scale_host<S>(size_t, const void*, double, void*, hipStream_t);                                \
   template void add_inplace<S>(size_t, const void*, void*, hipStream_t);                                       \

@@ -87,6 +87,57 @@ __global__ __launch_bounds__(256) void k_qt_part(size_t n, int r, const T* __res
     part[(size_t)blockIdx.x * 2 * r + e] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
 }
 
+// fp32 basis: lane l owns columns 2l and 2l+1 (one 8-byte load per row, a
+// wavefront reads a 512 B row of 128 columns in one instruction).
+template <typename S>
+__global__ __launch_bounds__(256) void k_qt_part32(size_t n, int r, const float* __restrict__ Q,
+                                                   const cplx_t<S>* __restrict__ x, size_t rows_per_block,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t i0 = (size_t)blockIdx.x * rows_per_block;
+  const size_t i1 = min(n, i0 + rows_per_block);
+  const int c0 = 2 * lane;
+  const bool pair = c0 + 1 < r, single = c0 < r;
+  double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
+  auto load2 = [&](size_t ii) -> float2 {
+    if (pair && ((r & 1) == 0)) return *reinterpret_cast<const float2*>(Q + ii * r + c0);
+    return make_float2(single ? Q[ii * r + c0] : 0.f, pair ? Q[ii * r + c0 + 1] : 0.f);
+  };
+  size_t i = i0 + wave;
+  for (; i + 12 < i1; i += 16) {
+    float2 q[4];
+    double2 xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xv[u] = ldc(x, i + 4 * u);
+      q[u] = load2(i + 4 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0r += (double)q[u].x * xv[u].x;
+      a0i += (double)q[u].x * xv[u].y;
+      a1r += (double)q[u].y * xv[u].x;
+      a1i += (double)q[u].y * xv[u].y;
+    }
+  }
+  for (; i < i1; i += 4) {
+    const double2 xv = ldc(x, i);
+    const float2 q = load2(i);
+    a0r += (double)q.x * xv.x;
+    a0i += (double)q.x * xv.y;
+    a1r += (double)q.y * xv.x;
+    a1i += (double)q.y * xv.y;
+  }
+  sh[wave][2 * c0] = a0r;
+  sh[wave][2 * c0 + 1] = a0i;
+  sh[wave][2 * c0 + 2] = a1r;
+  sh[wave][2 * c0 + 3] = a1i;
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * r; e += blockDim.x)
+    part[(size_t)blockIdx.x * 2 * r + e] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
+}
+
 // c = Ainv y: block j computes row j (r x r complex, row-major)
 __global__ __launch_bounds__(64) void k_ainv(int r, const double* __restrict__ Ainv, const double* __restrict__ y,
                                              double* __restrict__ c) {
@@ -166,6 +217,67 @@ __global__ __launch_bounds__(256) void k_skinny(size_t n, int r, const T* __rest
         } else {
           stc(z, ii, mask[ii] ? czero() : cscale(y, sc));
         }
+      }
+    }
+  }
+}
+
+// fp32 basis version of k_skinny: lane l owns columns 2l, 2l+1 (one 8-byte
+// load per row); same butterfly over four rows.
+template <typename S, int MODE>
+__global__ __launch_bounds__(256) void k_skinny32(size_t n, int r, const float* __restrict__ Q,
+                                                  const double* __restrict__ c, cplx_t<S>* __restrict__ z,
+                                                  const uint8_t* __restrict__ mask, const double* __restrict__ scal) {
+  const int lane = threadIdx.x & 63;
+  const size_t wave_g = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6;
+  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  const int c0 = 2 * lane;
+  const bool pair = c0 + 1 < r, single = c0 < r;
+  const double2 cc0 = single ? make_double2(c[2 * c0], c[2 * c0 + 1]) : czero();
+  const double2 cc1 = pair ? make_double2(c[2 * c0 + 2], c[2 * c0 + 3]) : czero();
+  double sc = 1.0;
+  if (MODE == SK_SYNTH) sc = scal[0];
+  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+  for (size_t i = wave_g * 4; i < n; i += nwaves * 4) {
+    double v[8];
+#pragma unroll
+    for (int rho = 0; rho < 4; ++rho) {
+      const size_t ii = i + rho;
+      float2 q = make_float2(0.f, 0.f);
+      if (ii < n) {
+        if (pair && ((r & 1) == 0)) q = *reinterpret_cast<const float2*>(Q + ii * r + c0);
+        else q = make_float2(single ? Q[ii * r + c0] : 0.f, pair ? Q[ii * r + c0 + 1] : 0.f);
+      }
+      v[2 * rho] = (double)q.x * cc0.x + (double)q.y * cc1.x;
+      v[2 * rho + 1] = (double)q.x * cc0.y + (double)q.y * cc1.y;
+    }
+    double w4[4];
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const double send = v[4 * (1 - b5) + qq];
+      w4[qq] = v[4 * b5 + qq] + __shfl_xor(send, 32, 64);
+    }
+    double w2[2];
+#pragma unroll
+    for (int qq = 0; qq < 2; ++qq) {
+      const double send = w4[2 * (1 - b4) + qq];
+      w2[qq] = w4[2 * b4 + qq] + __shfl_xor(send, 16, 64);
+    }
+    double w1;
+    {
+      const double send = w2[1 - b3];
+      w1 = w2[b3] + __shfl_xor(send, 8, 64);
+    }
+    w1 += __shfl_xor(w1, 4, 64);
+    w1 += __shfl_xor(w1, 2, 64);
+    w1 += __shfl_xor(w1, 1, 64);
+    const double other = __shfl_xor(w1, 8, 64);
+    if ((lane & 15) == 0) {
+      const size_t ii = i + 2 * b5 + b4;
+      if (ii < n) {
+        const double2 y = make_double2(w1, other);
+        if (MODE == SK_ADD) stc(z, ii, cadd(ldc(z, ii), y));
+        else stc(z, ii, mask[ii] ? czero() : cscale(y, sc));
       }
     }
   }
@@ -254,7 +366,11 @@ void qt_partials(size_t n, int r, const T* Q, const void* x, double* part, hipSt
   const int nb = qt_nblocks(n);
   const size_t rpb = (n + nb - 1) / nb;
   kprof_begin(st);
-  hipLaunchKernelGGL((k_qt_part<T, S>), dim3(nb), dim3(256), 0, st, n, r, Q, (const cplx_t<S>*)x, rpb, part);
+  if (sizeof(T) == sizeof(float))
+    hipLaunchKernelGGL((k_qt_part32<S>), dim3(nb), dim3(256), 0, st, n, r, (const float*)Q, (const cplx_t<S>*)x, rpb,
+                       part);
+  else
+    hipLaunchKernelGGL((k_qt_part<T, S>), dim3(nb), dim3(256), 0, st, n, r, Q, (const cplx_t<S>*)x, rpb, part);
   kprof_end(KP_QT, (double)n * (sizeof(T) * r + 2 * sizeof(S)), st);
 }
 
@@ -266,12 +382,21 @@ void skinny_apply(size_t n, int r, const T* Q, const double* c, void* z, const u
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
   kprof_begin(st);
-  if (synth)
+  if (sizeof(T) == sizeof(float)) {
+    const float* Qf = (const float*)Q;
+    if (synth)
+      hipLaunchKernelGGL((k_skinny32<S, SK_SYNTH>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Qf, c, (cplx_t<S>*)z,
+                         mask, scal);
+    else
+      hipLaunchKernelGGL((k_skinny32<S, SK_ADD>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Qf, c, (cplx_t<S>*)z,
+                         mask, scal);
+  } else if (synth) {
     hipLaunchKernelGGL((k_skinny<T, S, SK_SYNTH>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Q, c, (cplx_t<S>*)z,
                        mask, scal);
-  else
+  } else {
     hipLaunchKernelGGL((k_skinny<T, S, SK_ADD>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Q, c, (cplx_t<S>*)z, mask,
                        scal);
+  }
   // Q once; z read and written (ADD) or du written and the mask read (SYNTH)
   kprof_end(KP_SKINNY, (double)n * (sizeof(T) * r + (synth ? 2 * sizeof(S) + 1 : 4 * sizeof(S))), st);
 }
@@ -279,6 +404,8 @@ template void skinny_apply<double, double>(size_t, int, const double*, const dou
                                            const double*, int, hipStream_t);
 template void skinny_apply<float, float>(size_t, int, const float*, const double*, void*, const uint8_t*,
                                          const double*, int, hipStream_t);
+template void skinny_apply<float, double>(size_t, int, const float*, const double*, void*, const uint8_t*,
+                                          const double*, int, hipStream_t);
 
 // ---- setup -----------------------------------------------------------------------
 void coarse_release(helm_op_s* op) {
@@ -296,7 +423,7 @@ void coarse_release(helm_op_s* op) {
 }
 
 template <typename TT, typename S>
-static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, hipStream_t st) {
+static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32, hipStream_t st) {
   Coarse& c = op->coarse;
   const size_t n = op->nn;
   helm_status s;
@@ -360,9 +487,14 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, hipStream
   if ((s = sync_stream(st, "coarse: pass 2"))) return s;
   if (((int*)op->host)[1] != 0 || ((int*)op->host)[0] != r)
     return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", ((int*)op->host)[0], r);
-  // stored basis (dtype precision); Q <- stored values
-  if ((s = c.Q.ensure(n * (size_t)r * sizeof(TT)))) return s;
-  hipLaunchKernelGGL((k_round_q<TT>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (TT*)c.Q.ptr);
+  // stored basis (fp32 when requested or for C64, else fp64); Q <- stored values
+  c.q_f32 = qf32 || sizeof(TT) == sizeof(float);
+  if ((s = c.Q.ensure(n * (size_t)r * (c.q_f32 ? sizeof(float) : sizeof(double))))) return s;
+  if (c.q_f32)
+    hipLaunchKernelGGL((k_round_q<float>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (float*)c.Q.ptr);
+  else
+    hipLaunchKernelGGL((k_round_q<double>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q,
+                       (double*)c.Q.ptr);
   // B = (L - diag(Re s)) Q into W2; A_c = Q^T B - i Q^T diag(Im s) Q
   double* Bm = Q1;
   hipLaunchKernelGGL((k_batched_lap<S>), dim3(ew_grid(n * r)), dim3(256), 0, st, op->geom, r, Q,
@@ -391,13 +523,15 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, hipStream
   return launch_check("coarse setup");
 }
 
-helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, hipStream_t st) {
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, hipStream_t st) {
   Coarse& c = op->coarse;
-  if (c.valid && c.net_serial == don_serial(net) && c.p_used == p_used && c.ksq_version == op->ksq_version)
+  const bool want_f32 = q_fp32 || op->dt == HELM_C64;
+  if (c.valid && c.net_serial == don_serial(net) && c.p_used == p_used && c.ksq_version == op->ksq_version &&
+      c.q_f32 == want_f32)
     return HELM_OK;
   c.valid = false;
-  helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, st)
-                                      : coarse_build<float, float>(op, net, p_used, st);
+  helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, q_fp32, st)
+                                      : coarse_build<float, float>(op, net, p_used, true, st);
   if (s) return s;
   c.net_serial = don_serial(net);
   c.ksq_version = op->ksq_version;
@@ -414,10 +548,12 @@ helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t s
   double* part = (double*)c.qpart.ptr;
   double* y = op->red + 1024;
   double* cc = op->red + 2048;
-  qt_partials<S, S>(n, r, (const S*)c.Q.ptr, r1, part, st);
-  reduce_rows(part, nb, 2 * (size_t)r, y, 1.0, st);
+  if (c.q_f32) qt_partials<float, S>(n, r, (const float*)c.Q.ptr, r1, part, st);
+  else qt_partials<double, S>(n, r, (const double*)c.Q.ptr, r1, part, st);
+  reduce_cols(part, nb, 2 * r, y, st);
   hipLaunchKernelGGL(k_ainv, dim3(r), dim3(64), 0, st, r, (const double*)c.Ainv.ptr, y, cc);
-  skinny_apply<S, S>(n, r, (const S*)c.Q.ptr, cc, z, op->mask, nullptr, 0, st);
+  if (c.q_f32) skinny_apply<float, S>(n, r, (const float*)c.Q.ptr, cc, z, op->mask, nullptr, 0, st);
+  else skinny_apply<double, S>(n, r, (const double*)c.Q.ptr, cc, z, op->mask, nullptr, 0, st);
   return launch_check("coarse correction");
 }
 

@@ -2,7 +2,7 @@
 // (CGS2 coefficients, complex Givens rotations, residual estimate) and the
 // upper-triangular back-solve.  O(m) / O(m^2) work in fp64, one thread: the
 // host never touches H, so a cycle needs no host round trip except the
-// convergence flag.
+// convergence flag.  Restart lengths up to 1000 are supported.
 #include "common.h"
 #include "internal.h"
 
@@ -19,62 +19,131 @@ __device__ static inline void H_set(double* H, int m, int i, int j, double2 v) {
 }
 __device__ static inline double cabs2(double2 a) { return hypot(a.x, a.y); }
 
-__global__ void k_arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1,
-                                 const double* h2, const double* nrm2, GmState* gs) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = 0; i <= j; ++i)
-    H_set(H, m, i, j, make_double2(h1[2 * i] + h2[2 * i], h1[2 * i + 1] + h2[2 * i + 1]));
-  const double hn = sqrt(nrm2[0]);
-  gs->hn = hn;
-  gs->inv_hn = hn != 0.0 ? 1.0 / hn : 0.0;
-  // previous rotations G_i = [[c, s], [-conj(s), c]] on rows (i, i+1)
-  for (int i = 0; i < j; ++i) {
-    const double2 a = H_at(H, m, i, j), b = H_at(H, m, i + 1, j);
-    const double c = cs[i];
-    const double2 s = make_double2(sn[2 * i], sn[2 * i + 1]);
-    const double2 sconj = make_double2(s.x, -s.y);
-    H_set(H, m, i, j, cadd(cscale(a, c), cmul(s, b)));
-    H_set(H, m, i + 1, j, csub(cscale(b, c), cmul(sconj, a)));
+// One wavefront: the new column (CGS2 coefficients h1 + h2) and the previous
+// rotations are staged in LDS, lane 0 applies the rotations (inherently
+// sequential, now on LDS), and the column is written back in parallel.
+__global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn,
+                                                       const double* h1, const double* h2, const double* nrm2,
+                                                       GmState* gs, GmState* ghost) {
+  __shared__ double col[2 * 1002];
+  __shared__ double rc[1001], rs[2 * 1001];
+  const int l = threadIdx.x;
+  for (int i = l; i <= j; i += 64) {
+    col[2 * i] = h1[2 * i] + h2[2 * i];
+    col[2 * i + 1] = h1[2 * i + 1] + h2[2 * i + 1];
   }
-  const double2 a = H_at(H, m, j, j);
-  const double b = hn;
-  double c;
-  double2 s;
-  if (b == 0.0) {
-    c = 1.0;
-    s = czero();
-  } else if (a.x == 0.0 && a.y == 0.0) {
-    c = 0.0;
-    s = make_double2(1.0, 0.0);
-  } else {
-    const double aa = cabs2(a);
-    const double nu = sqrt(aa * aa + b * b);
-    c = aa / nu;
-    s = cscale(make_double2(a.x / aa, a.y / aa), b / nu);
+  for (int i = l; i < j; i += 64) {
+    rc[i] = cs[i];
+    rs[2 * i] = sn[2 * i];
+    rs[2 * i + 1] = sn[2 * i + 1];
   }
-  cs[j] = c;
-  sn[2 * j] = s.x;
-  sn[2 * j + 1] = s.y;
-  H_set(H, m, j, j, cadd(cscale(a, c), cscale(s, b)));
-  H_set(H, m, j + 1, j, czero());
-  const double2 gj = make_double2(g[2 * j], g[2 * j + 1]);
-  const double2 gn = cmul(make_double2(-s.x, s.y), gj);  // -conj(s) g_j
-  g[2 * (j + 1)] = gn.x;
-  g[2 * (j + 1) + 1] = gn.y;
-  g[2 * j] = c * gj.x;
-  g[2 * j + 1] = c * gj.y;
-  gs->gabs = cabs2(gn);
-  gs->flag = (isfinite(hn) && isfinite(gs->gabs)) ? 0 : -5;
+  __syncthreads();
+  if (l == 0) {
+    const double hn = sqrt(nrm2[0]);
+    gs->hn = hn;
+    gs->inv_hn = hn != 0.0 ? 1.0 / hn : 0.0;
+    // previous rotations G_i = [[c, s], [-conj(s), c]] on rows (i, i+1)
+    for (int i = 0; i < j; ++i) {
+      const double2 a = make_double2(col[2 * i], col[2 * i + 1]);
+      const double2 b = make_double2(col[2 * i + 2], col[2 * i + 3]);
+      const double c = rc[i];
+      const double2 s = make_double2(rs[2 * i], rs[2 * i + 1]);
+      const double2 sconj = make_double2(s.x, -s.y);
+      const double2 na = cadd(cscale(a, c), cmul(s, b));
+      const double2 nb = csub(cscale(b, c), cmul(sconj, a));
+      col[2 * i] = na.x;
+      col[2 * i + 1] = na.y;
+      col[2 * i + 2] = nb.x;
+      col[2 * i + 3] = nb.y;
+    }
+    const double2 a = make_double2(col[2 * j], col[2 * j + 1]);
+    const double b = hn;
+    double c;
+    double2 s;
+    if (b == 0.0) {
+      c = 1.0;
+      s = czero();
+    } else if (a.x == 0.0 && a.y == 0.0) {
+      c = 0.0;
+      s = make_double2(1.0, 0.0);
+    } else {
+      const double aa = cabs2(a);
+      const double nu = sqrt(aa * aa + b * b);
+      c = aa / nu;
+      s = cscale(make_double2(a.x / aa, a.y / aa), b / nu);
+    }
+    cs[j] = c;
+    sn[2 * j] = s.x;
+    sn[2 * j + 1] = s.y;
+    const double2 hjj = cadd(cscale(a, c), cscale(s, b));
+    col[2 * j] = hjj.x;
+    col[2 * j + 1] = hjj.y;
+    col[2 * (j + 1)] = 0.0;
+    col[2 * (j + 1) + 1] = 0.0;
+    const double2 gj = make_double2(g[2 * j], g[2 * j + 1]);
+    const double2 gn = cmul(make_double2(-s.x, s.y), gj);  // -conj(s) g_j
+    g[2 * (j + 1)] = gn.x;
+    g[2 * (j + 1) + 1] = gn.y;
+    g[2 * j] = c * gj.x;
+    g[2 * j + 1] = c * gj.y;
+    gs->gabs = cabs2(gn);
+    gs->flag = (isfinite(hn) && isfinite(gs->gabs)) ? 0 : -5;
+    gs->step = j;
+    // the host reads this copy after an event recorded behind the kernel
+    ghost->gabs = gs->gabs;
+    ghost->hn = hn;
+    ghost->inv_hn = gs->inv_hn;
+    ghost->flag = gs->flag;
+    ghost->step = j;
+    __threadfence_system();
+  }
+  __syncthreads();
+  for (int i = l; i <= j + 1; i += 64) H_set(H, m, i, j, make_double2(col[2 * i], col[2 * i + 1]));
 }
 
-__global__ void k_backsolve(int k, int m, const double* H, const double* g, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Back substitution H[:k,:k] y = g, one wavefront: row i's dot product is
+// split over lanes and summed with shuffles, lane 0 forms y_i.  y lives in LDS;
+// the upper triangle of H is staged in LDS too when it fits (k <= 76, packed
+// rows), otherwise it is read from global memory.
+constexpr int BS_LDS_MAX = 76;
+__device__ static inline int tri(int k, int i, int c) { return i * k - (i * (i - 1)) / 2 + (c - i); }
+
+__global__ __launch_bounds__(64) void k_backsolve(int k, int m, const double* H, const double* g, double* y) {
+  extern __shared__ double lds[];
+  double* ys = lds;           // 2k
+  double* hl = lds + 2 * k;   // packed upper triangle, k(k+1)/2 complex
+  const int l = threadIdx.x;
+  const bool staged = k <= BS_LDS_MAX;
+  if (staged)
+    for (int i = 0; i < k; ++i)
+      for (int c = i + l; c < k; c += 64) {
+        const double2 v = H_at(H, m, i, c);
+        const int o = tri(k, i, c);
+        hl[2 * o] = v.x;
+        hl[2 * o + 1] = v.y;
+      }
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
     double2 acc = czero();
-    for (int l = i + 1; l < k; ++l) acc = cadd(acc, cmul(H_at(H, m, i, l), make_double2(y[2 * l], y[2 * l + 1])));
-    const double2 v = cdiv(csub(make_double2(g[2 * i], g[2 * i + 1]), acc), H_at(H, m, i, i));
-    y[2 * i] = v.x;
-    y[2 * i + 1] = v.y;
+    for (int c = i + 1 + l; c < k; c += 64) {
+      const int o = tri(k, i, c);
+      const double2 h = staged ? make_double2(hl[2 * o], hl[2 * o + 1]) : H_at(H, m, i, c);
+      acc = cadd(acc, cmul(h, make_double2(ys[2 * c], ys[2 * c + 1])));
+    }
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (l == 0) {
+      const int o = tri(k, i, i);
+      const double2 hii = staged ? make_double2(hl[2 * o], hl[2 * o + 1]) : H_at(H, m, i, i);
+      const double2 v = cdiv(csub(make_double2(g[2 * i], g[2 * i + 1]), acc), hii);
+      ys[2 * i] = v.x;
+      ys[2 * i + 1] = v.y;
+    }
+    __syncthreads();
+  }
+  for (int i = l; i < k; i += 64) {
+    y[2 * i] = ys[2 * i];
+    y[2 * i + 1] = ys[2 * i + 1];
   }
 }
 
@@ -85,11 +154,12 @@ __global__ void k_gmres_init(double beta, double* g, int m) {
 }
 
 void arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1, const double* h2,
-                    const double* nrm2, GmState* gs, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, st, j, m, H, g, cs, sn, h1, h2, nrm2, gs);
+                    const double* nrm2, GmState* gs, GmState* ghost, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, st, j, m, H, g, cs, sn, h1, h2, nrm2, gs, ghost);
 }
 void gmres_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, st, k, m, H, g, y);
+  const size_t lds = sizeof(double) * 2 * ((size_t)k + (k <= BS_LDS_MAX ? (size_t)k * (k + 1) / 2 : 0));
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), lds, st, k, m, H, g, y);
 }
 void gmres_init(double beta, double* g, int m, hipStream_t st) {
   hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, st, beta, g, m);

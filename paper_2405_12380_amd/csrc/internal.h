@@ -18,22 +18,29 @@ StencilGeom make_geom(int dim, const int n[3], int zb);
 int stencil_nblocks(const StencilGeom& g);
 
 // ---- stencil.hip ----------------------------------------------------------
+// The stencil kernels take the per-node neighbour code built by build_codes
+// (bit 0 = masked node, bits 1..6 = absent x-, x+, y-, y+, z-, z+ neighbour).
+void build_codes(const StencilGeom& g, const uint8_t* mask, uint8_t* code, hipStream_t st);
 template <typename S>
-void stencil_apply(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* x, void* y,
+void stencil_apply(const StencilGeom& g, const void* sc, const uint8_t* code, const void* x, void* y,
                    hipStream_t st);
 // r = f - A u; part[stencil_nblocks(g)] receives per-block partials of ||r||^2
 template <typename S>
-void stencil_resid(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* f, const void* u,
+void stencil_resid(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, const void* u,
                    void* r, double* part, hipStream_t st);
 template <typename S>
-void stencil_jacobi(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* f, const void* u,
+void stencil_jacobi(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, const void* u,
                     void* unew, double omega, hipStream_t st);
 template <typename S>
-void stencil_rbgs(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* f, void* u,
+void stencil_rbgs(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* u,
                   double omega, hipStream_t st);
 template <typename S>
 void jacobi_from_zero(size_t n, double dsum, const void* sc, const uint8_t* mask, const void* f, void* z,
                       double omega, hipStream_t st);
+// two Jacobi sweeps on A z = f from z = 0 in one pass (z must not alias f)
+template <typename S>
+void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* z, double omega,
+                       hipStream_t st);
 template <typename S>
 void build_s(size_t n, const double* ksq, const double* alpha, void* sc, hipStream_t st);
 
@@ -54,6 +61,12 @@ void multidot_part(size_t n, const void* V, size_t ldv, int nv, const void* w, d
 template <typename S>
 void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef, double sgn, const void* base,
                 void* out, double* part, hipStream_t st);
+// Fused CGS pass for nv <= cgs_fused_max_nv(): w <- w - sum_i V_i h_i, and
+// part[b][2i..] = per-block partials of conj(V_i) w_new (cgs_fused_nblocks(n) blocks)
+int cgs_fused_max_nv();
+int cgs_fused_nblocks(size_t n);
+template <typename S>
+void cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st);
 // y = x * scal[0] (real scale on device)
 template <typename S>
 void scale_dev(size_t n, const void* x, const double* scal, void* y, hipStream_t st);
@@ -96,12 +109,13 @@ struct GmState {
   double hn;    // ||w|| before normalisation
   double inv_hn;
   int flag;
-  int pad;
+  int step;     // Arnoldi step j this record belongs to
 };
 // H: (m+1) x m complex column-major (H + 2*(j*(m+1) + i)); g: m+1 complex; cs: m real; sn: m complex
-// h1, h2: reduced CGS passes (j+1 complex each); nrm2: ||w||^2
+// h1, h2: reduced CGS passes (j+1 complex each); nrm2: ||w||^2; ghost: a second copy of
+// the status record in host-mapped memory (device address of pinned host memory)
 void arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1, const double* h2,
-                    const double* nrm2, GmState* gs, hipStream_t st);
+                    const double* nrm2, GmState* gs, GmState* ghost, hipStream_t st);
 void gmres_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t st);
 void gmres_init(double beta, double* g, int m, hipStream_t st);
 

@@ -34,6 +34,7 @@ struct Coarse {
   int p_used = 0;
   int ksq_version = -1;
   bool valid = false;
+  bool q_f32 = false;  // basis stored in fp32
   int rank = 0;
   double cond_est = 0.0;
   double setup_ms = 0.0;
@@ -57,9 +58,11 @@ struct helm_op_s {
   helm::StencilGeom geom{};
   void* sc = nullptr;        // s = k^2 (1 + i alpha), complex in the dtype's precision
   uint8_t* mask = nullptr;   // scatterer indicator
+  uint8_t* code = nullptr;   // per-node neighbour code for the stencil kernels
   double* alpha = nullptr;   // sponge profile (kept to rebuild s after helm_set_ksq)
   double* red = nullptr;     // small reduced results (device, 4096 doubles)
   double* host = nullptr;    // pinned host mirror for scalar read-backs (4096 doubles)
+  double* host_dev = nullptr;  // the same pinned buffer as seen from the device
   int ksq_version = 0;
   helm::Buffer tmp;          // one field: Jacobi ping-pong
   helm::Buffer part;         // reduction partials
@@ -84,7 +87,7 @@ helm_status don_full(don_s* net, helm_op_s* op, const void* r, double k, void* d
 helm_status don_trunk(don_s* net, helm_op_s* op, void* out, hipStream_t st);
 
 // ---- coarse space (coarse.hip) ----
-helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, hipStream_t st);
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, hipStream_t st);
 template <typename S>
 helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st);  // z += Q A_c^-1 Q^T r1
 void coarse_release(helm_op_s* op);
@@ -96,7 +99,7 @@ helm_status residual_norm(helm_op_s* op, const void* f, const void* u, void* r, 
   const int nb = stencil_nblocks(op->geom);
   helm_status s = op_part(op, (size_t)nb, &part);
   if (s) return s;
-  stencil_resid<S>(op->geom, op->sc, op->mask, f, u, r, part, st);
+  stencil_resid<S>(op->geom, op->sc, op->code, f, u, r, part, st);
   if (norm) {
     reduce_cols(part, nb, 1, op->red, st);
     hipError_t e = hipMemcpyAsync(op->host, op->red, sizeof(double), hipMemcpyDeviceToHost, st);
@@ -127,7 +130,7 @@ template <typename S>
 helm_status relax(helm_op_s* op, int kind, double omega, int sweeps, const void* f, void* u, hipStream_t st) {
   if (sweeps <= 0) return HELM_OK;
   if (kind == HELM_RBGS) {
-    for (int k = 0; k < sweeps; ++k) stencil_rbgs<S>(op->geom, op->sc, op->mask, f, u, omega, st);
+    for (int k = 0; k < sweeps; ++k) stencil_rbgs<S>(op->geom, op->sc, op->code, f, u, omega, st);
     return launch_check("rbgs");
   }
   helm_status s = op->tmp.ensure(op->nn * op_esz(op));
@@ -135,7 +138,7 @@ helm_status relax(helm_op_s* op, int kind, double omega, int sweeps, const void*
   void* a = u;
   void* b = op->tmp.ptr;
   for (int k = 0; k < sweeps; ++k) {
-    stencil_jacobi<S>(op->geom, op->sc, op->mask, f, a, b, omega, st);
+    stencil_jacobi<S>(op->geom, op->sc, op->code, f, a, b, omega, st);
     void* t = a;
     a = b;
     b = t;

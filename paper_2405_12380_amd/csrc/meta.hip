@@ -31,6 +31,21 @@ struct Carve {
   static size_t need(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 };
 
+// Two timing-free events, destroyed with the scope.
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  EventPair() {
+    for (auto& x : e)
+      if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) x = nullptr;
+  }
+  ~EventPair() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  bool ok() const { return e[0] && e[1]; }
+  hipEvent_t operator[](int i) const { return e[i]; }
+};
+
 struct MetaCtx {
   const meta_opts* o;
   don_s* net;
@@ -47,22 +62,26 @@ helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* 
   helm_status s;
   if (o->n_r > 0) {
     if (o->smoother == HELM_JACOBI) {
-      jacobi_from_zero<S>(n, op->geom.dsum, op->sc, op->mask, v, z, o->omega, st);
-      if (o->n_r > 1) {
+      if (o->n_r == 1) {
+        jacobi_from_zero<S>(n, op->geom.dsum, op->sc, op->mask, v, z, o->omega, st);
+      } else {
+        // first two sweeps fused; the remaining n_r - 2 ping-pong through op->tmp
+        // so that the last one lands in z
         if ((s = op->tmp.ensure(n * op_esz(op)))) return s;
-        void* a = z;
-        void* b = op->tmp.ptr;
-        for (int k = 1; k < o->n_r; ++k) {
-          stencil_jacobi<S>(op->geom, op->sc, op->mask, v, a, b, o->omega, st);
+        const int rest = o->n_r - 2;
+        void* a = (rest & 1) ? op->tmp.ptr : z;
+        void* b = (rest & 1) ? z : op->tmp.ptr;
+        jacobi2_from_zero<S>(op->geom, op->sc, op->code, v, a, o->omega, st);
+        for (int k = 0; k < rest; ++k) {
+          stencil_jacobi<S>(op->geom, op->sc, op->code, v, a, b, o->omega, st);
           void* t = a;
           a = b;
           b = t;
         }
-        if (a != z) copy_vec<S>(n, a, z, st);
       }
     } else {
       zero_vec<S>(n, z, st);
-      for (int k = 0; k < o->n_r; ++k) stencil_rbgs<S>(op->geom, op->sc, op->mask, v, z, o->omega, st);
+      for (int k = 0; k < o->n_r; ++k) stencil_rbgs<S>(op->geom, op->sc, op->code, v, z, o->omega, st);
     }
   } else {
     zero_vec<S>(n, z, st);
@@ -70,7 +89,7 @@ helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* 
   if (c.net) {
     double* part;
     if ((s = op_part(op, (size_t)stencil_nblocks(op->geom), &part))) return s;
-    stencil_resid<S>(op->geom, op->sc, op->mask, v, z, c.r1, part, st);
+    stencil_resid<S>(op->geom, op->sc, op->code, v, z, c.r1, part, st);
     if ((s = coarse_correct<S>(op, c.r1, z, st))) return s;
   }
   return launch_check("precond");
@@ -112,11 +131,20 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   auto Vj = [&](int j) { return (void*)(V + (size_t)j * fld); };
 
   const int mdb = multidot_nblocks(n), rdb = red_nblocks(n), stb = stencil_nblocks(op->geom);
+  const int cfb = cgs_fused_nblocks(n);
   size_t pneed = (size_t)mdb * 2 * (m + 1);
+  const size_t cneed = (size_t)cfb * 2 * (m + 1 < cgs_fused_max_nv() ? m + 1 : cgs_fused_max_nv());
+  if (cneed > pneed) pneed = cneed;
   if ((size_t)rdb > pneed) pneed = rdb;
   if ((size_t)stb > pneed) pneed = stb;
   double* part;
   if ((s = op_part(op, pneed, &part))) return s;
+
+  // status records land directly in pinned host memory (written by the kernel)
+  GmState* slot[2] = {(GmState*)(op->host + 64), (GmState*)(op->host + 128)};
+  GmState* slot_dev[2] = {(GmState*)(op->host_dev + 64), (GmState*)(op->host_dev + 128)};
+  EventPair ev;
+  if (!ev.ok()) return fail(HELM_E_HIP, "gmres: event creation failed");
 
   double fn;
   if ((s = vec_norm<S>(op, f, &fn, st))) return s;
@@ -127,7 +155,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   double beta = 0.0;
   for (;;) {
     // r = f - A u into V_0, beta = ||r||
-    stencil_resid<S>(op->geom, op->sc, op->mask, f, u, Vj(0), part, st);
+    stencil_resid<S>(op->geom, op->sc, op->code, f, u, Vj(0), part, st);
     matvecs++;
     reduce_cols(part, stb, 1, nrm, st);
     if ((s = read_host(op, nrm, sizeof(double), st, "gmres: residual"))) return s;
@@ -144,37 +172,57 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
     if (count >= o->max_iters) break;
     scale_host<S>(n, Vj(0), 1.0 / beta, Vj(0), st);
     gmres_init(beta, g, m, st);
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
+    // One Arnoldi step: z = M v_j, w = A z into V_{j+1}, CGS2, Givens, scale.
+    // Its status record is copied to pinned slot j & 1 and an event marks it.
+    auto enqueue_step = [&](int j) -> helm_status {
       const void* zj = Vj(j);
       if (c.use_M) {
-        if ((s = precond_apply<S>(op, c, Vj(j), z, st))) return s;
+        helm_status e2 = precond_apply<S>(op, c, Vj(j), z, st);
+        if (e2) return e2;
         zj = z;
-        papps++;
       }
       void* w = Vj(j + 1);
-      stencil_apply<S>(op->geom, op->sc, op->mask, zj, w, st);
-      matvecs++;
-      // CGS2: two classical Gram-Schmidt passes
+      stencil_apply<S>(op->geom, op->sc, op->code, zj, w, st);
       multidot_part<S>(n, V, ldv, j + 1, w, part, st);
       reduce_cols(part, mdb, 2 * (j + 1), h1, st);
-      multi_axpy<S>(n, V, ldv, j + 1, h1, -1.0, w, w, nullptr, st);
-      multidot_part<S>(n, V, ldv, j + 1, w, part, st);
-      reduce_cols(part, mdb, 2 * (j + 1), h2, st);
+      if (j + 1 <= cgs_fused_max_nv()) {
+        // first projection and second inner products in one pass over V
+        cgs_fused<S>(n, V, ldv, j + 1, h1, w, part, st);
+        reduce_cols(part, cfb, 2 * (j + 1), h2, st);
+      } else {
+        multi_axpy<S>(n, V, ldv, j + 1, h1, -1.0, w, w, nullptr, st);
+        multidot_part<S>(n, V, ldv, j + 1, w, part, st);
+        reduce_cols(part, mdb, 2 * (j + 1), h2, st);
+      }
       multi_axpy<S>(n, V, ldv, j + 1, h2, -1.0, w, w, part, st);
       reduce_cols(part, rdb, 1, nrm, st);
-      arnoldi_finish(j, m, H, g, cs, sn, h1, h2, nrm, gs, st);
+      arnoldi_finish(j, m, H, g, cs, sn, h1, h2, nrm, gs, slot_dev[j & 1], st);
+      hipError_t e1 = hipEventRecord(ev[j & 1], st);
+      if (e1 != hipSuccess) return hip_fail(e1, "gmres: status event");
       scale_dev<S>(n, w, &gs->inv_hn, w, st);
-      if ((s = read_host(op, gs, sizeof(GmState), st, "gmres: arnoldi"))) return s;
-      const GmState* hs = (const GmState*)op->host;
+      return launch_check("gmres: arnoldi step");
+    };
+    int k = 0;
+    if ((s = enqueue_step(0))) return s;
+    for (int j = 0; j < m; ++j) {
+      // look ahead: queue step j+1 before waiting for step j's status; if step j
+      // ends the cycle the queued step is discarded (it only touches V_{j+2},
+      // column j+1 of H and g[j+1..j+2], none of which the back-solve reads)
+      if (j + 1 < m && count + 1 < o->max_iters)
+        if ((s = enqueue_step(j + 1))) return s;
+      hipError_t e1 = hipEventSynchronize(ev[j & 1]);
+      if (e1 != hipSuccess) return hip_fail(e1, "gmres: status wait");
+      const GmState hs = *slot[j & 1];
       count++;
+      matvecs++;
+      if (c.use_M) papps++;
       k = j + 1;
-      if (o->history && hlen <= o->max_iters) o->history[hlen++] = fn > 0 ? hs->gabs / fn : hs->gabs;
-      if (hs->flag) {
+      if (o->history && hlen <= o->max_iters) o->history[hlen++] = fn > 0 ? hs.gabs / fn : hs.gabs;
+      if (hs.flag) {
         status = HELM_E_NONFINITE;
         break;
       }
-      if (hs->gabs <= thr || count >= o->max_iters || hs->hn == 0.0) break;
+      if (hs.gabs <= thr || count >= o->max_iters || hs.hn == 0.0) break;
     }
     if (status == HELM_E_NONFINITE) break;
     // u += M (V_k y)
@@ -262,7 +310,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
         if ((s = precond_apply<S>(op, c, p, ph, st))) return s;
         papps++;
       }
-      stencil_apply<S>(op->geom, op->sc, op->mask, ph, v, st);
+      stencil_apply<S>(op->geom, op->sc, op->code, ph, v, st);
       matvecs++;
       dot_part<S>(n, rh, v, part, st);
       reduce_cols(part, rdb, 2, red, st);
@@ -292,7 +340,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
         if ((s = precond_apply<S>(op, c, sv, sh, st))) return s;
         papps++;
       }
-      stencil_apply<S>(op->geom, op->sc, op->mask, sh, t, st);
+      stencil_apply<S>(op->geom, op->sc, op->code, sh, t, st);
       matvecs++;
       two_dot_part<S>(n, t, sv, part, st);
       reduce_cols(part, rdb, 3, red + 4, st);
@@ -401,7 +449,7 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
   (void)hipEventCreate(&e2);
   (void)hipEventRecord(e0, st);
   if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
-    if ((s = coarse_ensure(op, net, o->p_used, st))) {
+    if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, st))) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       (void)hipEventDestroy(e2);
@@ -473,7 +521,7 @@ helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void
   helm_status s = check_opts(op, net, o);
   if (s) return s;
   hipStream_t hs = (hipStream_t)stream;
-  if (net && (s = coarse_ensure(op, net, o->p_used, hs))) return s;
+  if (net && (s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, hs))) return s;
   const size_t fld = op->nn * op_esz(op);
   if ((s = op->ws.ensure(fld))) return s;
   MetaCtx c{o, net, true, op->ws.ptr};
@@ -488,7 +536,7 @@ helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* r
   helm_status s = check_net_for_op(net, op, o->p_used);
   if (s) return s;
   hipStream_t hs = (hipStream_t)stream;
-  if ((s = coarse_ensure(op, net, o->p_used, hs))) return s;
+  if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, hs))) return s;
   const int r = op->coarse.rank;
   *rank = r;
   if (Ac) {
@@ -498,7 +546,7 @@ helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* r
   }
   if (Q) {
     if (q_cap < op->nn * (size_t)r) return fail(HELM_E_INVAL, "meta_coarse_info: Q capacity too small");
-    const size_t rs = op->dt == HELM_C128 ? sizeof(double) : sizeof(float);
+    const size_t rs = op->coarse.q_f32 ? sizeof(float) : sizeof(double);
     hipError_t e = hipMemcpyAsync(Q, op->coarse.Q.ptr, rs * op->nn * r, hipMemcpyDeviceToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "meta_coarse_info: Q");
   }

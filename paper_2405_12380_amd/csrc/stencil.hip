@@ -5,7 +5,9 @@
 // one contiguous 1 KiB (complex128) row segment per load), 4 rows in y, and
 // each thread marches over `zb` consecutive z-planes keeping the z-1, z, z+1
 // values of its column in registers, so every node is loaded from HBM once;
-// x/y neighbours are re-read from L1/L2.  Logical blocks are laid out x-, y-,
+// x/y neighbours are re-read from L1/L2.  Masks enter through one neighbour
+// code byte per node, so all loads of a node are independent and issued
+// together.  Logical blocks are laid out x-, y-,
 // then z-fastest and remapped so that each XCD owns one contiguous range of
 // them (one z-slab), keeping halo re-reads inside that XCD's L2.
 //
@@ -20,12 +22,42 @@ namespace helm {
 
 enum { ST_APPLY = 0, ST_JACOBI = 1, ST_RESID = 2, ST_RBGS = 3 };
 
+// Neighbour code of a node (built once per op): bit 0 = the node is masked;
+// bits 1..6 = its x-, x+, y-, y+, z-, z+ neighbour is absent (ghost or masked)
+// and contributes 0.  One byte replaces seven mask reads per node, and lets
+// every neighbour load be issued unconditionally (clamped inside the grid).
+enum { NB_SELF = 1, NB_XM = 2, NB_XP = 4, NB_YM = 8, NB_YP = 16, NB_ZM = 32, NB_ZP = 64 };
+
+__global__ void k_build_codes(int dim, int nx, int ny, int nz, const uint8_t* __restrict__ mask,
+                              uint8_t* __restrict__ code) {
+  const size_t n = (size_t)nx * ny * nz, plane = (size_t)nx * ny;
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(p % nx), j = (int)((p / nx) % ny), l = (int)(p / plane);
+    uint8_t c = mask[p] ? NB_SELF : 0;
+    if (i == 0 || mask[p - 1]) c |= NB_XM;
+    if (i + 1 == nx || mask[p + 1]) c |= NB_XP;
+    if (j == 0 || mask[p - nx]) c |= NB_YM;
+    if (j + 1 == ny || mask[p + nx]) c |= NB_YP;
+    if (dim == 3) {
+      if (l == 0 || mask[p - plane]) c |= NB_ZM;
+      if (l + 1 == nz || mask[p + plane]) c |= NB_ZP;
+    }
+    code[p] = c;
+  }
+}
+
+__device__ __forceinline__ double2 sel0(bool absent, double2 v) { return absent ? czero() : v; }
+
+static int stencil_blocks(const StencilGeom& g) {
+  const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = (g.nz + g.zb - 1) / g.zb;
+  return nbx * nby * nbz;
+}
+
 template <typename S, int DIM, int MODE>
 __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const cplx_t<S>* __restrict__ sc,
-                                                 const uint8_t* __restrict__ mask, const cplx_t<S>* x,
+                                                 const uint8_t* __restrict__ code, const cplx_t<S>* x,
                                                  const cplx_t<S>* __restrict__ f, cplx_t<S>* y,
                                                  double omega, int color, double* __restrict__ partials) {
-  __shared__ double sh[16];
   const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
   const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4;
   const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
@@ -35,66 +67,61 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const cplx_t<S>*
   const int z1 = min(g.nz, z0 + g.zb);
   const bool active = (i < g.nx) && (j < g.ny);
   const size_t plane = (size_t)g.nx * g.ny;
+  // clamped neighbour offsets (an absent neighbour is read from the node itself
+  // and then replaced by 0 through the code bits)
+  const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
+  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
   double nrm = 0.0;
   if (active && z0 < z1) {
     size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
     double2 c = ldc(x, p);
-    bool mc = mask[p] != 0;
     double2 zm = czero();
-    if (DIM == 3 && z0 > 0) {
-      if (!mask[p - plane]) zm = ldc(x, p - plane);
-    }
+    if (DIM == 3 && z0 > 0) zm = ldc(x, p - plane);
     for (int z = z0; z < z1; ++z, p += plane) {
       double2 znext = czero();
-      bool mnext = false;
-      if (DIM == 3 && z + 1 < g.nz) {
-        znext = ldc(x, p + plane);
-        mnext = mask[p + plane] != 0;
-      }
+      if (DIM == 3 && z + 1 < g.nz) znext = ldc(x, p + plane);
       const bool upd = (MODE != ST_RBGS) || (((i + j + z) & 1) == color);
       if (upd) {
+        const unsigned cd = code[p];
+        const double2 xm = ldc(x, p + oxm), xp = ldc(x, p + oxp);
+        const double2 ym = ldc(x, p + oym), yp = ldc(x, p + oyp);
+        const double2 sp = ldc(sc, p);
+        double2 fp = czero();
+        if (MODE != ST_APPLY) fp = ldc(f, p);
         double2 ax;
-        if (mc) {
+        if (cd & NB_SELF) {
           ax = c;
         } else {
-          double2 xm = czero(), xp = czero(), ym = czero(), yp = czero();
-          if (i > 0 && !mask[p - 1]) xm = ldc(x, p - 1);
-          if (i + 1 < g.nx && !mask[p + 1]) xp = ldc(x, p + 1);
-          if (j > 0 && !mask[p - g.nx]) ym = ldc(x, p - g.nx);
-          if (j + 1 < g.ny && !mask[p + g.nx]) yp = ldc(x, p + g.nx);
+          const double2 a = sel0(cd & NB_XM, xm), b = sel0(cd & NB_XP, xp);
+          const double2 e = sel0(cd & NB_YM, ym), h = sel0(cd & NB_YP, yp);
           double2 acc;
-          acc.x = ((c.x - xm.x) + (c.x - xp.x)) * g.ih2[0];
-          acc.y = ((c.y - xm.y) + (c.y - xp.y)) * g.ih2[0];
-          acc.x = acc.x + ((c.x - ym.x) + (c.x - yp.x)) * g.ih2[1];
-          acc.y = acc.y + ((c.y - ym.y) + (c.y - yp.y)) * g.ih2[1];
+          acc.x = ((c.x - a.x) + (c.x - b.x)) * g.ih2[0];
+          acc.y = ((c.y - a.y) + (c.y - b.y)) * g.ih2[0];
+          acc.x = acc.x + ((c.x - e.x) + (c.x - h.x)) * g.ih2[1];
+          acc.y = acc.y + ((c.y - e.y) + (c.y - h.y)) * g.ih2[1];
           if (DIM == 3) {
-            const double2 zp = mnext ? czero() : znext;
-            acc.x = acc.x + ((c.x - zm.x) + (c.x - zp.x)) * g.ih2[2];
-            acc.y = acc.y + ((c.y - zm.y) + (c.y - zp.y)) * g.ih2[2];
+            const double2 q = sel0(cd & NB_ZM, zm), w = sel0(cd & NB_ZP, znext);
+            acc.x = acc.x + ((c.x - q.x) + (c.x - w.x)) * g.ih2[2];
+            acc.y = acc.y + ((c.y - q.y) + (c.y - w.y)) * g.ih2[2];
           }
-          ax = csub(acc, cmul(ldc(sc, p), c));
+          ax = csub(acc, cmul(sp, c));
         }
         if (MODE == ST_APPLY) {
           stc(y, p, ax);
         } else if (MODE == ST_RESID) {
-          const double2 r = csub(ldc(f, p), ax);
+          const double2 r = csub(fp, ax);
           nrm += r.x * r.x + r.y * r.y;
           stc(y, p, r);
         } else {  // Jacobi / RB-GS update
-          const double2 r = csub(ldc(f, p), ax);
-          double2 d = make_double2(1.0, 0.0);
-          if (!mc) {
-            const double2 sp = ldc(sc, p);
-            d = make_double2(g.dsum - sp.x, -sp.y);
-          }
+          const double2 r = csub(fp, ax);
+          const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
           const double2 q = cdiv(r, d);
           stc(y, p, make_double2(c.x + omega * q.x, c.y + omega * q.y));
         }
       }
       if (DIM == 3) {
-        zm = mc ? czero() : c;
+        zm = c;
         c = znext;
-        mc = mnext;
       }
     }
   }
@@ -107,7 +134,92 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const cplx_t<S>*
     __syncthreads();
     if (t == 0) partials[lb] = (shr[0] + shr[1]) + (shr[2] + shr[3]);
   }
-  (void)sh;
+}
+
+// Two damped Jacobi sweeps on A z = f started from z = 0, in one pass:
+// z1 = omega D^{-1} f is formed on the fly at the node and its neighbours (f and
+// s re-read from cache), then z2 = z1 + omega D^{-1} (f - A z1).  The per-node
+// arithmetic is that of two separate sweeps; the HBM traffic is that of one
+// (f, s, code in; z2 out).
+__device__ __forceinline__ double2 jac0(double2 f, double2 s, double dsum, bool masked, double omega) {
+  const double2 d = masked ? make_double2(1.0, 0.0) : make_double2(dsum - s.x, -s.y);
+  const double2 q = cdiv(f, d);
+  return make_double2(omega * q.x, omega * q.y);
+}
+
+template <typename S, int DIM>
+__global__ __launch_bounds__(256) void k_jacobi2z(StencilGeom g, const cplx_t<S>* __restrict__ sc,
+                                                  const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ f,
+                                                  cplx_t<S>* __restrict__ y, double omega) {
+  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4;
+  const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+  const int i = bx * 64 + threadIdx.x;
+  const int j = by * 4 + threadIdx.y;
+  const int z0 = bz * g.zb;
+  const int z1e = min(g.nz, z0 + g.zb);
+  if (!(i < g.nx && j < g.ny) || z0 >= z1e) return;
+  const size_t plane = (size_t)g.nx * g.ny;
+  const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
+  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
+  size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
+  // z1 of the column at z-1, z (the z-1 value only matters when present)
+  double2 zc = jac0(ldc(f, p), ldc(sc, p), g.dsum, code[p] & NB_SELF, omega);
+  double2 zmv = czero();
+  if (DIM == 3 && z0 > 0) zmv = jac0(ldc(f, p - plane), ldc(sc, p - plane), g.dsum, false, omega);
+  for (int z = z0; z < z1e; ++z, p += plane) {
+    double2 znv = czero();
+    if (DIM == 3 && z + 1 < g.nz) znv = jac0(ldc(f, p + plane), ldc(sc, p + plane), g.dsum, false, omega);
+    const unsigned cd = code[p];
+    const double2 fp = ldc(f, p), sp = ldc(sc, p);
+    double2 ax;
+    if (cd & NB_SELF) {
+      ax = zc;
+    } else {
+      const double2 a = (cd & NB_XM) ? czero() : jac0(ldc(f, p + oxm), ldc(sc, p + oxm), g.dsum, false, omega);
+      const double2 b = (cd & NB_XP) ? czero() : jac0(ldc(f, p + oxp), ldc(sc, p + oxp), g.dsum, false, omega);
+      const double2 e = (cd & NB_YM) ? czero() : jac0(ldc(f, p + oym), ldc(sc, p + oym), g.dsum, false, omega);
+      const double2 h = (cd & NB_YP) ? czero() : jac0(ldc(f, p + oyp), ldc(sc, p + oyp), g.dsum, false, omega);
+      double2 acc;
+      acc.x = ((zc.x - a.x) + (zc.x - b.x)) * g.ih2[0];
+      acc.y = ((zc.y - a.y) + (zc.y - b.y)) * g.ih2[0];
+      acc.x = acc.x + ((zc.x - e.x) + (zc.x - h.x)) * g.ih2[1];
+      acc.y = acc.y + ((zc.y - e.y) + (zc.y - h.y)) * g.ih2[1];
+      if (DIM == 3) {
+        const double2 q = (cd & NB_ZM) ? czero() : zmv, w = (cd & NB_ZP) ? czero() : znv;
+        acc.x = acc.x + ((zc.x - q.x) + (zc.x - w.x)) * g.ih2[2];
+        acc.y = acc.y + ((zc.y - q.y) + (zc.y - w.y)) * g.ih2[2];
+      }
+      ax = csub(acc, cmul(sp, zc));
+    }
+    const double2 r = csub(fp, ax);
+    const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
+    const double2 q = cdiv(r, d);
+    stc(y, p, make_double2(zc.x + omega * q.x, zc.y + omega * q.y));
+    if (DIM == 3) {
+      zmv = zc;
+      zc = znv;
+      // the next node's own z1 needs its own mask bit; recompute if it is masked
+      if (z + 1 < z1e && (code[p + plane] & NB_SELF))
+        zc = jac0(ldc(f, p + plane), ldc(sc, p + plane), g.dsum, true, omega);
+    }
+  }
+}
+
+template <typename S>
+void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* z, double omega,
+                       hipStream_t st) {
+  using C = cplx_t<S>;
+  const int nb = stencil_blocks(g);
+  const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
+  kprof_begin(st);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_jacobi2z<S, 3>), dim3(nb), dim3(64, 4), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
+                       omega);
+  else
+    hipLaunchKernelGGL((k_jacobi2z<S, 2>), dim3(nb), dim3(64, 4), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
+                       omega);
+  kprof_end(KP_STENCIL, n * (3 * esz + 1), st);
 }
 
 // z = omega D^{-1} f: a Jacobi sweep started from z = 0 (no stencil needed).
@@ -136,10 +248,6 @@ __global__ void k_build_s(size_t n, const double* __restrict__ ksq, const double
     stc(sc, p, make_double2(ksq[p], ksq[p] * alpha[p]));
 }
 
-static int stencil_blocks(const StencilGeom& g) {
-  const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = (g.nz + g.zb - 1) / g.zb;
-  return nbx * nby * nbz;
-}
 
 StencilGeom make_geom(int dim, const int n[3], int zb) {
   StencilGeom g;
@@ -168,45 +276,52 @@ StencilGeom make_geom(int dim, const int n[3], int zb) {
 
 int stencil_nblocks(const StencilGeom& g) { return stencil_blocks(g); }
 
+void build_codes(const StencilGeom& g, const uint8_t* mask, uint8_t* code, hipStream_t st) {
+  size_t n = (size_t)g.nx * g.ny * g.nz;
+  size_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_build_codes, dim3((unsigned)nb), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz, mask, code);
+}
+
 template <typename S, int MODE>
-static void launch_mode(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* x, const void* f,
+static void launch_mode(const StencilGeom& g, const void* sc, const uint8_t* code, const void* x, const void* f,
                         void* y, double omega, int color, double* part, hipStream_t st) {
   using C = cplx_t<S>;
   dim3 blk(64, 4);
   const int nb = stencil_blocks(g);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
-  // algorithmic bytes: x, s, mask, y (+ f); a red-black colour pass is half a sweep
+  // algorithmic bytes: x, s, the code byte, y (+ f); a red-black colour pass is half a sweep
   const double bytes = MODE == ST_APPLY ? n * (3 * esz + 1) : MODE == ST_RBGS ? n * (4 * esz + 1) / 2 : n * (4 * esz + 1);
   kprof_begin(st);
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_stencil<S, 3, MODE>), dim3(nb), blk, 0, st, g, (const C*)sc, mask, (const C*)x,
+    hipLaunchKernelGGL((k_stencil<S, 3, MODE>), dim3(nb), blk, 0, st, g, (const C*)sc, code, (const C*)x,
                        (const C*)f, (C*)y, omega, color, part);
   else
-    hipLaunchKernelGGL((k_stencil<S, 2, MODE>), dim3(nb), blk, 0, st, g, (const C*)sc, mask, (const C*)x,
+    hipLaunchKernelGGL((k_stencil<S, 2, MODE>), dim3(nb), blk, 0, st, g, (const C*)sc, code, (const C*)x,
                        (const C*)f, (C*)y, omega, color, part);
   kprof_end(KP_STENCIL, bytes, st);
 }
 
 template <typename S>
-void stencil_apply(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* x, void* y,
+void stencil_apply(const StencilGeom& g, const void* sc, const uint8_t* code, const void* x, void* y,
                    hipStream_t st) {
-  launch_mode<S, ST_APPLY>(g, sc, mask, x, nullptr, y, 0.0, 0, nullptr, st);
+  launch_mode<S, ST_APPLY>(g, sc, code, x, nullptr, y, 0.0, 0, nullptr, st);
 }
 template <typename S>
-void stencil_resid(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* f, const void* u,
+void stencil_resid(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, const void* u,
                    void* r, double* part, hipStream_t st) {
-  launch_mode<S, ST_RESID>(g, sc, mask, u, f, r, 0.0, 0, part, st);
+  launch_mode<S, ST_RESID>(g, sc, code, u, f, r, 0.0, 0, part, st);
 }
 template <typename S>
-void stencil_jacobi(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* f, const void* u,
+void stencil_jacobi(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, const void* u,
                     void* unew, double omega, hipStream_t st) {
-  launch_mode<S, ST_JACOBI>(g, sc, mask, u, f, unew, omega, 0, nullptr, st);
+  launch_mode<S, ST_JACOBI>(g, sc, code, u, f, unew, omega, 0, nullptr, st);
 }
 template <typename S>
-void stencil_rbgs(const StencilGeom& g, const void* sc, const uint8_t* mask, const void* f, void* u, double omega,
+void stencil_rbgs(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* u, double omega,
                   hipStream_t st) {
-  launch_mode<S, ST_RBGS>(g, sc, mask, u, f, u, omega, 0, nullptr, st);
-  launch_mode<S, ST_RBGS>(g, sc, mask, u, f, u, omega, 1, nullptr, st);
+  launch_mode<S, ST_RBGS>(g, sc, code, u, f, u, omega, 0, nullptr, st);
+  launch_mode<S, ST_RBGS>(g, sc, code, u, f, u, omega, 1, nullptr, st);
 }
 template <typename S>
 void jacobi_from_zero(size_t n, double dsum, const void* sc, const uint8_t* mask, const void* f, void* z,
@@ -235,6 +350,8 @@ void build_s(size_t n, const double* ksq, const double* alpha, void* sc, hipStre
                                 hipStream_t);                                                               \
   template void jacobi_from_zero<S>(size_t, double, const void*, const uint8_t*, const void*, void*, double,  \
                                     hipStream_t);                                                           \
+  template void jacobi2_from_zero<S>(const StencilGeom&, const void*, const uint8_t*, const void*, void*,     \
+                                     double, hipStream_t);                                                  \
   template void build_s<S>(size_t, const double*, const double*, void*, hipStream_t);
 HELM_INST(double)
 HELM_INST(float)

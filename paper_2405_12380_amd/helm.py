@@ -38,9 +38,9 @@ EXPORTED = ["helm_setup", "helm_set_ksq", "helm_destroy", "helm_size", "helm_app
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
             "meta_solve", "meta_precond", "meta_coarse_info", "helm_kprof_enable", "helm_kprof_read",
             "helm_strerror", "helm_last_error"]
-KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY = 0, 1, 2, 3, 4
+KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY, KP_CGS = 0, 1, 2, 3, 4, 5
 KP_NAMES = {KP_STENCIL: "stencil", KP_MULTIDOT: "multidot", KP_MULTIAXPY: "multi_axpy", KP_QT: "qt_part",
-            KP_SKINNY: "skinny_apply"}
+            KP_SKINNY: "skinny_apply", KP_CGS: "cgs_fused"}
 
 
 class HelmGrid(C.Structure):
@@ -56,7 +56,7 @@ class DonDesc(C.Structure):
 class MetaOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("restart", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
                 ("smoother", C.c_int), ("n_r", C.c_int), ("omega", C.c_double), ("nn_every", C.c_int),
-                ("p_used", C.c_int), ("k", C.c_double), ("history", C.POINTER(C.c_double))]
+                ("p_used", C.c_int), ("k", C.c_double), ("history", C.POINTER(C.c_double)), ("q_fp32", C.c_int)]
 
 
 class MetaStats(C.Structure):
@@ -254,12 +254,12 @@ _SMOOTH = {"jacobi": JACOBI, "rbgs": RBGS}
 
 
 def _opts(kind, restart=50, tol=1e-6, max_iters=20000, smoother="jacobi", n_r=3, omega=0.5, nn_every=25,
-          p_used=None, k=0.0, history=None, net=None):
+          p_used=None, k=0.0, history=None, net=None, q_fp32=False):
     pu = p_used if p_used is not None else (net.p if net is not None else 0)
     hp = history.ctypes.data_as(C.POINTER(C.c_double)) if history is not None else None
     return MetaOpts(_KIND[kind] if isinstance(kind, str) else int(kind), int(restart), float(tol), int(max_iters),
                     _SMOOTH[smoother] if isinstance(smoother, str) else int(smoother), int(n_r), float(omega),
-                    int(nn_every), int(pu), float(k), hp)
+                    int(nn_every), int(pu), float(k), hp, 1 if q_fp32 else 0)
 
 
 def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, stream=None, **kw):
@@ -286,15 +286,16 @@ def meta_precond(op: Op, net: DeepONet | None, r, z=None, stream=None, **kw):
     return z
 
 
-def coarse_info(op: Op, net: DeepONet, p_used=None, want_q=False, stream=None):
+def coarse_info(op: Op, net: DeepONet, p_used=None, want_q=False, q_fp32=False, stream=None):
     """(rank, A_c as a complex numpy array[, Q as a device tensor n x rank])."""
-    o = _opts("gmres", net=net, p_used=p_used)
+    o = _opts("gmres", net=net, p_used=p_used, q_fp32=q_fp32)
     rank = C.c_int(0)
     _check(_lib.meta_coarse_info(op.h, net.h, C.byref(o), C.byref(rank), None, 0, None, 0, _stream(stream)),
            "meta_coarse_info")
     r = rank.value
     ac = np.zeros(2 * r * r)
-    q = torch.empty(op.size * r, dtype=rdtype(op.dtype), device="cuda") if want_q else None
+    qdt = torch.float32 if (q_fp32 or op.dtype == C64) else torch.float64
+    q = torch.empty(op.size * r, dtype=qdt, device="cuda") if want_q else None
     _check(_lib.meta_coarse_info(op.h, net.h, C.byref(o), C.byref(rank), ac.ctypes.data_as(C.POINTER(C.c_double)),
                                  r * r, _ptr(q), op.size * r if want_q else 0, _stream(stream)), "meta_coarse_info")
     A = ac.view(np.complex128).reshape(r, r)

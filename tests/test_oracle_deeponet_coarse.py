@@ -170,6 +170,21 @@ def test_galerkin_orthogonality_and_exactness_on_span():
     assert np.max(np.abs(cs.Q[P["mask"].ravel().astype(bool)])) <= 1e-14
 
 
+def test_fp32_stored_basis_is_exact_galerkin():
+    """With Q rounded to fp32 and A_c built from the rounded Q, M2 is still the
+    Galerkin correction on span(Q): Q^T (r - A M2 r) = 0 and M2 A Q = Q."""
+    P, s, T = _coarse_problem()
+    cs = coarse.CoarseSpace(T, s, P["mask"], 16, q_round="f32")
+    assert np.array_equal(cs.Q, cs.Q.astype(np.float32).astype(np.float64))
+    shape = s.shape
+    A = lambda v: op.apply(v.reshape(shape), s, P["mask"]).ravel()
+    r = P["f"].ravel()
+    z = cs.m2(r.reshape(shape)).ravel()
+    assert np.max(np.abs(cs.Q.T @ (r - A(z)))) <= 1e-11 * np.linalg.norm(r)
+    q = cs.Q[:, 3].astype(complex)
+    assert np.max(np.abs(cs.m2(A(q).reshape(shape)).ravel() - q)) <= 1e-10
+
+
 def test_basis_invariance():
     """M2 depends only on span(P): any invertible mixing of the columns gives
     the same correction."""
