@@ -228,22 +228,27 @@ __global__ void k_reduce_rows(const double* __restrict__ part, int nparts, size_
 }
 
 // ---- one-workgroup Cholesky with column dropping -------------------------------
-// G: p x p (row-major, fp64, overwritten) = P^T P.  Right-looking Cholesky
+// G: p x p (row-major, fp64) = P^T P, p <= 128, copied into LDS (128 KiB at
+// p = 128; gfx950 gives a workgroup up to 160 KiB).  Right-looking Cholesky
 // G = R^T R on the upper triangle; a column whose Schur-complement diagonal is
 // <= tau2 * max_j G[j][j] is dropped (its remaining norm is at most tau times
-// the largest column norm), which matches
-// Householder QR that skips such columns.  Outputs: S (p x r row-major) with
-// S[kept[a]][:] = (R1^{-1})[a][:] and zero rows for dropped columns, so that
-// Q = P S has orthonormal columns in exact arithmetic; info[0] = r;
-// info[1] = 1 if a column had to be dropped while allow_drop = 0.
-// G and X (r x r, scratch) live in global memory (L2-resident at these sizes).
-__global__ __launch_bounds__(1024) void k_chol_drop(int p, double* __restrict__ G, double tau2, int allow_drop,
-                                                    double* __restrict__ X, double* __restrict__ S,
-                                                    int* __restrict__ info) {
+// the largest column norm), which matches Householder QR that skips such
+// columns.  R1^{-1} (kept rows/columns) is then formed in the free strictly
+// lower triangle (transposed) plus a diagonal array, one thread per column.
+// Outputs: S (p x r row-major) with S[kept[a]][:] = (R1^{-1})[a][:] and zero
+// rows for dropped columns, so that Q = P S has orthonormal columns in exact
+// arithmetic; info[0] = r; info[1] = 1 if a column had to be dropped while
+// allow_drop = 0.
+__global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restrict__ Gin, double tau2, int allow_drop,
+                                                    double* __restrict__ S, int* __restrict__ info) {
+  extern __shared__ double G[];  // p x p
+  __shared__ double xdiag[128];
   __shared__ int kept[128];
   __shared__ int s_nk, s_fail;
   __shared__ double s_piv, s_thr2;
   const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < p * p; e += nt) G[e] = Gin[e];
+  __syncthreads();
   if (t == 0) {
     s_nk = 0;
     s_fail = 0;
@@ -255,12 +260,12 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, double* __restrict__ 
   const double thr2 = s_thr2;
   for (int j = 0; j < p; ++j) {
     if (t == 0) {
-      const double d = G[j * p + j];
-      if (!(d > thr2)) {
+      const double dj = G[j * p + j];
+      if (!(dj > thr2)) {
         s_piv = -1.0;
         if (!allow_drop) s_fail = 1;
       } else {
-        s_piv = sqrt(d);
+        s_piv = sqrt(dj);
         kept[s_nk] = j;
         s_nk = s_nk + 1;
       }
@@ -280,15 +285,18 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, double* __restrict__ 
     __syncthreads();
   }
   const int r = s_nk;
-  // X = R1^{-1} for R1[a][b] = G[kept[a]][kept[b]] (a <= b): back substitution,
-  // one thread per column b of X.
-  for (int e = t; e < r * r; e += nt) X[e] = 0.0;
-  __syncthreads();
+  // X = R1^{-1}, R1[a][b] = G[kept[a]][kept[b]] (a <= b).  X[a][b] (a < b) is kept
+  // at G[kept[b]][kept[a]] (strictly lower, unused by R), X[a][a] in xdiag.
   for (int b = t; b < r; b += nt) {
     for (int a = b; a >= 0; --a) {
       double acc = (a == b) ? 1.0 : 0.0;
-      for (int c = a + 1; c <= b; ++c) acc -= G[kept[a] * p + kept[c]] * X[c * r + b];
-      X[a * r + b] = acc / G[kept[a] * p + kept[a]];
+      for (int c = a + 1; c <= b; ++c) {
+        const double xcb = (c == b) ? xdiag[b] : G[kept[b] * p + kept[c]];
+        acc -= G[kept[a] * p + kept[c]] * xcb;
+      }
+      const double v = acc / G[kept[a] * p + kept[a]];
+      if (a == b) xdiag[b] = v;
+      else G[kept[b] * p + kept[a]] = v;
     }
   }
   __syncthreads();
@@ -296,7 +304,10 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, double* __restrict__ 
   __syncthreads();
   for (int e = t; e < r * r; e += nt) {
     const int a = e / r, b = e % r;
-    S[(size_t)kept[a] * r + b] = X[e];
+    double v = 0.0;
+    if (a == b) v = xdiag[a];
+    else if (a < b) v = G[kept[b] * p + kept[a]];
+    S[(size_t)kept[a] * r + b] = v;
   }
   if (t == 0) {
     info[0] = r;
@@ -304,136 +315,158 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, double* __restrict__ 
   }
 }
 
-// ---- Gauss-Jordan inverse of a complex r x r matrix, one workgroup -------------
-// Work array Wk: r x 2r complex (interleaved, row-major) = [A | I]; partial
-// pivoting by largest modulus (lowest index on ties).  Ainv receives the
-// inverse; info[0] = 1 if a pivot was exactly zero or non-finite.
+// ---- Gauss-Jordan inverse of a complex r x r matrix (r <= 128), one workgroup ----
+// The matrix lives in registers: thread t owns row t / 8 and the 16 columns
+// [16 (t % 8), 16 (t % 8) + 16).  In-place Gauss-Jordan with partial pivoting
+// (largest modulus, lowest row on ties): per pivot the column is published in
+// LDS, wavefront 0 picks the pivot, the two rows are exchanged through LDS, the
+// pivot row is scaled and broadcast, and every thread updates its 16 entries.
+// The row interchanges are undone at the end as column interchanges in
+// reverse order.  info[0] = 1 if a pivot was zero or non-finite;
 // cond[0] = ||A||_1 ||A^{-1}||_1.
-__global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __restrict__ A, double* __restrict__ Wk,
-                                                     double* __restrict__ Ainv, int* __restrict__ info,
-                                                     double* __restrict__ cond) {
-  __shared__ double smax[1024];
-  __shared__ int sidx[1024];
-  __shared__ int s_piv;
-  __shared__ double s_anorm;
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int w2 = 2 * r;
-  for (int e = t; e < r * w2; e += nt) {
-    const int i = e / w2, c = e % w2;
-    double re, im;
-    if (c < r) {
-      re = A[2 * ((size_t)i * r + c)];
-      im = A[2 * ((size_t)i * r + c) + 1];
-    } else {
-      re = (c - r == i) ? 1.0 : 0.0;
-      im = 0.0;
-    }
-    Wk[2 * (size_t)e] = re;
-    Wk[2 * (size_t)e + 1] = im;
+__global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __restrict__ A, double* __restrict__ Ainv,
+                                                     int* __restrict__ info, double* __restrict__ cond) {
+  __shared__ double2 pcol[128], prow[128], bufk[128], bufp[128];
+  __shared__ double pabs[128], csum[128];
+  __shared__ int perm[128];
+  __shared__ int s_piv, s_bad;
+  const int t = threadIdx.x;
+  const int i = t >> 3, cb = t & 7, c0 = 16 * cb;
+  const bool row_in = i < r;
+  double2 a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int c = c0 + q;
+    a[q] = (row_in && c < r) ? make_double2(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]) : czero();
   }
-  // ||A||_1 = max column sum
-  if (t == 0) s_anorm = 0.0;
-  __syncthreads();
-  for (int c = t; c < r; c += nt) {
+  // ||A||_1: column sums
+  if (t < 128) {
     double sm = 0.0;
-    for (int i = 0; i < r; ++i) sm += hypot(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]);
-    smax[t] = sm;
+    if (t < r)
+      for (int ii = 0; ii < r; ++ii) sm += hypot(A[2 * ((size_t)ii * r + t)], A[2 * ((size_t)ii * r + t) + 1]);
+    csum[t] = sm;
   }
-  __syncthreads();
-  if (t == 0) {
-    double mx = 0.0;
-    for (int c = 0; c < r && c < nt; ++c) mx = fmax(mx, smax[c]);
-    s_anorm = mx;
-    info[0] = 0;
-  }
+  if (t == 0) s_bad = 0;
   __syncthreads();
   for (int k = 0; k < r; ++k) {
-    // pivot search in column k, rows k..r-1
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + t; i < r; i += nt) {
-      const size_t o = 2 * ((size_t)i * w2 + k);
-      const double v = hypot(Wk[o], Wk[o + 1]);
-      if (v > best) {
-        best = v;
-        bi = i;
+    const int kb = k >> 4, kq = k & 15;
+    if (cb == kb && row_in) {
+      double2 v = czero();
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q == kq) v = a[q];
+      pcol[i] = v;
+      pabs[i] = i >= k ? hypot(v.x, v.y) : -1.0;
+    }
+    __syncthreads();
+    if (t < 64) {
+      double best = -2.0;
+      int bi = 0;
+      for (int ii = t; ii < r; ii += 64)
+        if (pabs[ii] > best) {
+          best = pabs[ii];
+          bi = ii;
+        }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (t == 0) {
+        s_piv = bi;
+        perm[k] = bi;
+        if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
       }
     }
-    smax[t] = best;
-    sidx[t] = bi;
     __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (t < s) {
-        if (smax[t + s] > smax[t] || (smax[t + s] == smax[t] && sidx[t + s] < sidx[t])) {
-          smax[t] = smax[t + s];
-          sidx[t] = sidx[t + s];
-        }
+    const int p = s_piv;
+    if (p != k) {
+      if (i == k)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) bufk[c0 + q] = a[q];
+      if (i == p)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) bufp[c0 + q] = a[q];
+      __syncthreads();
+      if (i == k)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = bufp[c0 + q];
+      if (i == p)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = bufk[c0 + q];
+      if (t == 0) {
+        const double2 tmp = pcol[k];
+        pcol[k] = pcol[p];
+        pcol[p] = tmp;
       }
       __syncthreads();
     }
-    if (t == 0) {
-      s_piv = sidx[0];
-      if (!(smax[0] > 0.0) || !isfinite(smax[0])) info[0] = 1;
-    }
-    __syncthreads();
-    const int pr = s_piv;
-    if (pr != k)
-      for (int c = t; c < w2; c += nt) {
-        const size_t a = 2 * ((size_t)k * w2 + c), b = 2 * ((size_t)pr * w2 + c);
-        const double x0 = Wk[a], x1 = Wk[a + 1];
-        Wk[a] = Wk[b];
-        Wk[a + 1] = Wk[b + 1];
-        Wk[b] = x0;
-        Wk[b + 1] = x1;
+    // scale the pivot row: A[k][k] <- 1, row /= pivot; publish it
+    if (i == k) {
+      const double2 piv = pcol[k];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double2 v = (c0 + q == k) ? make_double2(1.0, 0.0) : a[q];
+        a[q] = cdiv(v, piv);
+        prow[c0 + q] = a[q];
       }
-    __syncthreads();
-    // scale pivot row
-    const double2 pv = make_double2(Wk[2 * ((size_t)k * w2 + k)], Wk[2 * ((size_t)k * w2 + k) + 1]);
-    __syncthreads();
-    for (int c = t; c < w2; c += nt) {
-      const size_t a = 2 * ((size_t)k * w2 + c);
-      const double2 v = cdiv(make_double2(Wk[a], Wk[a + 1]), pv);
-      Wk[a] = v.x;
-      Wk[a + 1] = v.y;
     }
     __syncthreads();
-    // eliminate column k from every other row
-    for (int e = t; e < r * w2; e += nt) {
-      const int i = e / w2, c = e % w2;
-      if (i == k || c == k) continue;
-      const size_t fi = 2 * ((size_t)i * w2 + k);
-      const double2 fct = make_double2(Wk[fi], Wk[fi + 1]);
-      const size_t a = 2 * ((size_t)i * w2 + c), b = 2 * ((size_t)k * w2 + c);
-      const double2 v = csub(make_double2(Wk[a], Wk[a + 1]), cmul(fct, make_double2(Wk[b], Wk[b + 1])));
-      Wk[a] = v.x;
-      Wk[a + 1] = v.y;
-    }
-    __syncthreads();
-    for (int i = t; i < r; i += nt)
-      if (i != k) {
-        const size_t fi = 2 * ((size_t)i * w2 + k);
-        Wk[fi] = 0.0;
-        Wk[fi + 1] = 0.0;
+    // eliminate column k from every other row: A[i][:] <- (A[i][:] with A[i][k] = 0) - f A[k][:]
+    if (i != k && row_in) {
+      const double2 f = pcol[i];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const double2 v = (c0 + q == k) ? czero() : a[q];
+        a[q] = csub(v, cmul(f, prow[c0 + q]));
       }
+    }
     __syncthreads();
   }
-  for (int e = t; e < r * r; e += nt) {
-    const int i = e / r, c = e % r;
-    const size_t o = 2 * ((size_t)i * w2 + r + c);
-    Ainv[2 * (size_t)e] = Wk[o];
-    Ainv[2 * (size_t)e + 1] = Wk[o + 1];
+  if (row_in)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = c0 + q;
+      if (c < r) {
+        Ainv[2 * ((size_t)i * r + c)] = a[q].x;
+        Ainv[2 * ((size_t)i * r + c) + 1] = a[q].y;
+      }
+    }
+  __syncthreads();
+  // undo the row interchanges: column interchanges in reverse order, row by row
+  if (t < r) {
+    double* row = Ainv + 2 * (size_t)t * r;
+    for (int k = r - 1; k >= 0; --k) {
+      const int p = perm[k];
+      if (p != k) {
+        const double x0 = row[2 * k], x1 = row[2 * k + 1];
+        row[2 * k] = row[2 * p];
+        row[2 * k + 1] = row[2 * p + 1];
+        row[2 * p] = x0;
+        row[2 * p + 1] = x1;
+      }
+    }
   }
   __syncthreads();
-  for (int c = t; c < r; c += nt) {
+  if (t < 128) {
     double sm = 0.0;
-    for (int i = 0; i < r; ++i) sm += hypot(Ainv[2 * ((size_t)i * r + c)], Ainv[2 * ((size_t)i * r + c) + 1]);
-    smax[t] = sm;
+    if (t < r)
+      for (int ii = 0; ii < r; ++ii) sm += hypot(Ainv[2 * ((size_t)ii * r + t)], Ainv[2 * ((size_t)ii * r + t) + 1]);
+    pabs[t] = sm;
   }
   __syncthreads();
   if (t == 0) {
-    double mx = 0.0;
-    for (int c = 0; c < r && c < nt; ++c) mx = fmax(mx, smax[c]);
-    cond[0] = s_anorm * mx;
+    double na = 0.0, ni = 0.0;
+    for (int c = 0; c < r; ++c) {
+      na = fmax(na, csum[c]);
+      ni = fmax(ni, pabs[c]);
+    }
+    cond[0] = na * ni;
+    info[0] = s_bad;
   }
 }
 
@@ -495,11 +528,20 @@ void reduce_rows(const double* part, int nparts, size_t width, double* out, doub
 }
 
 void chol_drop(int p, double* G, double tau2, int allow_drop, double* X, double* S, int* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(1024), 0, st, p, G, tau2, allow_drop, X, S, info);
+  (void)X;
+  const size_t lds = sizeof(double) * (size_t)p * p;
+  static bool attr_set = false;
+  if (!attr_set) {
+    // G staged in LDS: up to 128 KiB at p = 128 (a gfx950 workgroup may use 160 KiB)
+    (void)hipFuncSetAttribute((const void*)k_chol_drop, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(1024), lds, st, p, G, tau2, allow_drop, S, info);
 }
 
 void gj_inverse(int r, const double* A, double* work, double* Ainv, int* info, double* cond, hipStream_t st) {
-  hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(1024), 0, st, r, A, work, Ainv, info, cond);
+  (void)work;
+  hipLaunchKernelGGL(k_gj_inverse, dim3(1), dim3(1024), 0, st, r, A, Ainv, info, cond);
 }
 
 template void coord_layer<double>(int, const int*, size_t, size_t, const double*, const double*, int, int, double*,

@@ -23,11 +23,15 @@ __device__ static inline double cabs2(double2 a) { return hypot(a.x, a.y); }
 // rotations are staged in LDS, lane 0 applies the rotations (inherently
 // sequential, now on LDS), and the column is written back in parallel.
 __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn,
-                                                       const double* h1, const double* h2, const double* nrm2,
-                                                       GmState* gs, GmState* ghost) {
+                                                       const double* h1, const double* h2, const double* npart,
+                                                       int nparts, GmState* gs, GmState* ghost) {
   __shared__ double col[2 * 1002];
   __shared__ double rc[1001], rs[2 * 1001];
   const int l = threadIdx.x;
+  // ||w||^2 from the per-block partials of the last CGS update (fixed order)
+  double ns = 0.0;
+  for (int b = l; b < nparts; b += 64) ns += npart[b];
+  ns = wave_sum(ns);
   for (int i = l; i <= j; i += 64) {
     col[2 * i] = h1[2 * i] + h2[2 * i];
     col[2 * i + 1] = h1[2 * i + 1] + h2[2 * i + 1];
@@ -39,7 +43,7 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
   }
   __syncthreads();
   if (l == 0) {
-    const double hn = sqrt(nrm2[0]);
+    const double hn = sqrt(ns);
     gs->hn = hn;
     gs->inv_hn = hn != 0.0 ? 1.0 / hn : 0.0;
     // previous rotations G_i = [[c, s], [-conj(s), c]] on rows (i, i+1)
@@ -154,8 +158,8 @@ __global__ void k_gmres_init(double beta, double* g, int m) {
 }
 
 void arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1, const double* h2,
-                    const double* nrm2, GmState* gs, GmState* ghost, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, st, j, m, H, g, cs, sn, h1, h2, nrm2, gs, ghost);
+                    const double* npart, int nparts, GmState* gs, GmState* ghost, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, st, j, m, H, g, cs, sn, h1, h2, npart, nparts, gs, ghost);
 }
 void gmres_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t st) {
   const size_t lds = sizeof(double) * 2 * ((size_t)k + (k <= BS_LDS_MAX ? (size_t)k * (k + 1) / 2 : 0));

@@ -10,6 +10,8 @@ namespace helm {
 
 struct StencilGeom {
   int nx, ny, nz, dim, zb;
+  int ty;    // tile height (rows per workgroup): 4 or 8
+  bool nt;   // non-temporal output stores (grids much larger than the caches)
   double ih2[3];  // 1/h_a^2 (0 for absent axes)
   double dsum;    // sum_a 2/h_a^2, the Laplacian's diagonal
 };
@@ -112,10 +114,11 @@ struct GmState {
   int step;     // Arnoldi step j this record belongs to
 };
 // H: (m+1) x m complex column-major (H + 2*(j*(m+1) + i)); g: m+1 complex; cs: m real; sn: m complex
-// h1, h2: reduced CGS passes (j+1 complex each); nrm2: ||w||^2; ghost: a second copy of
-// the status record in host-mapped memory (device address of pinned host memory)
+// h1, h2: reduced CGS passes (j+1 complex each); npart: nparts per-block partials of
+// ||w||^2 (summed in order inside); ghost: a second copy of the status record in
+// host-mapped memory (device address of pinned host memory)
 void arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1, const double* h2,
-                    const double* nrm2, GmState* gs, GmState* ghost, hipStream_t st);
+                    const double* npart, int nparts, GmState* gs, GmState* ghost, hipStream_t st);
 void gmres_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t st);
 void gmres_init(double beta, double* g, int m, hipStream_t st);
 

@@ -195,8 +195,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
         reduce_cols(part, mdb, 2 * (j + 1), h2, st);
       }
       multi_axpy<S>(n, V, ldv, j + 1, h2, -1.0, w, w, part, st);
-      reduce_cols(part, rdb, 1, nrm, st);
-      arnoldi_finish(j, m, H, g, cs, sn, h1, h2, nrm, gs, slot_dev[j & 1], st);
+      arnoldi_finish(j, m, H, g, cs, sn, h1, h2, part, rdb, gs, slot_dev[j & 1], st);
       hipError_t e1 = hipEventRecord(ev[j & 1], st);
       if (e1 != hipSuccess) return hip_fail(e1, "gmres: status event");
       scale_dev<S>(n, w, &gs->inv_hn, w, st);

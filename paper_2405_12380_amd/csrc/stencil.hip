@@ -1,7 +1,8 @@
 // Stencil kernels of the discrete Helmholtz operator (§2 eq. 1) and of the
 // point relaxations of eq. 2 (damped Jacobi, red-black Gauss-Seidel).
 //
-// Mapping: a workgroup is 64 x 4 threads, lanes along x (a wavefront reads
+// Mapping: a workgroup is 64 x ty threads (ty = 4, or 8 on large grids),
+// lanes along x (a wavefront reads
 // one contiguous 1 KiB (complex128) row segment per load), 4 rows in y, and
 // each thread marches over `zb` consecutive z-planes keeping the z-1, z, z+1
 // values of its column in registers, so every node is loaded from HBM once;
@@ -49,20 +50,33 @@ __global__ void k_build_codes(int dim, int nx, int ny, int nz, const uint8_t* __
 __device__ __forceinline__ double2 sel0(bool absent, double2 v) { return absent ? czero() : v; }
 
 static int stencil_blocks(const StencilGeom& g) {
-  const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = (g.nz + g.zb - 1) / g.zb;
+  const int nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty, nbz = (g.nz + g.zb - 1) / g.zb;
   return nbx * nby * nbz;
 }
 
+// Output store: non-temporal (streaming, not kept in L2/MALL) when the grid is
+// far larger than the caches, so neighbour rows stay resident.
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stc_out(double2* p, size_t i, double2 v, bool nt) {
+  if (nt) __builtin_nontemporal_store(dv2{v.x, v.y}, reinterpret_cast<dv2*>(p + i));
+  else p[i] = v;
+}
+__device__ __forceinline__ void stc_out(float2* p, size_t i, double2 v, bool nt) {
+  if (nt) __builtin_nontemporal_store(fv2{(float)v.x, (float)v.y}, reinterpret_cast<fv2*>(p + i));
+  else p[i] = make_float2((float)v.x, (float)v.y);
+}
+
 template <typename S, int DIM, int MODE>
-__global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const cplx_t<S>* __restrict__ sc,
+__global__ __launch_bounds__(512) void k_stencil(StencilGeom g, const cplx_t<S>* __restrict__ sc,
                                                  const uint8_t* __restrict__ code, const cplx_t<S>* x,
                                                  const cplx_t<S>* __restrict__ f, cplx_t<S>* y,
                                                  double omega, int color, double* __restrict__ partials) {
   const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
-  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4;
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
   const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
   const int i = bx * 64 + threadIdx.x;
-  const int j = by * 4 + threadIdx.y;
+  const int j = by * g.ty + threadIdx.y;
   const int z0 = bz * g.zb;
   const int z1 = min(g.nz, z0 + g.zb);
   const bool active = (i < g.nx) && (j < g.ny);
@@ -107,16 +121,16 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const cplx_t<S>*
           ax = csub(acc, cmul(sp, c));
         }
         if (MODE == ST_APPLY) {
-          stc(y, p, ax);
+          stc_out(y, p, ax, g.nt);
         } else if (MODE == ST_RESID) {
           const double2 r = csub(fp, ax);
           nrm += r.x * r.x + r.y * r.y;
-          stc(y, p, r);
-        } else {  // Jacobi / RB-GS update
+          stc_out(y, p, r, g.nt);
+        } else {  // Jacobi / RB-GS update (red-black updates in place: plain stores)
           const double2 r = csub(fp, ax);
           const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
           const double2 q = cdiv(r, d);
-          stc(y, p, make_double2(c.x + omega * q.x, c.y + omega * q.y));
+          stc_out(y, p, make_double2(c.x + omega * q.x, c.y + omega * q.y), MODE == ST_JACOBI && g.nt);
         }
       }
       if (DIM == 3) {
@@ -126,13 +140,17 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const cplx_t<S>*
     }
   }
   if (MODE == ST_RESID) {
-    // deterministic per-block partial of ||r||^2
+    // deterministic per-block partial of ||r||^2 (one value per row-wavefront)
     __shared__ double shr[16];
     const int t = threadIdx.x + 64 * threadIdx.y;
     double v = wave_sum(nrm);
     if ((t & 63) == 0) shr[t >> 6] = v;
     __syncthreads();
-    if (t == 0) partials[lb] = (shr[0] + shr[1]) + (shr[2] + shr[3]);
+    if (t == 0) {
+      double a = 0.0;
+      for (int w = 0; w < g.ty; ++w) a += shr[w];
+      partials[lb] = a;
+    }
   }
 }
 
@@ -148,14 +166,14 @@ __device__ __forceinline__ double2 jac0(double2 f, double2 s, double dsum, bool 
 }
 
 template <typename S, int DIM>
-__global__ __launch_bounds__(256) void k_jacobi2z(StencilGeom g, const cplx_t<S>* __restrict__ sc,
+__global__ __launch_bounds__(512) void k_jacobi2z(StencilGeom g, const cplx_t<S>* __restrict__ sc,
                                                   const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ f,
                                                   cplx_t<S>* __restrict__ y, double omega) {
   const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
-  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4;
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
   const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
   const int i = bx * 64 + threadIdx.x;
-  const int j = by * 4 + threadIdx.y;
+  const int j = by * g.ty + threadIdx.y;
   const int z0 = bz * g.zb;
   const int z1e = min(g.nz, z0 + g.zb);
   if (!(i < g.nx && j < g.ny) || z0 >= z1e) return;
@@ -214,10 +232,10 @@ void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   kprof_begin(st);
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_jacobi2z<S, 3>), dim3(nb), dim3(64, 4), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
+    hipLaunchKernelGGL((k_jacobi2z<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
                        omega);
   else
-    hipLaunchKernelGGL((k_jacobi2z<S, 2>), dim3(nb), dim3(64, 4), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
+    hipLaunchKernelGGL((k_jacobi2z<S, 2>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
                        omega);
   kprof_end(KP_STENCIL, n * (3 * esz + 1), st);
 }
@@ -262,9 +280,14 @@ StencilGeom make_geom(int dim, const int n[3], int zb) {
     g.ih2[a] = 1.0 / (h * h);
     g.dsum += 2.0 * g.ih2[a];
   }
+  // taller tiles (fewer y-halo re-reads) on large grids; 64 x 4 keeps enough
+  // workgroups on small ones
+  const size_t nn = (size_t)g.nx * g.ny * g.nz;
+  g.ty = (g.ny >= 128 && nn >= ((size_t)1 << 22)) ? 8 : 4;
+  g.nt = nn >= ((size_t)1 << 23);
   if (zb <= 0) {
     // enough blocks to fill 256 CUs several times over, long z-marches otherwise
-    const long nxy = (long)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+    const long nxy = (long)((g.nx + 63) / 64) * ((g.ny + g.ty - 1) / g.ty);
     long target = 2048;
     zb = (int)((nxy * g.nz) / target);
     if (zb < 1) zb = 1;
@@ -287,7 +310,7 @@ template <typename S, int MODE>
 static void launch_mode(const StencilGeom& g, const void* sc, const uint8_t* code, const void* x, const void* f,
                         void* y, double omega, int color, double* part, hipStream_t st) {
   using C = cplx_t<S>;
-  dim3 blk(64, 4);
+  dim3 blk(64, g.ty);
   const int nb = stencil_blocks(g);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   // algorithmic bytes: x, s, the code byte, y (+ f); a red-black colour pass is half a sweep
