@@ -17,5 +17,6 @@ krylov     restarted GMRES(m) with CGS2 and BiCGStab, right-preconditioned  (§3
 deeponet   MLP branch/trunk networks and the DeepONet output head         (App. B)
 coarse     trunk-basis prolongation, QR, Galerkin coarse matrix, M2     (App. C)
 meta       relaxation meta-solver (eq. 3) and the Krylov preconditioner (§3.1.2, App. C)
+adjoint    receiver misfit and its k^2 gradient by the conjugate-transpose solve  (§2 eq. 1)
 """
-from . import operator, krylov, deeponet, coarse, meta  # noqa: F401
+from . import operator, krylov, deeponet, coarse, meta, adjoint  # noqa: F401

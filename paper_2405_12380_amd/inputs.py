@@ -214,3 +214,50 @@ def random_problem(n, seed: int, mask_frac: float = 0.05, k=None) -> dict:
     f = g.uniform(-1, 1, shp) + 1j * g.uniform(-1, 1, shp)
     return dict(n=tuple(n), k=k, ksq=np.full(shp, k * k), alpha=sponge(n), mask=mask,
                 x=x.astype(np.complex128), f=f.astype(np.complex128))
+
+
+def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: float = 0.05,
+            trunk_gain: float = 30.0) -> dict:
+    """Adjoint case: homogeneous k = 20, 8-cell sponge, submarine-like scatterer
+    (capsule along x plus sail), plane wave incident from the top.
+
+    * The incident wave is a sheet source of real unit amplitude per unit area
+      (value 1/h_z) on the first z-plane below the top sponge (index
+      n_z - 1 - SPONGE_WIDTH), zeroed on the scatterer; it radiates a plane
+      wave travelling in -z, the upward half being absorbed by the sponge.
+    * Receivers: the x-plane nearest x = 0.9 (``receiver = (axis 0, index)``).
+    * ``ksq_true = k^2 (1 + perturb g)`` with g a GRF (l = 0.2) scaled to
+      max |g| = 1: the medium that generates the synthetic data.
+    * The network is config 2's (same weights stream).
+    """
+    g = rng_for(5, instance)
+    n = tuple(int(v) for v in n)
+    shp = field_shape(n)
+    mask = capsule_sail_mask(n)
+    alpha = sponge(n)
+    ksq = np.full(shp, k * k)
+    f = np.zeros(shp, dtype=np.complex128)
+    zs = n[2] - 1 - SPONGE_WIDTH if len(n) == 3 else n[1] - 1 - SPONGE_WIDTH
+    f[zs] = float(n[-1] + 1)
+    f[mask.astype(bool)] = 0
+    pert = grf(n, 0.2, g)
+    pert /= np.max(np.abs(pert))
+    ksq_true = ksq * (1.0 + perturb * pert)
+    rx = int(min(max(round(0.9 * (n[0] + 1)) - 1, 0), n[0] - 1))
+    w = np.random.default_rng([2405, 3, 0])
+    branch = glorot_mlp([2 * 16 ** 3 + 1, 256, 256, 256, 256, 256], w)
+    trunk = glorot_mlp([3, 256, 256, 256, 256, 128], w, first_gain=trunk_gain)
+    return dict(n=n, k=k, ksq=ksq, alpha=alpha, mask=mask, f=f, ksq_true=ksq_true, receiver=(0, rx),
+                source_plane=zs, branch=branch, trunk=trunk, head="split_output", p=128,
+                branch_grid=(16, 16, 16), k_input=True)
+
+
+def directions(n, count: int, instance: int = 0, length: float = 0.2) -> list:
+    """Seeded smooth perturbation directions for finite-difference checks of a
+    k^2 gradient: GRFs (length scale ``length``) scaled to max |v| = 1."""
+    g = rng_for(55, instance)
+    out = []
+    for _ in range(count):
+        v = grf(tuple(n), length, g)
+        out.append(v / np.max(np.abs(v)))
+    return out

@@ -1,0 +1,114 @@
+"""Pins of the adjoint-gradient oracle (k^2 gradient of a receiver misfit,
+§2 eq. 1 differentiated): sparse assembly against the node-by-node dense
+matrix, the adjoint identity through the operator's apply, the gradient
+against brute-force central differences at every node of a tiny grid, and
+the special cases (exact data, masked nodes)."""
+import numpy as np
+import pytest
+
+from paper_2405_12380_amd import inputs as I
+from oracle import adjoint as adj, operator as op
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")
+
+
+def _tiny(n=(5, 5, 5), seed=0):
+    g = np.random.default_rng([7, seed])
+    shp = I.field_shape(n)
+    ksq = g.uniform(60.0, 140.0, shp)
+    alpha = g.uniform(0.0, 1.0, shp)             # nonzero everywhere: the (1 + i alpha) factor matters
+    mask = (g.random(shp) < 0.15).astype(np.uint8)
+    f = g.standard_normal(shp) + 1j * g.standard_normal(shp)
+    f[mask.astype(bool)] = 0
+    return ksq, alpha, mask, f, g
+
+
+@pytest.mark.parametrize("n", [(5, 4, 3), (6, 5)])
+def test_sparse_matches_dense_definition(n):
+    ksq, alpha, mask, f, _ = _tiny(n)
+    s = op.coefficient(ksq, alpha)
+    A = adj.sparse(s, mask).toarray()
+    assert np.abs(A - op.dense(s, mask)).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_solve_residual_and_adjoint_identity():
+    ksq, alpha, mask, f, g = _tiny((6, 5, 4))
+    s = op.coefficient(ksq, alpha)
+    u = adj.solve(s, mask, f)
+    assert np.linalg.norm(op.residual(u, f, s, mask)) <= 1e-12 * np.linalg.norm(f)
+    # A^H lam = b  <=>  lam^H (A x) = b^H x for every x (apply is pinned separately)
+    b = g.standard_normal(f.shape) + 1j * g.standard_normal(f.shape)
+    lam = adj.adjoint_solve(s, mask, b)
+    for _ in range(3):
+        x = g.standard_normal(f.shape) + 1j * g.standard_normal(f.shape)
+        lhs = np.vdot(lam, op.apply(x, s, mask))
+        rhs = np.vdot(b, x)
+        assert abs(lhs - rhs) <= 1e-11 * abs(rhs)
+
+
+def test_trans_h_solve_matches_explicit_adjoint():
+    ksq, alpha, mask, f, g = _tiny((5, 5, 4), seed=1)
+    d = g.standard_normal((4, 5)) + 1j * g.standard_normal((4, 5))
+    L, grad, u, lam = adj.loss_and_gradient(ksq, alpha, mask, f, d, 0, 3)
+    _, gvec = adj.misfit(u, d, 0, 3, mask)
+    lam2 = adj.adjoint_solve(op.coefficient(ksq, alpha), mask, gvec)
+    assert np.abs(lam - lam2).max() <= 1e-12 * np.abs(lam2).max()
+
+
+@pytest.mark.parametrize("axis,index", [(0, 3), (1, 1), (2, 2)])
+def test_gradient_brute_force_every_node(axis, index):
+    """Central differences of L at every node against the adjoint gradient."""
+    ksq, alpha, mask, f, g = _tiny((5, 5, 5), seed=2 + axis)
+    plane = adj.observe(np.zeros(f.shape), axis, index).shape
+    d = 0.01 * (g.standard_normal(plane) + 1j * g.standard_normal(plane))
+    L, grad, u, lam = adj.loss_and_gradient(ksq, alpha, mask, f, d, axis, index)
+    eps = 1e-3
+    fd = np.zeros_like(ksq)
+    for p in np.ndindex(ksq.shape):
+        kp = ksq.copy(); kp[p] += eps
+        km = ksq.copy(); km[p] -= eps
+        fd[p] = (adj.loss(kp, alpha, mask, f, d, axis, index) - adj.loss(km, alpha, mask, f, d, axis, index)) / (2 * eps)
+    assert np.all(grad[mask.astype(bool)] == 0) and np.all(np.abs(fd[mask.astype(bool)]) <= 1e-12)
+    assert np.abs(fd - grad).max() <= 1e-6 * np.abs(grad).max()
+
+
+def test_exact_data_gives_zero_loss_and_gradient():
+    ksq, alpha, mask, f, _ = _tiny((5, 5, 5), seed=5)
+    u = adj.solve(op.coefficient(ksq, alpha), mask, f)
+    d = adj.observe(u, 2, 1)
+    L, grad, _, _ = adj.loss_and_gradient(ksq, alpha, mask, f, d, 2, 1)
+    assert L == 0.0 and np.all(grad == 0)
+
+
+def test_observe_and_misfit_against_loops():
+    g = np.random.default_rng(11)
+    u = g.standard_normal((3, 4, 5)) + 1j * g.standard_normal((3, 4, 5))   # (z, y, x)
+    mask = np.zeros(u.shape, np.uint8); mask[1, 2, 3] = 1
+    for axis, index in [(0, 3), (1, 2), (2, 1)]:
+        P = adj.observe(u, axis, index)
+        for (l, j, i), v in np.ndenumerate(u):
+            ijl = (i, j, l)
+            if ijl[axis] != index:
+                continue
+            rest = [c for a, c in enumerate(ijl) if a != axis]      # x-fastest among the remaining axes
+            assert P[rest[1], rest[0]] == v
+        d = g.standard_normal(P.shape) + 1j * g.standard_normal(P.shape)
+        L, gv = adj.misfit(u, d, axis, index, mask)
+        r = P - d
+        assert abs(L - 0.5 * np.sum(np.abs(r) ** 2)) <= 1e-12 * L
+        # the masked node (x=3, y=2, z=1) lies on each of these planes: g is 0 there only
+        assert gv[1, 2, 3] == 0
+        assert np.count_nonzero(gv) == P.size - 1
+
+
+def test_config5_layout():
+    C = I.config5(n=(32, 32, 32))
+    assert C["receiver"] == (0, adj.plane_index(32, 0.9)) == (0, 29)
+    assert adj.plane_index(128, 0.9) == 115
+    zs = C["source_plane"]
+    # first plane below the top sponge: alpha = 0 in its middle, > 0 one plane up
+    assert zs == 23 and C["alpha"][zs, 16, 16] == 0 and C["alpha"][zs + 1, 16, 16] > 0
+    assert np.all(C["f"][C["mask"].astype(bool)] == 0)
+    assert np.count_nonzero(C["f"]) == np.count_nonzero(C["f"][zs]) == 32 * 32 - int(C["mask"][zs].sum())
+    rel = C["ksq_true"] / C["ksq"] - 1
+    assert abs(np.abs(rel).max() - 0.05) <= 1e-12
