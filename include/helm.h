@@ -217,6 +217,41 @@ helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* r
                              size_t ac_cap, void* Q, size_t q_cap, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Adjoint: k^2 gradient of a receiver misfit (§2 eq. 1 differentiated)     */
+/* ------------------------------------------------------------------------ */
+
+/* Solve the conjugate-transpose system A^H lam = g with the meta-solver of
+ * opts o (same kinds, options, statuses and stats as meta_solve; rel_res is
+ * ||g - A^H lam|| / ||g||).  A is complex symmetric, so the call runs
+ * meta_solve on conj(g) and conjugates the iterate: the preconditioner acting
+ * on the adjoint system is M built from A^H, and a cached coarse space of the
+ * op is reused.  lam holds the initial guess on entry and the last iterate on
+ * exit; g and lam are complex fields of the op's dtype and must not alias.
+ * Uses one op-owned field of scratch.  Synchronous. */
+helm_status meta_solve_adjoint(helm_op op, don_net net, const meta_opts* o, const void* g, void* lam,
+                               meta_stats* st, void* stream);
+
+/* Receiver misfit on the grid plane {i_axis = index} (axis 0 = x, 1 = y,
+ * 2 = z):  r = P u - d,  loss = 1/2 ||r||_2^2,  g = P^T r with g = 0 on
+ * scatterer nodes (u is 0 there; the loss does not depend on them) and off
+ * the plane.  d: device array of the plane's values, complex in the op's
+ * dtype, ordered with the remaining axes in x-fastest order (axis 0: y
+ * fastest then z; axis 1: x then z; axis 2: x then y; a 2D grid's plane is a
+ * line).  g: complex field, overwritten.  If loss is non-NULL the call waits
+ * for the stream and stores the loss (host double); otherwise async.
+ * Errors: HELM_E_INVAL for NULL pointers, an axis outside the grid, an
+ * index outside [0, n[axis]), or g aliasing u or d. */
+helm_status helm_misfit(helm_op op, int axis, int index, const void* u, const void* d, void* g, double* loss,
+                        void* stream);
+
+/* Pointwise k^2 gradient of a loss L(u) with A(k^2) u = f, given the adjoint
+ * state A^H lam = dL/du:  grad_p = Re(conj(lam_p) (1 + i alpha_p) u_p), and 0
+ * on scatterer nodes (their identity rows carry no k^2).  grad: real device
+ * array of n in the dtype's precision (double for C128, float for C64); it
+ * must not alias u or lam.  Async. */
+helm_status helm_ksq_gradient(helm_op op, const void* u, const void* lam, void* grad, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement hook                                                          */
 /* ------------------------------------------------------------------------ */
 

@@ -197,6 +197,7 @@ void helm_destroy(helm_op op) {
   op->tmp.release();
   op->part.release();
   op->ws.release();
+  op->adj.release();
   delete op;
 }
 

@@ -82,6 +82,8 @@ template <typename S>
 void copy_vec(size_t n, const void* x, void* y, hipStream_t st);
 template <typename S>
 void zero_vec(size_t n, void* x, hipStream_t st);
+template <typename S>
+void conj_vec(size_t n, const void* x, void* y, hipStream_t st);  // y = conj(x); x == y allowed
 
 // BiCGStab fused updates (scalars live on the device in a BiState)
 struct BiState {

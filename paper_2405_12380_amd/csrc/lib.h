@@ -67,6 +67,7 @@ struct helm_op_s {
   helm::Buffer tmp;          // one field: Jacobi ping-pong
   helm::Buffer part;         // reduction partials
   helm::Buffer ws;           // solver workspace
+  helm::Buffer adj;          // one field: the conjugated right-hand side of an adjoint solve
   helm::Coarse coarse;
 };
 

@@ -514,6 +514,34 @@ helm_status meta_solve(helm_op op, don_net net, const meta_opts* o, const void* 
                              : meta_dispatch<float>(op, net, o, f, u, st, hs);
 }
 
+helm_status meta_solve_adjoint(helm_op op, don_net net, const meta_opts* o, const void* g, void* lam, meta_stats* st,
+                               void* stream) {
+  if (!op || !g || !lam || !st) return fail(HELM_E_INVAL, "meta_solve_adjoint: NULL argument");
+  if (g == lam) return fail(HELM_E_INVAL, "meta_solve_adjoint: g and lam alias");
+  helm_status s = check_opts(op, net, o);
+  if (s) return s;
+  std::memset(st, 0, sizeof *st);
+  hipStream_t hs = (hipStream_t)stream;
+  if ((s = op->adj.ensure(op->nn * op_esz(op)))) return s;
+  // A is complex symmetric, so A^H lam = g  <=>  A conj(lam) = conj(g): the same
+  // solver (and its cached coarse space) on conjugated data.  The preconditioner
+  // this applies to the adjoint system is conj(M(conj(.))), i.e. M built from A^H.
+  const bool c128 = op->dt == HELM_C128;
+  if (c128) {
+    conj_vec<double>(op->nn, g, op->adj.ptr, hs);
+    conj_vec<double>(op->nn, lam, lam, hs);
+    s = meta_dispatch<double>(op, net, o, op->adj.ptr, lam, st, hs);
+    conj_vec<double>(op->nn, lam, lam, hs);
+  } else {
+    conj_vec<float>(op->nn, g, op->adj.ptr, hs);
+    conj_vec<float>(op->nn, lam, lam, hs);
+    s = meta_dispatch<float>(op, net, o, op->adj.ptr, lam, st, hs);
+    conj_vec<float>(op->nn, lam, lam, hs);
+  }
+  helm_status s2 = sync_stream(hs, "meta_solve_adjoint");
+  return s ? s : s2;
+}
+
 helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void* r, void* z, void* stream) {
   if (!op || !r || !z) return fail(HELM_E_INVAL, "meta_precond: NULL argument");
   if (r == z) return fail(HELM_E_INVAL, "meta_precond: r and z alias");

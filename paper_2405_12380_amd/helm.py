@@ -36,7 +36,8 @@ META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
 
 EXPORTED = ["helm_setup", "helm_set_ksq", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
-            "meta_solve", "meta_precond", "meta_coarse_info", "helm_kprof_enable", "helm_kprof_read",
+            "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "helm_misfit",
+            "helm_ksq_gradient", "helm_kprof_enable", "helm_kprof_read",
             "helm_strerror", "helm_last_error"]
 KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY, KP_CGS = 0, 1, 2, 3, 4, 5
 KP_NAMES = {KP_STENCIL: "stencil", KP_MULTIDOT: "multidot", KP_MULTIAXPY: "multi_axpy", KP_QT: "qt_part",
@@ -83,6 +84,9 @@ _sig = {
     "meta_precond": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), _vp, _vp, _vp]),
     "meta_coarse_info": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
                                    C.c_size_t, _vp, C.c_size_t, _vp]),
+    "meta_solve_adjoint": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), _vp, _vp, C.POINTER(MetaStats), _vp]),
+    "helm_misfit": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
+    "helm_ksq_gradient": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "helm_kprof_enable": (C.c_int, [C.c_int]),
     "helm_kprof_read": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "helm_strerror": (C.c_char_p, [C.c_int]),
@@ -191,6 +195,21 @@ class Op:
                "helm_relax")
         return u
 
+    def misfit(self, axis: int, index: int, u, d, g=None, loss=True, stream=None):
+        """(1/2 ||P u - d||^2 or None, g = P^T (P u - d)) on the plane {i_axis = index}."""
+        g = self.field() if g is None else g
+        lv = C.c_double()
+        _check(_lib.helm_misfit(self.h, int(axis), int(index), _ptr(u), _ptr(d), _ptr(g),
+                                C.byref(lv) if loss else None, _stream(stream)), "helm_misfit")
+        return (lv.value if loss else None), g
+
+    def ksq_gradient(self, u, lam, grad=None, stream=None):
+        """Re(conj(lam) (1 + i alpha) u), 0 on the scatterer (real field)."""
+        if grad is None:
+            grad = torch.empty(self.size, dtype=rdtype(self.dtype), device="cuda")
+        _check(_lib.helm_ksq_gradient(self.h, _ptr(u), _ptr(lam), _ptr(grad), _stream(stream)), "helm_ksq_gradient")
+        return grad
+
     def dot(self, x, y, stream=None) -> complex:
         out = (C.c_double * 2)()
         _check(_lib.helm_dot(self.h, _ptr(x), _ptr(y), out, _stream(stream)), "helm_dot")
@@ -262,15 +281,16 @@ def _opts(kind, restart=50, tol=1e-6, max_iters=20000, smoother="jacobi", n_r=3,
                     int(nn_every), int(pu), float(k), hp, 1 if q_fp32 else 0)
 
 
-def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, stream=None, **kw):
-    """Run ``meta_solve``; returns (status, stats dict[, history array]).  u is
-    updated in place.  Status HELM_NOT_CONVERGED is returned, not raised."""
+def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, stream=None, adjoint=False, **kw):
+    """Run ``meta_solve`` (``meta_solve_adjoint`` for A^H u = f when adjoint is
+    set); returns (status, stats dict[, history array]).  u is updated in
+    place.  Status HELM_NOT_CONVERGED is returned, not raised."""
     hist = np.zeros(int(kw.get("max_iters", 20000)) + 2) if history else None
     o = _opts(kind, history=hist, net=net, **kw)
     st = MetaStats()
-    s = _lib.meta_solve(op.h, net.h if net is not None else None, C.byref(o), _ptr(f), _ptr(u), C.byref(st),
-                        _stream(stream))
-    _check(s, "meta_solve", allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    fn, name = (_lib.meta_solve_adjoint, "meta_solve_adjoint") if adjoint else (_lib.meta_solve, "meta_solve")
+    s = fn(op.h, net.h if net is not None else None, C.byref(o), _ptr(f), _ptr(u), C.byref(st), _stream(stream))
+    _check(s, name, allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
     stats = {name: getattr(st, name) for name, _ in MetaStats._fields_}
     stats["status"] = s
     if history:

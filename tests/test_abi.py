@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ["helm_setup", "helm_apply", "helm_relax", "meta_solve", "deeponet_infer", "deeponet_load",
                  "helm_residual", "helm_dot", "helm_nrm2", "meta_precond", "meta_coarse_info", "helm_destroy",
-                 "deeponet_free", "helm_strerror", "helm_last_error", "helm_set_ksq", "helm_size"]:
+                 "deeponet_free", "helm_strerror", "helm_last_error", "helm_set_ksq", "helm_size",
+                 "meta_solve_adjoint", "helm_misfit", "helm_ksq_gradient"]:
         assert must in names
 
 
@@ -78,6 +79,9 @@ def test_null_handles_rejected():
     assert lib.helm_relax(None, 0, C.c_double(0.5), 1, None, None, None) == -1
     assert lib.meta_solve(None, None, None, None, None, None, None) == -1
     assert lib.deeponet_infer(None, None, 0, None, C.c_double(0.0), None, None) == -1
+    assert lib.meta_solve_adjoint(None, None, None, None, None, None, None) == -1
+    assert lib.helm_misfit(None, 0, 0, None, None, None, None, None) == -1
+    assert lib.helm_ksq_gradient(None, None, None, None, None) == -1
     lib.helm_size.restype = C.c_size_t
     assert lib.helm_size(None) == 0
     lib.helm_destroy(None)

@@ -1,0 +1,195 @@
+"""GPU parity of the adjoint row: the conjugate-transpose meta-solve, the
+receiver misfit, the pointwise k^2 gradient, and the gradient of the whole
+chain (forward meta-solve, misfit, adjoint meta-solve) against the oracle's
+sparse-LU gradient and against central finite differences of the GPU loss.
+
+The oracle's adjoint system is built from conj(s): A(conj s) = A(s)^H is
+pinned entry by entry on the CPU, so forced-count parity compares the GPU's
+conjugated solve with Krylov iterations run on A^H itself."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2405_12380_amd import inputs as I
+from oracle import operator as op_or, meta as meta_or, deeponet as don_or, coarse as co_or, adjoint as adj_or
+from tests.helpers import make_op, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+helm = pytest.importorskip("paper_2405_12380_amd.helm")
+from paper_2405_12380_amd import adjoint as AD  # noqa: E402
+
+
+def _net(C, dtype):
+    return helm.DeepONet(dtype, C["branch"], C["trunk"], C["p"], head="split_output", branch_grid=(16, 16, 16),
+                         k_input=True)
+
+
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+@pytest.mark.parametrize("kind,iters", [("gmres", 12), ("bicgstab", 6)])
+def test_adjoint_forced_count_parity(kind, iters, dtype):
+    """DeepONet-Krylov on A^H lam = g at a forced count against the oracle's
+    iterations on A(conj s) with the preconditioner built from A(conj s)."""
+    C = I.config2(1, n=(16, 16, 16))
+    s = op_or.coefficient(C["ksq"], C["alpha"])
+    op = make_op(helm, C, dtype)
+    net = _net(C, dtype)
+    g = np.random.default_rng(21)
+    rhs = g.standard_normal(C["f"].shape) + 1j * g.standard_normal(C["f"].shape)
+    rhs[C["mask"].astype(bool)] = 0
+    if dtype == helm.C64:
+        rhs = rhs.astype(np.complex64).astype(np.complex128)
+    sH = np.conj(s)
+    T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
+    cs = co_or.CoarseSpace(T, sH, C["mask"], 64, q_round="f32" if dtype == helm.C64 else None,
+                           tau=co_or.TAU_C128 if dtype == helm.C128 else co_or.TAU_C64)
+    M = meta_or.krylov_preconditioner(sH, C["mask"], "jacobi", 3, 0.5, cs)
+    lam_or, _ = meta_or.krylov_meta(kind, rhs, np.zeros_like(rhs), sH, C["mask"], 50, 0.0, iters, precond=M)
+    lam = op.field()
+    st, stats = helm.meta_solve(op, net, op.field(rhs), lam, kind=kind, restart=50, tol=0.0, max_iters=iters, n_r=3,
+                                omega=0.5, p_used=64, adjoint=True)
+    assert stats["iters"] == iters and stats["rank_used"] == cs.rank
+    assert rel_err(to_np(lam), lam_or) <= (1e-10 if dtype == helm.C128 else 2e-4)
+
+
+def test_adjoint_solve_against_sparse_lu():
+    """Standalone GMRES on A^H to 1e-12 against the oracle's LU of A^H, with a
+    nonzero initial guess (it is conjugated in and out)."""
+    P = I.random_problem((12, 10, 9), seed=4)
+    s = op_or.coefficient(P["ksq"], P["alpha"])
+    op = make_op(helm, P, helm.C128)
+    g = P["f"].copy()
+    g[P["mask"].astype(bool)] = 0
+    lam_ref = adj_or.adjoint_solve(s, P["mask"], g)
+    lam = op.field(0.1 * P["x"] * (1 - P["mask"]))
+    st, stats = helm.meta_solve(op, None, op.field(g), lam, kind="gmres", restart=60, tol=1e-12, max_iters=20000,
+                                adjoint=True)
+    assert st == helm.OK and stats["rel_res"] <= 1e-12
+    assert rel_err(to_np(lam), lam_ref) <= 1e-8
+
+
+@pytest.mark.parametrize("n", [(9, 7, 6), (11, 8)])
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+def test_misfit_and_gradient_kernels(n, dtype):
+    P = I.random_problem(n, seed=7)
+    op = make_op(helm, P, dtype)
+    g = np.random.default_rng(5)
+    u = P["x"] * (1 - P["mask"])
+    lam = g.standard_normal(u.shape) + 1j * g.standard_normal(u.shape)
+    if dtype == helm.C64:
+        u = u.astype(np.complex64).astype(np.complex128)
+        lam = lam.astype(np.complex64).astype(np.complex128)
+    tol = 1e-14 if dtype == helm.C128 else 1e-6
+    for axis in range(len(n)):
+        for index in (0, n[axis] // 2, n[axis] - 1):
+            plane = adj_or.observe(u, axis, index)
+            d = g.standard_normal(plane.shape) + 1j * g.standard_normal(plane.shape)
+            if dtype == helm.C64:
+                d = d.astype(np.complex64).astype(np.complex128)
+            L_or, g_or = adj_or.misfit(u, d, axis, index, P["mask"])
+            L, gv = op.misfit(axis, index, op.field(u), op.field(d.ravel()))
+            assert abs(L - L_or) <= tol * L_or
+            assert rel_err(to_np(gv), g_or) <= tol
+    gr = op.ksq_gradient(op.field(u), op.field(lam))
+    gr_or = adj_or.ksq_gradient(lam, u, P["alpha"], P["mask"])
+    assert rel_err(to_np(gr), gr_or) <= tol
+    assert np.all(to_np(gr)[P["mask"].ravel().astype(bool)] == 0)
+
+
+def test_misfit_argument_errors():
+    P = I.random_problem((6, 5, 4), seed=1)
+    op = make_op(helm, P, helm.C128)
+    u = op.field(P["x"])
+    d = op.field(np.zeros(20))
+    for axis, index in [(3, 0), (-1, 0), (0, 6), (2, -1)]:
+        with pytest.raises(helm.HelmError):
+            op.misfit(axis, index, u, d)
+    with pytest.raises(helm.HelmError):
+        op.misfit(0, 0, u, d, g=u)
+
+
+def _adjoint_case(n):
+    C = I.config5(n=(n, n, n))
+    s_true = op_or.coefficient(C["ksq_true"], C["alpha"])
+    axis, index = C["receiver"]
+    d = adj_or.observe(adj_or.solve(s_true, C["mask"], C["f"]), axis, index)
+    return C, d, axis, index
+
+
+@pytest.fixture(scope="module")
+def case32():
+    C, d, axis, index = _adjoint_case(32)
+    L_or, grad_or, u_or, lam_or = adj_or.loss_and_gradient(C["ksq"], C["alpha"], C["mask"], C["f"], d, axis, index)
+    return C, d, axis, index, L_or, grad_or
+
+
+def _solver(C, dtype=helm.C128, tol=1e-11, kind="gmres"):
+    op = make_op(helm, C, dtype)
+    net = _net(C, dtype)
+    return AD.Solver(op, net, kind=kind, restart=50, tol=tol, max_iters=20000, n_r=3, omega=0.5, p_used=128,
+                     k=C["k"])
+
+
+@pytest.mark.parametrize("kind", ["gmres", "bicgstab"])
+def test_gradient_against_oracle_32(case32, kind):
+    """Whole chain at 32^3 (capsule + sail, k = 20, plane wave from the top):
+    autograd through the forward meta-solve and the misfit, backward by the
+    adjoint meta-solve, against the oracle's sparse-LU gradient."""
+    C, d, axis, index, L_or, grad_or = case32
+    sv = _solver(C, kind=kind)
+    ksq = torch.tensor(C["ksq"].ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+    f = sv.op.field(C["f"])
+    u = AD.solve(ksq, f, sv)
+    L = AD.misfit(u, sv.op.field(d.ravel()), sv.op, axis, index)
+    L.backward()
+    assert abs(L.item() - L_or) <= 1e-8 * L_or
+    gr = to_np(ksq.grad).reshape(C["ksq"].shape)
+    assert np.all(gr[C["mask"].astype(bool)] == 0)
+    assert np.abs(gr - grad_or).max() <= 1e-6 * np.abs(grad_or).max()
+    assert [st["adjoint"] for st in sv.stats] == [False, True]
+
+
+def test_gradient_finite_differences_16_directions():
+    """<dL/dk^2, v> against central differences of the GPU loss on 16 seeded
+    smooth directions (step 1e-3 k^2 in max norm)."""
+    C, d, axis, index = _adjoint_case(24)
+    sv = _solver(C, tol=1e-12)
+    dd = sv.op.field(d.ravel())
+    f = sv.op.field(C["f"])
+    ksq0 = torch.tensor(C["ksq"].ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+    L = AD.misfit(AD.solve(ksq0, f, sv), dd, sv.op, axis, index)
+    L.backward()
+    grad = ksq0.grad.detach()
+    eps = 1e-3 * float(C["ksq"].max())
+    worst = 0.0
+    for v in I.directions(C["n"], 16):
+        vt = torch.tensor(v.ravel(), dtype=torch.float64, device="cuda")
+        with torch.no_grad():
+            Lp = AD.misfit(AD.solve(ksq0.detach() + eps * vt, f, sv), dd, sv.op, axis, index).item()
+            Lm = AD.misfit(AD.solve(ksq0.detach() - eps * vt, f, sv), dd, sv.op, axis, index).item()
+        fd = (Lp - Lm) / (2 * eps)
+        an = float(torch.dot(grad, vt))
+        worst = max(worst, abs(fd - an) / abs(an))
+    assert worst <= 1e-4, worst
+
+
+def test_source_gradient_is_the_adjoint_state():
+    """dL/df = lam: L is quadratic in f, so a central difference along any
+    direction is exact up to solver error."""
+    C, d, axis, index = _adjoint_case(16)
+    sv = _solver(C, tol=1e-12)
+    ksq = torch.tensor(C["ksq"].ravel(), dtype=torch.float64, device="cuda")
+    f = sv.op.field(C["f"]).requires_grad_(True)
+    dd = sv.op.field(d.ravel())
+    L = AD.misfit(AD.solve(ksq, f, sv), dd, sv.op, axis, index)
+    L.backward()
+    g = np.random.default_rng(3)
+    v = g.standard_normal(C["f"].shape) + 1j * g.standard_normal(C["f"].shape)
+    v[C["mask"].astype(bool)] = 0
+    vt = sv.op.field(v)
+    eps = 1e-3 * float(np.abs(C["f"]).max())
+    with torch.no_grad():
+        Lp = AD.misfit(AD.solve(ksq, f.detach() + eps * vt, sv), dd, sv.op, axis, index).item()
+        Lm = AD.misfit(AD.solve(ksq, f.detach() - eps * vt, sv), dd, sv.op, axis, index).item()
+    an = float(torch.real(torch.vdot(f.grad, vt)))
+    assert abs((Lp - Lm) / (2 * eps) - an) <= 1e-6 * abs(an)

@@ -112,3 +112,13 @@ def test_config5_layout():
     assert np.count_nonzero(C["f"]) == np.count_nonzero(C["f"][zs]) == 32 * 32 - int(C["mask"][zs].sum())
     rel = C["ksq_true"] / C["ksq"] - 1
     assert abs(np.abs(rel).max() - 0.05) <= 1e-12
+
+
+def test_conjugated_coefficient_is_the_adjoint_matrix():
+    """A(conj s) = A(s)^H entry by entry: the operator built from conj(s) is the
+    adjoint system the GPU adjoint solves are compared with."""
+    ksq, alpha, mask, f, _ = _tiny((5, 4, 3), seed=9)
+    s = op.coefficient(ksq, alpha)
+    A = adj.sparse(s, mask)
+    AH = adj.sparse(np.conj(s), mask)
+    assert abs(AH - A.conj().T).max() == 0
