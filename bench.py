@@ -74,6 +74,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle Arnoldi steps timed for the CPU baseline")
     ap.add_argument("--q-fp32", action="store_true", help="headline solves store the trunk basis in fp32")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
+    ap.add_argument("--adjoint-n", type=int, default=128, help="grid nodes per axis of the adjoint workload")
+    ap.add_argument("--adjoint-fd", type=int, default=2,
+                    help="finite-difference directions checked against the adjoint gradient")
     ap.add_argument("--pmc-run", action="store_true",
                     help="for counter collection: one headline solve plus a device copy of known size "
                          "(a 256^3 complex128 field, 268,435,456 B read and written), then exit")
@@ -221,11 +225,76 @@ def main():
         log(f"stencil bandwidth at {args.stencil_n}^3")
         out["stencil"] = stencil_bandwidth(helm, I, torch, dev, args.stencil_n)
 
+    if not args.no_adjoint:
+        log(f"adjoint gradient at {args.adjoint_n}^3")
+        out["adjoint"] = adjoint_gradient(helm, I, torch, dev, args.adjoint_n, args.adjoint_fd)
+
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(insts[0]["host"], out["iters_mean"], args.cpu_iters)
 
     print(json.dumps(out), flush=True)
+
+
+def adjoint_gradient(helm, I, torch, dev, N, fd_dirs):
+    """k^2 gradient of the receiver misfit (capsule + sail, k = 20, plane wave
+    from the top): forward DeepONet-BiCGStab to 1e-8, misfit, adjoint
+    DeepONet-BiCGStab to 1e-8 and the pointwise gradient, timed as one step
+    (coarse-space setup for the new k^2 included); the synthetic data come from
+    a forward solve in the perturbed medium, which also serves as warm-up.  A
+    few finite-difference directions (solves to 1e-10) check the result."""
+    from paper_2405_12380_amd import adjoint as AD
+    C = I.config5(n=(N, N, N))
+    dt = helm.C128
+    op = helm.Op(C["n"], dt, C["ksq"], C["alpha"], C["mask"])
+    net = helm.DeepONet(dt, C["branch"], C["trunk"], C["p"], head="split_output", branch_grid=(16, 16, 16),
+                        k_input=True)
+    sv = AD.Solver(op, net, kind="bicgstab", tol=1e-8, max_iters=20000, n_r=3, omega=0.5, p_used=128, k=C["k"])
+    axis, index = C["receiver"]
+    f = op.field(C["f"])
+    with torch.no_grad():
+        kt = torch.as_tensor(C["ksq_true"].ravel()).to(dev)
+        u_true = AD.solve(kt, f, sv)
+        d = u_true.reshape(N, N, N)[:, :, index].contiguous().reshape(-1)   # plane x = index: y fastest, z slowest
+    ksq_host = torch.as_tensor(C["ksq"].ravel()).to(dev)
+
+    def one():
+        sv.stats.clear()
+        ksq = ksq_host.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = AD.solve(ksq, f, sv)
+        L = AD.misfit(u, d, op, axis, index)
+        L.backward()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, L.item(), ksq.grad.detach(), list(sv.stats)
+
+    ms, L, grad, st = one()
+    fwd, adj = st
+    res = {"grid": [N, N, N], "k": C["k"], "sponge_width": C["sponge_width"], "solver": "deeponet_bicgstab",
+           "receivers": int(d.numel()), "ms": round(ms, 2), "loss": L,
+           "forward": {"iters": fwd["iters"], "setup_ms": round(fwd["setup_ms"], 2), "solve_ms": round(fwd["solve_ms"], 2),
+                       "rel_res": fwd["rel_res"]},
+           "adjoint": {"iters": adj["iters"], "setup_ms": round(adj["setup_ms"], 2), "solve_ms": round(adj["solve_ms"], 2),
+                       "rel_res": adj["rel_res"]},
+           "grad_max": float(grad.abs().max())}
+    log(f"adjoint step {ms:.1f} ms, forward {fwd['iters']} / adjoint {adj['iters']} iterations")
+    if fd_dirs:
+        eps = 1e-3 * float(C["ksq"].max())
+        sv.opts["tol"] = 1e-10
+        errs = []
+        for v in I.directions(C["n"], fd_dirs):
+            vt = torch.as_tensor(v.ravel()).to(dev)
+            with torch.no_grad():
+                Lp = AD.misfit(AD.solve(ksq_host + eps * vt, f, sv), d, op, axis, index).item()
+                Lm = AD.misfit(AD.solve(ksq_host - eps * vt, f, sv), d, op, axis, index).item()
+            an = float(torch.dot(grad, vt))
+            errs.append(abs((Lp - Lm) / (2 * eps) - an) / abs(an))
+            log(f"finite difference {len(errs)}: rel err {errs[-1]:.2e}")
+        res["fd_check"] = {"directions": fd_dirs, "step": eps, "max_rel_err": max(errs)}
+    op.close()
+    net.close()
+    return res
 
 
 def stencil_bandwidth(helm, I, torch, dev, N, reps=40):

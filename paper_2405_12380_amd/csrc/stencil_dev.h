@@ -1,0 +1,192 @@
+// Device bodies of the stencil kernels (§2 eq. 1, §3.1.1 eq. 2), shared by the
+// single-grid kernels and the batched ones: a workgroup of 64 x ty threads
+// handles logical tile lb of a geometry (the mapping and the fixed per-node
+// arithmetic are described in stencil.hip).
+#pragma once
+
+#include "common.h"
+#include "internal.h"
+
+namespace helm {
+
+enum { ST_APPLY = 0, ST_JACOBI = 1, ST_RESID = 2, ST_RBGS = 3 };
+
+// Neighbour code of a node (built once per op): bit 0 = the node is masked;
+// bits 1..6 = its x-, x+, y-, y+, z-, z+ neighbour is absent (ghost or masked)
+// and contributes 0.  One byte replaces seven mask reads per node, and lets
+// every neighbour load be issued unconditionally (clamped inside the grid).
+enum { NB_SELF = 1, NB_XM = 2, NB_XP = 4, NB_YM = 8, NB_YP = 16, NB_ZM = 32, NB_ZP = 64 };
+
+__device__ __forceinline__ double2 sel0(bool absent, double2 v) { return absent ? czero() : v; }
+
+// Output store: non-temporal (streaming, not kept in L2/MALL) when the grid is
+// far larger than the caches, so neighbour rows stay resident.
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stc_out(double2* p, size_t i, double2 v, bool nt) {
+  if (nt) __builtin_nontemporal_store(dv2{v.x, v.y}, reinterpret_cast<dv2*>(p + i));
+  else p[i] = v;
+}
+__device__ __forceinline__ void stc_out(float2* p, size_t i, double2 v, bool nt) {
+  if (nt) __builtin_nontemporal_store(fv2{(float)v.x, (float)v.y}, reinterpret_cast<fv2*>(p + i));
+  else p[i] = make_float2((float)v.x, (float)v.y);
+}
+
+// One workgroup's tile: logical block lb of geometry g.  RESID writes the
+// block's partial of ||r||^2 to *partial.
+template <typename S, int DIM, int MODE>
+__device__ __forceinline__ void stencil_tile(const StencilGeom& g, unsigned lb, const cplx_t<S>* __restrict__ sc,
+                                             const uint8_t* __restrict__ code, const cplx_t<S>* x,
+                                             const cplx_t<S>* __restrict__ f, cplx_t<S>* y, double omega, int color,
+                                             double* __restrict__ partial) {
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
+  const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+  const int i = bx * 64 + threadIdx.x;
+  const int j = by * g.ty + threadIdx.y;
+  const int z0 = bz * g.zb;
+  const int z1 = min(g.nz, z0 + g.zb);
+  const bool active = (i < g.nx) && (j < g.ny);
+  const size_t plane = (size_t)g.nx * g.ny;
+  // clamped neighbour offsets (an absent neighbour is read from the node itself
+  // and then replaced by 0 through the code bits)
+  const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
+  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
+  double nrm = 0.0;
+  if (active && z0 < z1) {
+    size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
+    double2 c = ldc(x, p);
+    double2 zm = czero();
+    if (DIM == 3 && z0 > 0) zm = ldc(x, p - plane);
+    for (int z = z0; z < z1; ++z, p += plane) {
+      double2 znext = czero();
+      if (DIM == 3 && z + 1 < g.nz) znext = ldc(x, p + plane);
+      const bool upd = (MODE != ST_RBGS) || (((i + j + z) & 1) == color);
+      if (upd) {
+        const unsigned cd = code[p];
+        const double2 xm = ldc(x, p + oxm), xp = ldc(x, p + oxp);
+        const double2 ym = ldc(x, p + oym), yp = ldc(x, p + oyp);
+        const double2 sp = ldc(sc, p);
+        double2 fp = czero();
+        if (MODE != ST_APPLY) fp = ldc(f, p);
+        double2 ax;
+        if (cd & NB_SELF) {
+          ax = c;
+        } else {
+          const double2 a = sel0(cd & NB_XM, xm), b = sel0(cd & NB_XP, xp);
+          const double2 e = sel0(cd & NB_YM, ym), h = sel0(cd & NB_YP, yp);
+          double2 acc;
+          acc.x = ((c.x - a.x) + (c.x - b.x)) * g.ih2[0];
+          acc.y = ((c.y - a.y) + (c.y - b.y)) * g.ih2[0];
+          acc.x = acc.x + ((c.x - e.x) + (c.x - h.x)) * g.ih2[1];
+          acc.y = acc.y + ((c.y - e.y) + (c.y - h.y)) * g.ih2[1];
+          if (DIM == 3) {
+            const double2 q = sel0(cd & NB_ZM, zm), w = sel0(cd & NB_ZP, znext);
+            acc.x = acc.x + ((c.x - q.x) + (c.x - w.x)) * g.ih2[2];
+            acc.y = acc.y + ((c.y - q.y) + (c.y - w.y)) * g.ih2[2];
+          }
+          ax = csub(acc, cmul(sp, c));
+        }
+        if (MODE == ST_APPLY) {
+          stc_out(y, p, ax, g.nt);
+        } else if (MODE == ST_RESID) {
+          const double2 r = csub(fp, ax);
+          nrm += r.x * r.x + r.y * r.y;
+          stc_out(y, p, r, g.nt);
+        } else {  // Jacobi / RB-GS update (red-black updates in place: plain stores)
+          const double2 r = csub(fp, ax);
+          const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
+          const double2 q = cdiv(r, d);
+          stc_out(y, p, make_double2(c.x + omega * q.x, c.y + omega * q.y), MODE == ST_JACOBI && g.nt);
+        }
+      }
+      if (DIM == 3) {
+        zm = c;
+        c = znext;
+      }
+    }
+  }
+  if (MODE == ST_RESID) {
+    // deterministic per-block partial of ||r||^2 (one value per row-wavefront)
+    __shared__ double shr[16];
+    const int t = threadIdx.x + 64 * threadIdx.y;
+    double v = wave_sum(nrm);
+    if ((t & 63) == 0) shr[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      double a = 0.0;
+      for (int w = 0; w < g.ty; ++w) a += shr[w];
+      *partial = a;
+    }
+  }
+}
+
+// Two damped Jacobi sweeps on A z = f started from z = 0, in one pass:
+// z1 = omega D^{-1} f is formed on the fly at the node and its neighbours (f and
+// s re-read from cache), then z2 = z1 + omega D^{-1} (f - A z1).  The per-node
+// arithmetic is that of two separate sweeps; the HBM traffic is that of one
+// (f, s, code in; z2 out).
+__device__ __forceinline__ double2 jac0(double2 f, double2 s, double dsum, bool masked, double omega) {
+  const double2 d = masked ? make_double2(1.0, 0.0) : make_double2(dsum - s.x, -s.y);
+  const double2 q = cdiv(f, d);
+  return make_double2(omega * q.x, omega * q.y);
+}
+
+template <typename S, int DIM>
+__device__ __forceinline__ void jacobi2z_tile(const StencilGeom& g, unsigned lb, const cplx_t<S>* __restrict__ sc,
+                                              const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ f,
+                                              cplx_t<S>* __restrict__ y, double omega) {
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
+  const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+  const int i = bx * 64 + threadIdx.x;
+  const int j = by * g.ty + threadIdx.y;
+  const int z0 = bz * g.zb;
+  const int z1e = min(g.nz, z0 + g.zb);
+  if (!(i < g.nx && j < g.ny) || z0 >= z1e) return;
+  const size_t plane = (size_t)g.nx * g.ny;
+  const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
+  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
+  size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
+  // z1 of the column at z-1, z (the z-1 value only matters when present)
+  double2 zc = jac0(ldc(f, p), ldc(sc, p), g.dsum, code[p] & NB_SELF, omega);
+  double2 zmv = czero();
+  if (DIM == 3 && z0 > 0) zmv = jac0(ldc(f, p - plane), ldc(sc, p - plane), g.dsum, false, omega);
+  for (int z = z0; z < z1e; ++z, p += plane) {
+    double2 znv = czero();
+    if (DIM == 3 && z + 1 < g.nz) znv = jac0(ldc(f, p + plane), ldc(sc, p + plane), g.dsum, false, omega);
+    const unsigned cd = code[p];
+    const double2 fp = ldc(f, p), sp = ldc(sc, p);
+    double2 ax;
+    if (cd & NB_SELF) {
+      ax = zc;
+    } else {
+      const double2 a = (cd & NB_XM) ? czero() : jac0(ldc(f, p + oxm), ldc(sc, p + oxm), g.dsum, false, omega);
+      const double2 b = (cd & NB_XP) ? czero() : jac0(ldc(f, p + oxp), ldc(sc, p + oxp), g.dsum, false, omega);
+      const double2 e = (cd & NB_YM) ? czero() : jac0(ldc(f, p + oym), ldc(sc, p + oym), g.dsum, false, omega);
+      const double2 h = (cd & NB_YP) ? czero() : jac0(ldc(f, p + oyp), ldc(sc, p + oyp), g.dsum, false, omega);
+      double2 acc;
+      acc.x = ((zc.x - a.x) + (zc.x - b.x)) * g.ih2[0];
+      acc.y = ((zc.y - a.y) + (zc.y - b.y)) * g.ih2[0];
+      acc.x = acc.x + ((zc.x - e.x) + (zc.x - h.x)) * g.ih2[1];
+      acc.y = acc.y + ((zc.y - e.y) + (zc.y - h.y)) * g.ih2[1];
+      if (DIM == 3) {
+        const double2 q = (cd & NB_ZM) ? czero() : zmv, w = (cd & NB_ZP) ? czero() : znv;
+        acc.x = acc.x + ((zc.x - q.x) + (zc.x - w.x)) * g.ih2[2];
+        acc.y = acc.y + ((zc.y - q.y) + (zc.y - w.y)) * g.ih2[2];
+      }
+      ax = csub(acc, cmul(sp, zc));
+    }
+    const double2 r = csub(fp, ax);
+    const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
+    const double2 q = cdiv(r, d);
+    stc(y, p, make_double2(zc.x + omega * q.x, zc.y + omega * q.y));
+    if (DIM == 3) {
+      zmv = zc;
+      zc = znv;
+      // the next node's own z1 needs its own mask bit; recompute if it is masked
+      if (z + 1 < z1e && (code[p + plane] & NB_SELF))
+        zc = jac0(ldc(f, p + plane), ldc(sc, p + plane), g.dsum, true, omega);
+    }
+  }
+}
+
+}  // namespace helm

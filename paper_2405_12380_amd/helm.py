@@ -162,7 +162,7 @@ class Op:
         self.size = int(_lib.helm_size(h))
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.helm_destroy(self.h)
             self.h = None
 
@@ -251,7 +251,8 @@ class DeepONet:
 
     def close(self):
         if getattr(self, "h", None):
-            _lib.deeponet_free(self.h)
+            if _lib is not None:
+                _lib.deeponet_free(self.h)
             self.h = None
 
     __del__ = close

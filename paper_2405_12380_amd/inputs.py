@@ -218,12 +218,16 @@ def random_problem(n, seed: int, mask_frac: float = 0.05, k=None) -> dict:
 
 def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: float = 0.05,
             trunk_gain: float = 30.0) -> dict:
-    """Adjoint case: homogeneous k = 20, 8-cell sponge, submarine-like scatterer
-    (capsule along x plus sail), plane wave incident from the top.
+    """Adjoint case: homogeneous k = 20, submarine-like scatterer (capsule
+    along x plus sail), plane wave incident from the top.
+
+    * The sponge is max(8, n_z / 8) cells wide: at least 8 cells and at least
+      1/8 of the domain (an 8-cell layer on a 128^3 grid is too thin to absorb
+      the k = 20 wave, and the solves stall on the reflections).
 
     * The incident wave is a sheet source of real unit amplitude per unit area
       (value 1/h_z) on the first z-plane below the top sponge (index
-      n_z - 1 - SPONGE_WIDTH), zeroed on the scatterer; it radiates a plane
+      n_z - 1 - width), zeroed on the scatterer; it radiates a plane
       wave travelling in -z, the upward half being absorbed by the sponge.
     * Receivers: the x-plane nearest x = 0.9 (``receiver = (axis 0, index)``).
     * ``ksq_true = k^2 (1 + perturb g)`` with g a GRF (l = 0.2) scaled to
@@ -234,10 +238,11 @@ def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: floa
     n = tuple(int(v) for v in n)
     shp = field_shape(n)
     mask = capsule_sail_mask(n)
-    alpha = sponge(n)
+    width = max(SPONGE_WIDTH, n[-1] // 8)
+    alpha = sponge(n, width=width)
     ksq = np.full(shp, k * k)
     f = np.zeros(shp, dtype=np.complex128)
-    zs = n[2] - 1 - SPONGE_WIDTH if len(n) == 3 else n[1] - 1 - SPONGE_WIDTH
+    zs = n[-1] - 1 - width
     f[zs] = float(n[-1] + 1)
     f[mask.astype(bool)] = 0
     pert = grf(n, 0.2, g)
@@ -248,7 +253,7 @@ def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: floa
     branch = glorot_mlp([2 * 16 ** 3 + 1, 256, 256, 256, 256, 256], w)
     trunk = glorot_mlp([3, 256, 256, 256, 256, 128], w, first_gain=trunk_gain)
     return dict(n=n, k=k, ksq=ksq, alpha=alpha, mask=mask, f=f, ksq_true=ksq_true, receiver=(0, rx),
-                source_plane=zs, branch=branch, trunk=trunk, head="split_output", p=128,
+                source_plane=zs, sponge_width=width, branch=branch, trunk=trunk, head="split_output", p=128,
                 branch_grid=(16, 16, 16), k_input=True)
 
 
