@@ -30,18 +30,22 @@ METRIC = "3D solve time to 1e-6 rel. residual (meta vs GMRES); stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # kernel class -> source file that defines its kernel (for the traffic record's validity)
-KERNEL_SOURCE = {"qt_part": "coarse.hip", "skinny_apply": "coarse.hip", "cgs_fused": "blas1.hip",
-                 "multidot": "blas1.hip", "multi_axpy": "blas1.hip", "stencil": "stencil.hip"}
+KERNEL_SOURCE = {"qt_part": ("coarse.hip", "coarse_dev.h"), "skinny_apply": ("coarse.hip", "coarse_dev.h"),
+                 "cgs_fused": ("blas1.hip",), "multidot": ("blas1.hip",), "multi_axpy": ("blas1.hip",),
+                 "stencil": ("stencil.hip", "stencil_dev.h")}
 
 
 def measured_traffic(kernel, grid_n):
     """HBM bytes per launch from the counter runs recorded in profiles/, if they
     were taken on the current source of that kernel; else None."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2405_12380_amd", "csrc", KERNEL_SOURCE.get(kernel, ""))
-    if not os.path.isfile(src):
+    srcs = [os.path.join(ROOT, "paper_2405_12380_amd", "csrc", f) for f in KERNEL_SOURCE.get(kernel, ())]
+    if not srcs or not all(os.path.isfile(f) for f in srcs):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()[:16]
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -75,6 +79,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle Arnoldi steps timed for the CPU baseline")
     ap.add_argument("--q-fp32", action="store_true", help="headline solves store the trunk basis in fp32")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched many-problem workload")
+    ap.add_argument("--batch-count", type=int, default=16,
+                    help="problems in the batched workload (the first ones of the 64-problem set)")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid nodes per axis of the adjoint workload")
     ap.add_argument("--adjoint-fd", type=int, default=2,
                     help="finite-difference directions checked against the adjoint gradient")
@@ -225,6 +232,10 @@ def main():
         log(f"stencil bandwidth at {args.stencil_n}^3")
         out["stencil"] = stencil_bandwidth(helm, I, torch, dev, args.stencil_n)
 
+    if not args.no_batch:
+        log(f"batched workload: {args.batch_count} problems")
+        out["batch"] = batched_solves(helm, I, torch, dev, args.batch_count)
+
     if not args.no_adjoint:
         log(f"adjoint gradient at {args.adjoint_n}^3")
         out["adjoint"] = adjoint_gradient(helm, I, torch, dev, args.adjoint_n, args.adjoint_fd)
@@ -234,6 +245,51 @@ def main():
         out["cpu_baseline"] = cpu_baseline(insts[0]["host"], out["iters_mean"], args.cpu_iters)
 
     print(json.dumps(out), flush=True)
+
+
+# algorithmic HBM bytes per node of one DeepONet-BiCGStab iteration (complex128,
+# n_r = 3 Jacobi, p = 128 fp64 basis): p-update 64; two preconditioner
+# applications of 2275 (Jacobi pair from zero 49, third sweep 65, residual 65,
+# Q^T r1 1040, z += Q c 1056); two stencils 49; r_hat^H v 32; s-update 48;
+# t^H s and t^H t 32; u/r update 128
+BICG_META_BYTES_PER_NODE = 64 + 2 * 2275 + 2 * 49 + 32 + 48 + 32 + 128
+
+
+def batched_solves(helm, I, torch, dev, count):
+    """Many independent problems (grids 48^3..128^3, k in [5, 25], cubes and
+    ellipsoids, GRF sources) solved together by DeepONet-BiCGStab to 1e-6 in
+    one batched launch sequence; throughput in solves/s, setup included."""
+    Ps = I.config4(count=count)   # the first `count` problems of the seeded stream
+    C0 = I.config2(0, n=(8, 8, 8))
+    dt = helm.C128
+    net = helm.DeepONet(dt, C0["branch"], C0["trunk"], C0["p"], head="split_output", branch_grid=(16, 16, 16),
+                        k_input=True)
+    ops = [helm.Op(P["n"], dt, P["ksq"], P["alpha"], P["mask"]) for P in Ps]
+    fs = [op.field(P["f"]) for op, P in zip(ops, Ps)]
+    us = [op.field() for op in ops]
+    del Ps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = helm.meta_solve_batch(ops, net, fs, us, kind="bicgstab", tol=1e-6, max_iters=20000, n_r=3,
+                                      omega=0.5, p_used=128)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = [op.size for op in ops]
+    iters = [s["iters"] for s in stats]
+    solve_ms = stats[0]["solve_ms"]
+    algo = sum(i * n for i, n in zip(iters, nodes)) * BICG_META_BYTES_PER_NODE
+    res = {"problems": count, "status": st, "converged": int(sum(s["converged"] for s in stats)),
+           "nodes_total": int(sum(nodes)), "grid_min": int(round(min(nodes) ** (1 / 3))),
+           "grid_max": int(round(max(nodes) ** (1 / 3))), "iters_min": min(iters), "iters_max": max(iters),
+           "iters_mean": float(np.mean(iters)), "rel_res_max": float(max(s["rel_res"] for s in stats)),
+           "setup_ms_total": round(float(sum(s["setup_ms"] for s in stats)), 2), "solve_ms": round(solve_ms, 2),
+           "wall_ms": round(wall * 1e3, 2), "solves_per_s": round(count / wall, 3),
+           "algorithmic_GBps": round(algo / (solve_ms * 1e-3) / 1e9, 1)}
+    log(f"batch: {res}")
+    for op in ops:
+        op.close()
+    net.close()
+    return res
 
 
 def adjoint_gradient(helm, I, torch, dev, N, fd_dirs):

@@ -216,6 +216,28 @@ helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void
 helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* rank, double* Ac,
                              size_t ac_cap, void* Q, size_t q_cap, void* stream);
 
+/* Solve `count` independent problems A_i u_i = f_i (§3.1.2: many grids, wave
+ * numbers, scatterers and sources at once) with BiCGStab, right-preconditioned
+ * as in meta_solve when net != NULL (M(r) = n_r Jacobi sweeps from zero, then
+ * the trunk-basis correction of App. C with p_used columns; M = I otherwise).
+ * o->kind must be META_BICGSTAB and o->smoother HELM_JACOBI; tol, max_iters,
+ * n_r, omega, p_used and q_fp32 apply to every problem; history is ignored.
+ * ops: `count` distinct ops of one dtype and dimension.  f[i], u[i]: complex
+ * fields of op i (u[i] holds u0 on entry, the last iterate on exit).
+ * st: array of `count` stats (solve_ms is the batch's wall time on the device).
+ * Every kernel of an iteration covers all problems and a problem's workgroups
+ * exit at once once it has stopped, so convergence is decided on the device;
+ * chunks of iterations are captured as one HIP graph on a library stream and
+ * replayed.  The coarse spaces are built (or reused) per op first, and their
+ * setup work buffers are released afterwards.  Device memory for ten complex
+ * fields per problem is allocated for the call.  Synchronous; the caller's
+ * stream is waited for before and after.
+ * Returns HELM_OK if every problem converged, else the most severe status
+ * (an error below 0, or HELM_NOT_CONVERGED); per-problem outcomes are in
+ * st[i].converged and st[i].rel_res.  HELM_E_INVAL for a bad argument. */
+helm_status meta_solve_batch(int count, const helm_op* ops, don_net net, const meta_opts* o,
+                             const void* const* f, void* const* u, meta_stats* st, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Adjoint: k^2 gradient of a receiver misfit (§2 eq. 1 differentiated)     */
 /* ------------------------------------------------------------------------ */

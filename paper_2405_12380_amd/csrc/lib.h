@@ -92,6 +92,10 @@ helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, hi
 template <typename S>
 helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st);  // z += Q A_c^-1 Q^T r1
 void coarse_release(helm_op_s* op);
+// Free the setup work buffers and the cached trunk matrix, keeping Q and A_c^{-1}.
+void coarse_trim(helm_op_s* op);
+// Validation of meta_opts against an op and a network (meta.hip).
+helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o);
 
 // ---- shared driver pieces ----
 template <typename S>

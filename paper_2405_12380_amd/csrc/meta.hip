@@ -474,7 +474,7 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
   return s;
 }
 
-static helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o) {
+helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o) {
   if (!o) return fail(HELM_E_INVAL, "meta: opts is NULL");
   if (o->kind < META_JACOBI || o->kind > META_BICGSTAB) return fail(HELM_E_INVAL, "meta: unknown kind %d", o->kind);
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(HELM_E_INVAL, "meta: tol must be finite and >= 0");

@@ -36,7 +36,7 @@ META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
 
 EXPORTED = ["helm_setup", "helm_set_ksq", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
-            "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "helm_misfit",
+            "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "meta_solve_batch", "helm_misfit",
             "helm_ksq_gradient", "helm_kprof_enable", "helm_kprof_read",
             "helm_strerror", "helm_last_error"]
 KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY, KP_CGS = 0, 1, 2, 3, 4, 5
@@ -85,6 +85,8 @@ _sig = {
     "meta_coarse_info": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
                                    C.c_size_t, _vp, C.c_size_t, _vp]),
     "meta_solve_adjoint": (C.c_int, [_vp, _vp, C.POINTER(MetaOpts), _vp, _vp, C.POINTER(MetaStats), _vp]),
+    "meta_solve_batch": (C.c_int, [C.c_int, C.POINTER(_vp), _vp, C.POINTER(MetaOpts), C.POINTER(_vp),
+                                   C.POINTER(_vp), C.POINTER(MetaStats), _vp]),
     "helm_misfit": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "helm_ksq_gradient": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "helm_kprof_enable": (C.c_int, [C.c_int]),
@@ -297,6 +299,25 @@ def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, 
     if history:
         return s, stats, hist[: st.history_len].copy()
     return s, stats
+
+
+def meta_solve_batch(ops, net: DeepONet | None, fs, us, stream=None, **kw):
+    """Run ``meta_solve_batch`` (BiCGStab over all problems at once); returns
+    (status, list of stats dicts).  us are updated in place."""
+    n = len(ops)
+    kw.setdefault("kind", "bicgstab")
+    o = _opts(net=net, **kw)
+    hops = (_vp * n)(*[op.h for op in ops])
+    hf = (_vp * n)(*[_ptr(f) for f in fs])
+    hu = (_vp * n)(*[_ptr(u) for u in us])
+    st = (MetaStats * n)()
+    s = _lib.meta_solve_batch(n, hops, net.h if net is not None else None, C.byref(o), hf, hu, st, _stream(stream))
+    _check(s, "meta_solve_batch", allow=(OK, NOT_CONVERGED, E_BREAKDOWN, E_NONFINITE))
+    out = []
+    for i in range(n):
+        d = {name: getattr(st[i], name) for name, _ in MetaStats._fields_}
+        out.append(d)
+    return s, out
 
 
 def meta_precond(op: Op, net: DeepONet | None, r, z=None, stream=None, **kw):

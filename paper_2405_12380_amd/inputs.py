@@ -19,6 +19,8 @@ Conventions (shared by every consumer):
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 SPONGE_WIDTH = 8
@@ -109,14 +111,16 @@ def gaussian_source(n, x0, sigma) -> np.ndarray:
     return np.exp(-r2 / (2.0 * sigma ** 2)).astype(np.complex128)
 
 
-def grf(n, length: float, rng: np.random.Generator) -> np.ndarray:
+def grf(n, length: float, rng: np.random.Generator, workers: int | None = None) -> np.ndarray:
     """Zero-mean, unit-variance Gaussian random field with covariance
     ``exp(-r^2 / (2 l^2))`` sampled at the grid's nodes.
 
     White noise on a periodic grid twice the size (same spacing) is convolved
     with ``exp(-|x|^2 / l^2)``; the autocorrelation of that kernel is the
     target covariance.  The result is divided by the kernel's l2 norm (the
-    exact standard deviation) and cropped to the interior nodes.
+    exact standard deviation) and cropped to the interior nodes.  With
+    ``workers`` the FFTs run multi-threaded (scipy.fft; the same field up to
+    rounding in the last bits).
     """
     h = [1.0 / (na + 1) for na in n]
     big = [2 * na for na in n]
@@ -130,16 +134,21 @@ def grf(n, length: float, rng: np.random.Generator) -> np.ndarray:
         s[len(n) - 1 - a] = na
         ker = ker * np.exp(-(d ** 2) / length ** 2).reshape(s)
     axes = list(range(len(shape)))
-    fld = np.fft.irfftn(np.fft.rfftn(noise, axes=axes) * np.fft.rfftn(ker, axes=axes), s=shape, axes=axes)
+    if workers:
+        import scipy.fft as sfft
+        fld = sfft.irfftn(sfft.rfftn(noise, axes=axes, workers=workers) * sfft.rfftn(ker, axes=axes, workers=workers),
+                          s=shape, axes=axes, workers=workers)
+    else:
+        fld = np.fft.irfftn(np.fft.rfftn(noise, axes=axes) * np.fft.rfftn(ker, axes=axes), s=shape, axes=axes)
     fld /= np.sqrt(np.sum(ker ** 2))
     sl = tuple(slice(0, na) for na in reversed(n))
     return np.ascontiguousarray(fld[sl])
 
 
-def complex_grf(n, length: float, rng: np.random.Generator) -> np.ndarray:
+def complex_grf(n, length: float, rng: np.random.Generator, workers: int | None = None) -> np.ndarray:
     """Re and Im drawn independently from the same field (App. B)."""
-    re = grf(n, length, rng)
-    im = grf(n, length, rng)
+    re = grf(n, length, rng, workers)
+    im = grf(n, length, rng, workers)
     return (re + 1j * im).astype(np.complex128)
 
 
@@ -214,6 +223,40 @@ def random_problem(n, seed: int, mask_frac: float = 0.05, k=None) -> dict:
     f = g.uniform(-1, 1, shp) + 1j * g.uniform(-1, 1, shp)
     return dict(n=tuple(n), k=k, ksq=np.full(shp, k * k), alpha=sponge(n), mask=mask,
                 x=x.astype(np.complex128), f=f.astype(np.complex128))
+
+
+def config4(count: int = 64, instance: int = 0, n_range=(48, 128), k_range=(5.0, 25.0)) -> list:
+    """Batched case: ``count`` independent cubic problems, n ~ U{48..128}
+    nodes per axis, homogeneous k ~ U[5, 25], a sponge of max(8, n / 8) cells
+    (as in ``config5``: at least 1/8 of the domain, so the k = 25 waves on the
+    finest grids are absorbed rather than reflected), a cube
+    (half-side ~ U[0.1, 0.3]) or an ellipsoid (semi-axes ~ U[0.1, 0.3]) with
+    probability 1/2 each, complex GRF source (l = 0.1) zeroed on the scatterer.
+
+    The centre is drawn per axis so that the scatterer stays out of the sponge
+    (nodes with index distance below the sponge width); where that interval is
+    empty the centre is 0.5."""
+    g = rng_for(4, instance)
+    out = []
+    for _ in range(count):
+        n1 = int(g.integers(n_range[0], n_range[1] + 1))
+        n = (n1, n1, n1)
+        k = float(g.uniform(*k_range))
+        ellipsoid = bool(g.random() < 0.5)
+        ext = g.uniform(0.1, 0.3, size=3) if ellipsoid else np.full(3, g.uniform(0.1, 0.3))
+        h = 1.0 / (n1 + 1)
+        width = max(SPONGE_WIDTH, n1 // 8)
+        lo_free, hi_free = (width + 1) * h, (n1 - width) * h
+        c = np.empty(3)
+        for a in range(3):
+            lo, hi = lo_free + ext[a], hi_free - ext[a]
+            c[a] = g.uniform(lo, hi) if lo < hi else 0.5
+        mask = ellipsoid_mask(n, c, ext) if ellipsoid else box_mask(n, c, ext[0])
+        f = complex_grf(n, 0.1, g, workers=min(os.cpu_count() or 1, 16))
+        f[mask.astype(bool)] = 0
+        out.append(dict(n=n, k=k, ksq=np.full(field_shape(n), k * k), alpha=sponge(n, width=width), mask=mask, f=f,
+                        shape="ellipsoid" if ellipsoid else "cube", center=c, extent=ext))
+    return out
 
 
 def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: float = 0.05,

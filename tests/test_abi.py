@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     for must in ["helm_setup", "helm_apply", "helm_relax", "meta_solve", "deeponet_infer", "deeponet_load",
                  "helm_residual", "helm_dot", "helm_nrm2", "meta_precond", "meta_coarse_info", "helm_destroy",
                  "deeponet_free", "helm_strerror", "helm_last_error", "helm_set_ksq", "helm_size",
-                 "meta_solve_adjoint", "helm_misfit", "helm_ksq_gradient"]:
+                 "meta_solve_adjoint", "helm_misfit", "helm_ksq_gradient", "meta_solve_batch"]:
         assert must in names
 
 
@@ -80,6 +80,7 @@ def test_null_handles_rejected():
     assert lib.meta_solve(None, None, None, None, None, None, None) == -1
     assert lib.deeponet_infer(None, None, 0, None, C.c_double(0.0), None, None) == -1
     assert lib.meta_solve_adjoint(None, None, None, None, None, None, None) == -1
+    assert lib.meta_solve_batch(0, None, None, None, None, None, None, None) == -1
     assert lib.helm_misfit(None, 0, 0, None, None, None, None, None) == -1
     assert lib.helm_ksq_gradient(None, None, None, None, None) == -1
     lib.helm_size.restype = C.c_size_t
