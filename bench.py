@@ -268,6 +268,13 @@ def batched_solves(helm, I, torch, dev, count):
     fs = [op.field(P["f"]) for op, P in zip(ops, Ps)]
     us = [op.field() for op in ops]
     del Ps
+    # stencil tiles autotuned per grid (one workgroup height for the whole batch)
+    ta = time.perf_counter()
+    tiles = {}
+    for op in ops:
+        ty, zb, _ = op.tune(fixed_ty=4)
+        tiles[f"{ty}x{zb}"] = tiles.get(f"{ty}x{zb}", 0) + 1
+    tune_ms = (time.perf_counter() - ta) * 1e3
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, stats = helm.meta_solve_batch(ops, net, fs, us, kind="bicgstab", tol=1e-6, max_iters=20000, n_r=3,
@@ -284,7 +291,8 @@ def batched_solves(helm, I, torch, dev, count):
            "iters_mean": float(np.mean(iters)), "rel_res_max": float(max(s["rel_res"] for s in stats)),
            "setup_ms_total": round(float(sum(s["setup_ms"] for s in stats)), 2), "solve_ms": round(solve_ms, 2),
            "wall_ms": round(wall * 1e3, 2), "solves_per_s": round(count / wall, 3),
-           "algorithmic_GBps": round(algo / (solve_ms * 1e-3) / 1e9, 1)}
+           "algorithmic_GBps": round(algo / (solve_ms * 1e-3) / 1e9, 1),
+           "tune_ms": round(tune_ms, 1), "tiles_ty_x_zb": tiles}
     log(f"batch: {res}")
     for op in ops:
         op.close()

@@ -90,6 +90,18 @@ void helm_destroy(helm_op op);
 /* Number of grid nodes of an op (0 for NULL). */
 size_t helm_size(helm_op op);
 
+/* Tile autotuner for the op's stencil kernels: times y = A x (8 launches after
+ * 2 warm-ups, HIP events on `stream`) for every workgroup height ty in {4, 8}
+ * (only fixed_ty when it is 4 or 8; 0 = free), z-march length zb in
+ * {1, 2, 4, 8, 16, 32} (<= n_z; 1 in 2D) and plain or non-temporal output
+ * stores, and keeps the fastest for all later stencil work on this op.  The
+ * per-node arithmetic does not depend on the tiling, so results of apply,
+ * relax and the sweeps are unchanged; reduction partials are regrouped.
+ * Outputs (each optional): the chosen ty and zb and its time per launch (us).
+ * Synchronous; uses op-owned scratch.  Do not call while a solve on the op is
+ * in flight. */
+helm_status helm_tune(helm_op op, int fixed_ty, void* stream, int* ty_out, int* zb_out, double* us_out);
+
 /* y = A x (§2 eq. 1 as above).  x, y: complex fields; must not alias.  Async. */
 helm_status helm_apply(helm_op op, const void* x, void* y, void* stream);
 

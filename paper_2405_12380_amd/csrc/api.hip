@@ -220,6 +220,72 @@ helm_status helm_residual(helm_op op, const void* f, const void* u, void* r, dou
                              : residual_norm<float>(op, f, u, r, rnorm, st);
 }
 
+helm_status helm_tune(helm_op op, int fixed_ty, void* stream, int* ty_out, int* zb_out, double* us_out) {
+  if (!op) return fail(HELM_E_INVAL, "helm_tune: NULL op");
+  if (fixed_ty != 0 && fixed_ty != 4 && fixed_ty != 8) return fail(HELM_E_INVAL, "helm_tune: tile height %d", fixed_ty);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t fld = op->nn * op_esz(op);
+  helm_status s;
+  if ((s = op->tmp.ensure(fld)) || (s = op->ws.ensure(fld))) return s;
+  void* x = op->tmp.ptr;
+  void* y = op->ws.ptr;
+  const bool c128 = op->dt == HELM_C128;
+  if (c128) zero_vec<double>(op->nn, x, st);
+  else zero_vec<float>(op->nn, x, st);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(HELM_E_HIP, "helm_tune: event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HELM_E_HIP, "helm_tune: event");
+  }
+  StencilGeom best = op->geom;
+  double best_us = INFINITY;
+  const int tys[2] = {4, 8};
+  const int zbs[6] = {1, 2, 4, 8, 16, 32};
+  for (int a = 0; a < 2; ++a) {
+    if (fixed_ty && tys[a] != fixed_ty) continue;
+    for (int b = 0; b < 6; ++b) {
+      if (op->dim == 2 && zbs[b] != 1) continue;
+      if (zbs[b] > op->geom.nz) continue;
+      for (int nt = 0; nt < 2; ++nt) {
+        StencilGeom g = op->geom;
+        g.ty = tys[a];
+        g.zb = zbs[b];
+        g.nt = nt != 0;
+        auto run = [&]() {
+          if (c128) stencil_apply<double>(g, op->sc, op->code, x, y, st);
+          else stencil_apply<float>(g, op->sc, op->code, x, y, st);
+        };
+        run();
+        run();
+        (void)hipEventRecord(e0, st);
+        for (int k = 0; k < 8; ++k) run();
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return launch_check("helm_tune");
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / 8;
+        if (us < best_us) {
+          best_us = us;
+          best = g;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if ((s = launch_check("helm_tune"))) return s;
+  op->geom = best;
+  if (ty_out) *ty_out = best.ty;
+  if (zb_out) *zb_out = best.zb;
+  if (us_out) *us_out = best_us;
+  return HELM_OK;
+}
+
 helm_status helm_relax(helm_op op, int kind, double omega, int sweeps, const void* f, void* u, void* stream) {
   if (!op || !f || !u) return fail(HELM_E_INVAL, "helm_relax: NULL argument");
   if (kind != HELM_JACOBI && kind != HELM_RBGS) return fail(HELM_E_INVAL, "helm_relax: unknown kind %d", kind);

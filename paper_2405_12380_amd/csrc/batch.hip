@@ -559,17 +559,18 @@ helm_status batch_drive(int np, helm_op_s* const* ops, don_s* net, const meta_op
     stats[i].rank_used = ops[i]->coarse.rank;
     stats[i].cond_Ac_est = ops[i]->coarse.cond_est;
   }
-  // problem descriptors; a uniform tile height for the batch
-  int ty = 4;
+  // problem descriptors; a uniform workgroup height for the batch: the ops'
+  // own (tuned) one when they agree, else 4
+  int ty = ops[0]->geom.ty;
+  for (int i = 1; i < np; ++i)
+    if (ops[i]->geom.ty != ty) ty = 4;
   std::vector<BProb> pr(np);
   size_t tot = 0;
   for (int i = 0; i < np; ++i) {
     BProb& q = pr[i];
     std::memset(&q, 0, sizeof q);
     q.g = ops[i]->geom;
-    if (q.g.ty != ty) {
-      q.g.ty = ty;
-    }
+    q.g.ty = ty;
     q.sc = ops[i]->sc;
     q.code = ops[i]->code;
     q.mask = ops[i]->mask;

@@ -34,7 +34,7 @@ DON_SPLIT_OUTPUT, DON_SPLIT_INPUT = 0, 1
 DON_TRUNK, DON_FULL = 0, 1
 META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
 
-EXPORTED = ["helm_setup", "helm_set_ksq", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
+EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
             "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "meta_solve_batch", "helm_misfit",
             "helm_ksq_gradient", "helm_kprof_enable", "helm_kprof_read",
@@ -70,6 +70,7 @@ _vp = C.c_void_p
 _sig = {
     "helm_setup": (C.c_int, [C.POINTER(HelmGrid), C.c_int, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "helm_set_ksq": (C.c_int, [_vp, _vp, _vp]),
+    "helm_tune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "helm_destroy": (None, [_vp]),
     "helm_size": (C.c_size_t, [_vp]),
     "helm_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
@@ -179,6 +180,13 @@ class Op:
     def set_ksq(self, ksq, stream=None):
         k = _dev(ksq, torch.float64)
         _check(_lib.helm_set_ksq(self.h, _ptr(k), _stream(stream)), "helm_set_ksq")
+
+    def tune(self, fixed_ty: int = 0, stream=None):
+        """Autotune the stencil tile (``helm_tune``); returns (ty, zb, us per apply)."""
+        ty, zb, us = C.c_int(), C.c_int(), C.c_double()
+        _check(_lib.helm_tune(self.h, int(fixed_ty), _stream(stream), C.byref(ty), C.byref(zb), C.byref(us)),
+               "helm_tune")
+        return ty.value, zb.value, us.value
 
     def apply(self, x, y=None, stream=None):
         y = self.field() if y is None else y

@@ -81,6 +81,7 @@ def test_null_handles_rejected():
     assert lib.deeponet_infer(None, None, 0, None, C.c_double(0.0), None, None) == -1
     assert lib.meta_solve_adjoint(None, None, None, None, None, None, None) == -1
     assert lib.meta_solve_batch(0, None, None, None, None, None, None, None) == -1
+    assert lib.helm_tune(None, 0, None, None, None, None) == -1
     assert lib.helm_misfit(None, 0, 0, None, None, None, None, None) == -1
     assert lib.helm_ksq_gradient(None, None, None, None, None) == -1
     lib.helm_size.restype = C.c_size_t

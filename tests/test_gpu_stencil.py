@@ -3,6 +3,7 @@ red-black Gauss-Seidel, and the Krylov inner products, against the oracle on
 the same seeded inputs.  Sizes span several 64 x 4 x zb tiles with ragged
 tails in every axis; the full-size cases check sampled nodes and invariants."""
 import numpy as np
+import torch
 import pytest
 
 from paper_2405_12380_amd import inputs as I
@@ -149,3 +150,25 @@ def test_invalid_arguments():
         op.relax(7, 0.5, 1, x, op.field())
     with pytest.raises(helm.HelmError):
         helm.Op((2, 8, 8), helm.C128, np.ones(128), np.zeros(128), np.zeros(128, np.uint8))
+
+
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+def test_tune_keeps_results(dtype):
+    """The autotuner changes only the tiling: apply and Jacobi sweeps stay
+    bit-identical, and the chosen tile is one of the candidates."""
+    P = I.random_problem((40, 36, 33), seed=12)
+    op = make_op(helm, P, dtype)
+    x = op.field(P["x"])
+    f = op.field(P["f"])
+    y0 = op.apply(x).clone()
+    u0 = x.clone()
+    op.relax(helm.JACOBI, 0.5, 3, f, u0)
+    ty, zb, us = op.tune()
+    assert ty in (4, 8) and zb in (1, 2, 4, 8, 16, 32) and zb <= 33 and us > 0
+    assert torch.equal(op.apply(x), y0)
+    u1 = x.clone()
+    op.relax(helm.JACOBI, 0.5, 3, f, u1)
+    assert torch.equal(u1, u0)
+    ty4, zb4, _ = op.tune(fixed_ty=4)
+    assert ty4 == 4
+    assert torch.equal(op.apply(x), y0)
