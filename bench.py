@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--q-fp32", action="store_true", help="headline solves store the trunk basis in fp32")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-problem workload")
+    ap.add_argument("--no-train", action="store_true", help="skip the DeepONet training workload")
+    ap.add_argument("--train-samples", type=int, default=1024, help="non-scattering 48^3 solves in the training set")
+    ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--batch-count", type=int, default=16,
                     help="problems in the batched workload (the first ones of the 64-problem set)")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid nodes per axis of the adjoint workload")
@@ -236,6 +239,10 @@ def main():
         log(f"batched workload: {args.batch_count} problems")
         out["batch"] = batched_solves(helm, I, torch, dev, args.batch_count)
 
+    if not args.no_train:
+        log(f"training workload: {args.train_samples} samples")
+        out["train"] = training(helm, I, torch, dev, args.train_samples, args.train_epochs)
+
     if not args.no_adjoint:
         log(f"adjoint gradient at {args.adjoint_n}^3")
         out["adjoint"] = adjoint_gradient(helm, I, torch, dev, args.adjoint_n, args.adjoint_fd)
@@ -296,6 +303,88 @@ def batched_solves(helm, I, torch, dev, count):
     log(f"batch: {res}")
     for op in ops:
         op.close()
+    net.close()
+    return res
+
+
+BF16_PEAK_TFLOPS = 2500.0  # dense bf16 MFMA, MI355X
+
+
+def train_flops_per_step(tr, S, P, nb, nt, p):
+    """Matrix-product flops of one training step (forward, loss products, backward)."""
+    f = 0
+    for which, M, nl in ((0, S, nb), (1, P, nt)):
+        for li in range(nl):
+            K, Kp, N, _, _ = tr.layout(which, li)
+            f += 2 * M * Kp * N          # forward
+            f += 2 * Kp * N * M          # dW
+            if li > 0:
+                f += 2 * M * N * Kp      # dH
+    f += 3 * 2 * (2 * S) * P * p         # Ut, dT, dBc
+    return f
+
+
+def training(helm, I, torch, dev, n_samples, epochs):
+    """DeepONet training (App. B, the 4x256 trunk, p = 128): labels from the
+    batched plain BiCGStab (to 1e-8) on non-scattering 48^3 problems, branch
+    inputs from the meta-solver's own sampling (DON_BRANCH_INPUT), then bf16
+    MFMA training with Adam (batch 64, lr 1e-3); 10% held out."""
+    n = (48, 48, 48)
+    P = 48 ** 3
+    dt = helm.C128
+    ks, alpha, f = I.config3(n_samples)
+    ops = [helm.Op(n, dt, np.full(P, k * k), alpha, np.zeros(P, np.uint8)) for k in ks]
+    fs = [f[i] for i in range(n_samples)]
+    us = [op.field() for op in ops]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, stats = helm.meta_solve_batch(ops, None, fs, us, kind="bicgstab", tol=1e-8, max_iters=20000)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    log(f"labels: {n_samples} solves in {label_s:.1f} s, iterations {min(s['iters'] for s in stats)}.."
+        f"{max(s['iters'] for s in stats)}, converged {sum(s['converged'] for s in stats)}")
+    w = np.random.default_rng([2405, 3, 1])
+    branch = I.glorot_mlp([2 * 16 ** 3 + 1, 256, 256, 256, 256, 256], w)
+    trunk = I.glorot_mlp([3, 256, 256, 256, 256, 128], w)
+    net = helm.DeepONet(dt, branch, trunk, 128, head="split_output", branch_grid=(16, 16, 16), k_input=True)
+    F = torch.empty((n_samples, 2 * 16 ** 3 + 1), dtype=torch.float64, device=dev)
+    for i in range(n_samples):
+        net.branch_input(ops[i], fs[i], k=float(ks[i]), out=F[i])
+    Y = torch.stack(us).to(torch.complex64)
+    for op in ops:
+        op.close()
+    del ops, us, fs, f
+    n_val = max(64, n_samples // 10)
+    n_train = n_samples - n_val
+    S = 64
+    steps = n_train // S
+    tr = helm.Trainer(net, I.node_points(n), batch=S, max_steps=max(steps, n_val // S), lr=1e-3)
+    tr.data(F.float(), Y)
+    del F
+    flops = train_flops_per_step(tr, S, P, 5, 5, 128)
+    rng = np.random.default_rng(7)
+    val_idx = np.arange(n_train, n_train + (n_val // S) * S)
+    ep = []
+    val0 = float(tr.eval(val_idx).mean())
+    for e in range(epochs):
+        idx = rng.permutation(n_train)[:steps * S]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        losses = tr.steps(idx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ta) * 1e3
+        ep.append({"ms": round(ms, 2), "loss_first": float(losses[0]), "loss_last": float(losses[-1])})
+        log(f"epoch {e}: {ms:.1f} ms, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    val = float(tr.eval(val_idx).mean())
+    step_ms = min(x["ms"] for x in ep) / steps
+    res = {"samples": n_samples, "train": n_train, "validation": int(len(val_idx)), "batch": S, "points": P,
+           "label_solves_s": round(label_s, 2), "label_iters_max": max(s["iters"] for s in stats),
+           "steps_per_epoch": steps, "epochs": ep, "ms_per_step": round(step_ms, 3),
+           "gemm_gflop_per_step": round(flops / 1e9, 2),
+           "mfma": {"achieved_tflops": round(flops / (step_ms * 1e-3) / 1e12, 1), "peak_tflops": BF16_PEAK_TFLOPS,
+                    "frac": round(flops / (step_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)},
+           "validation_rel_l2": {"before": val0, "after": val}}
+    tr.close()
     net.close()
     return res
 

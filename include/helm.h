@@ -135,7 +135,7 @@ enum { DON_TANH = 0, DON_RELU = 1, DON_LEAKY = 2 };
  * SPLIT_INPUT: the branch emits p values and is applied to Re and Im of the
  * input separately, N(r) = T branch(Re r) + i T branch(Im r). */
 enum { DON_SPLIT_OUTPUT = 0, DON_SPLIT_INPUT = 1 };
-enum { DON_TRUNK = 0, DON_FULL = 1 };
+enum { DON_TRUNK = 0, DON_FULL = 1, DON_BRANCH_INPUT = 2 };
 
 typedef struct {
   int n_branch;        /* number of widths in branch_w (layers + 1)                 */
@@ -163,9 +163,77 @@ void deeponet_free(don_net net);
  *            0 on masked nodes: the network correction M2 of eq. 3.  r and out
  *            are complex fields; the branch samples r/s on branch_grid (identity
  *            when it equals the op's grid, multilinear with zero ghosts otherwise).
+ * DON_BRANCH_INPUT: out = the branch's input vector for r (what DON_FULL feeds
+ *            its first branch layer: r/s sampled on branch_grid, Re then Im,
+ *            then k when k_input is set; for SPLIT_INPUT the Re and Im rows),
+ *            real in the dtype's precision — the training inputs of App. B.
  * k is the wave number fed to the branch when k_input is set.  Async. */
 helm_status deeponet_infer(don_net net, helm_op op, int mode, const void* r, double k, void* out,
                            void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* DeepONet training (App. B network; bf16 MFMA, fp32 accumulation)         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct don_trainer_s* don_trainer;
+
+typedef struct {
+  int n_points;    /* P: trunk evaluation points per sample (multiple of 32)        */
+  int batch;       /* S: samples per step (32, 64, 96 or 128)                       */
+  int max_steps;   /* capacity: most steps of one don_train_steps / don_train_eval  */
+  double lr, beta1, beta2, eps;  /* Adam                                            */
+} don_train_opts;
+
+/* Trainer for `net` (SPLIT_OUTPUT head, tanh; widths after each input multiples
+ * of 32 and <= 256).  It keeps fp32 master copies of the net's weights (input
+ * widths padded to multiples of 32 with zero rows), their bf16 copies, Adam's
+ * moments, and every activation of a step.  X: device array of P x d fp64 trunk
+ * inputs (node coordinates), copied.  One step on samples idx[0..S):
+ *   T = trunk(X), B = branch(F_idx), U_s = T B_s[:p] + i T B_s[p:],
+ *   L = mean_s ||U_s - Y_s|| / ||Y_s||, gradients by backpropagation, Adam
+ *   (Kingma & Ba) on the fp32 parameters.
+ * Every product runs as a bf16 MFMA GEMM with fp32 accumulation; tanh and its
+ * derivative, biases and the loss are fused or run in fp32 (norms in fp64). */
+helm_status don_train_create(don_net net, const don_train_opts* o, const double* X, don_trainer* out);
+
+/* The dataset: n samples; F: device fp32 n x K_b branch inputs (K_b = the
+ * net's branch input width), converted to padded bf16 (copied); Y: device
+ * complex64 n x P labels, sample-major — kept by pointer, so it must stay
+ * valid while the trainer uses it.  Synchronous. */
+helm_status don_train_data(don_trainer t, int n, const float* F, const void* Y);
+
+/* `count` Adam steps; step k uses samples idx[k S .. k S + S) (device int array,
+ * values in [0, n)).  A step is captured once as a HIP graph on the trainer's
+ * stream and replayed.  loss_out (optional host array of count floats): the
+ * loss of each step before its update.  Waits for `stream` first; synchronous. */
+helm_status don_train_steps(don_trainer t, int count, const int* idx, float* loss_out, void* stream);
+
+/* Losses of `count` batches (forward and backward, no update); loss_out: host
+ * array of count floats.  Synchronous. */
+helm_status don_train_eval(don_trainer t, int count, const int* idx, float* loss_out, void* stream);
+
+/* Loss (host float) and gradients (device fp32 array of don_train_nparam
+ * entries, the flat parameter layout) of one batch idx[0..S), no update. */
+helm_status don_train_grad(don_trainer t, const int* idx, float* loss, float* grads, void* stream);
+
+/* One Adam step with caller-provided gradients (device fp32, flat layout). */
+helm_status don_train_apply(don_trainer t, const float* grads, void* stream);
+
+/* Number of flat fp32 parameters (including padding), and the layout of layer
+ * `layer` of the branch (which = 0) or trunk (which = 1): true and padded input
+ * width, output width, offsets of W (Kp x N, row-major) and b (N). */
+size_t don_train_nparam(don_trainer t);
+helm_status don_train_layout(don_trainer t, int which, int layer, int* K, int* Kp, int* N, size_t* offW,
+                             size_t* offb);
+
+/* Copy the fp32 master parameters (flat layout) to a device array. */
+helm_status don_train_params(don_trainer t, float* out, void* stream);
+
+/* Write the trained weights back into `net` (its dtype); cached trunk matrices
+ * and coarse spaces built from the old weights are invalidated. */
+helm_status don_train_export(don_trainer t, don_net net, void* stream);
+
+void don_train_free(don_trainer t);
 
 /* ------------------------------------------------------------------------ */
 /* Meta-solvers (§3.1.1 eq. 3; §3.1.2 with the trunk basis of App. C)       */

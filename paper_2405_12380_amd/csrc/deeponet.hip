@@ -22,25 +22,13 @@
 #include "internal.h"
 #include "lib.h"
 
-struct don_s {
-  helm_dtype dt = HELM_C128;
-  int act = DON_TANH, head = DON_SPLIT_OUTPUT, p = 0, k_input = 0;
-  int bgrid[3] = {1, 1, 1};
-  std::vector<int> bw, tw;
-  std::vector<void*> bW, bB, tW, tB;
-  int serial = 0;
-  helm::Buffer act0, act1;  // branch activations (small) and trunk chunks
-  helm::Buffer tact0, tact1;
-  helm::Buffer part;
-  helm::Buffer coef;        // 2p doubles
-};
-
 namespace helm {
 
 static std::atomic<int> g_serial{1};
 
 int don_p(const don_s* net) { return net->p; }
 int don_serial(const don_s* net) { return net->serial; }
+void don_touch(don_s* net) { net->serial = g_serial.fetch_add(1); }
 
 static int map_act(int a) { return a == DON_TANH ? ACT_TANH : a == DON_RELU ? ACT_RELU : ACT_LEAKY; }
 
@@ -180,11 +168,12 @@ static bool same_grid(const don_s* net, const helm_op_s* op) {
 }
 
 template <typename T>
-static helm_status full_eval(don_s* net, helm_op_s* op, const void* r, double k, void* du, hipStream_t st) {
+static helm_status full_eval(don_s* net, helm_op_s* op, const void* r, double k, void* du, hipStream_t st,
+                             bool input_only = false) {
   const size_t n = op->nn;
   Coarse& c = op->coarse;
   helm_status s;
-  if (c.T_serial != net->serial) {
+  if (!input_only && c.T_serial != net->serial) {
     if ((s = c.T.ensure(n * (size_t)net->p * sizeof(T)))) return s;
     if ((s = trunk_eval<T>(net, op, (T*)c.T.ptr, st))) return s;
     c.T_serial = net->serial;
@@ -221,7 +210,11 @@ static helm_status full_eval(don_s* net, helm_op_s* op, const void* r, double k,
                        net->bgrid[0], net->bgrid[1], net->bgrid[2], (const cplx_t<T>*)r, sc, split_in, net->k_input,
                        k, x0);
   }
-  (void)K0;
+  if (input_only) {
+    hipError_t e = hipMemcpyAsync(du, x0, (size_t)B * K0 * sizeof(T), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "deeponet branch input");
+    return launch_check("deeponet branch input");
+  }
   // branch layers
   const int L = (int)net->bw.size() - 1;
   size_t pneed = 0;
@@ -248,6 +241,11 @@ static helm_status full_eval(don_s* net, helm_op_s* op, const void* r, double k,
 
 helm_status don_full(don_s* net, helm_op_s* op, const void* r, double k, void* du, hipStream_t st) {
   return net->dt == HELM_C128 ? full_eval<double>(net, op, r, k, du, st) : full_eval<float>(net, op, r, k, du, st);
+}
+
+static helm_status don_branch_input(don_s* net, helm_op_s* op, const void* r, double k, void* out, hipStream_t st) {
+  return net->dt == HELM_C128 ? full_eval<double>(net, op, r, k, out, st, true)
+                              : full_eval<float>(net, op, r, k, out, st, true);
 }
 
 }  // namespace helm
@@ -355,13 +353,15 @@ void deeponet_free(don_net net) {
 
 helm_status deeponet_infer(don_net net, helm_op op, int mode, const void* r, double k, void* out, void* stream) {
   if (!net || !op || !out) return fail(HELM_E_INVAL, "deeponet_infer: NULL argument");
-  if (mode != DON_TRUNK && mode != DON_FULL) return fail(HELM_E_INVAL, "deeponet_infer: unknown mode %d", mode);
+  if (mode != DON_TRUNK && mode != DON_FULL && mode != DON_BRANCH_INPUT)
+    return fail(HELM_E_INVAL, "deeponet_infer: unknown mode %d", mode);
   helm_status s = check_net_for_op(net, op, 1);
   if (s) return s;
   hipStream_t st = (hipStream_t)stream;
   if (mode == DON_TRUNK) return don_trunk(net, op, out, st);
   if (!r) return fail(HELM_E_INVAL, "deeponet_infer: r is NULL");
   if (r == out) return fail(HELM_E_INVAL, "deeponet_infer: r and out alias");
+  if (mode == DON_BRANCH_INPUT) return don_branch_input(net, op, r, k, out, st);
   return don_full(net, op, r, k, out, st);
 }
 

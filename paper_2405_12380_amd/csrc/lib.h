@@ -71,7 +71,20 @@ struct helm_op_s {
   helm::Coarse coarse;
 };
 
-struct don_s;
+// A loaded DeepONet (deeponet.hip): widths, weights on the device in the
+// dtype's real precision (W_l is in x out, row-major), and inference scratch.
+struct don_s {
+  helm_dtype dt = HELM_C128;
+  int act = DON_TANH, head = DON_SPLIT_OUTPUT, p = 0, k_input = 0;
+  int bgrid[3] = {1, 1, 1};
+  std::vector<int> bw, tw;
+  std::vector<void*> bW, bB, tW, tB;
+  int serial = 0;
+  helm::Buffer act0, act1;  // branch activations (small) and trunk chunks
+  helm::Buffer tact0, tact1;
+  helm::Buffer part;
+  helm::Buffer coef;        // 2p doubles
+};
 
 namespace helm {
 size_t op_esz(const helm_op_s* op);
@@ -82,6 +95,8 @@ helm_status op_part(helm_op_s* op, size_t doubles, double** out);
 helm_status check_net_for_op(const don_s* net, const helm_op_s* op, int p_used);
 int don_p(const don_s* net);
 int don_serial(const don_s* net);
+// A fresh serial number (weights changed: cached trunk matrices and coarse spaces go stale).
+void don_touch(don_s* net);
 // du = s N(r/s), masked (DON_FULL); async on st
 helm_status don_full(don_s* net, helm_op_s* op, const void* r, double k, void* du, hipStream_t st);
 // T = trunk(node coordinates) into `out` (n x p real, dtype precision); async

@@ -31,13 +31,15 @@ C64, C128 = 1, 2
 JACOBI, RBGS = 0, 1
 DON_TANH, DON_RELU, DON_LEAKY = 0, 1, 2
 DON_SPLIT_OUTPUT, DON_SPLIT_INPUT = 0, 1
-DON_TRUNK, DON_FULL = 0, 1
+DON_TRUNK, DON_FULL, DON_BRANCH_INPUT = 0, 1, 2
 META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
 
 EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
             "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "meta_solve_batch", "helm_misfit",
-            "helm_ksq_gradient", "helm_kprof_enable", "helm_kprof_read",
+            "helm_ksq_gradient", "don_train_create", "don_train_data", "don_train_steps", "don_train_eval",
+            "don_train_grad", "don_train_apply", "don_train_nparam", "don_train_layout", "don_train_params",
+            "don_train_export", "don_train_free", "helm_kprof_enable", "helm_kprof_read",
             "helm_strerror", "helm_last_error"]
 KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY, KP_CGS = 0, 1, 2, 3, 4, 5
 KP_NAMES = {KP_STENCIL: "stencil", KP_MULTIDOT: "multidot", KP_MULTIAXPY: "multi_axpy", KP_QT: "qt_part",
@@ -66,6 +68,11 @@ class MetaStats(C.Structure):
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("cond_Ac_est", C.c_double)]
 
 
+class DonTrainOpts(C.Structure):
+    _fields_ = [("n_points", C.c_int), ("batch", C.c_int), ("max_steps", C.c_int), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 _vp = C.c_void_p
 _sig = {
     "helm_setup": (C.c_int, [C.POINTER(HelmGrid), C.c_int, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
@@ -90,6 +97,18 @@ _sig = {
                                    C.POINTER(_vp), C.POINTER(MetaStats), _vp]),
     "helm_misfit": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "helm_ksq_gradient": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "don_train_create": (C.c_int, [_vp, C.POINTER(DonTrainOpts), _vp, C.POINTER(_vp)]),
+    "don_train_data": (C.c_int, [_vp, C.c_int, _vp, _vp]),
+    "don_train_steps": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_float), _vp]),
+    "don_train_eval": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_float), _vp]),
+    "don_train_grad": (C.c_int, [_vp, _vp, C.POINTER(C.c_float), _vp, _vp]),
+    "don_train_apply": (C.c_int, [_vp, _vp, _vp]),
+    "don_train_nparam": (C.c_size_t, [_vp]),
+    "don_train_layout": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "don_train_params": (C.c_int, [_vp, _vp, _vp]),
+    "don_train_export": (C.c_int, [_vp, _vp, _vp]),
+    "don_train_free": (None, [_vp]),
     "helm_kprof_enable": (C.c_int, [C.c_int]),
     "helm_kprof_read": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "helm_strerror": (C.c_char_p, [C.c_int]),
@@ -243,6 +262,7 @@ class DeepONet:
                  k_input=False):
         self.dtype = dtype
         self.p = int(p)
+        self.head = head
         bw = [int(branch[0][0].shape[0])] + [int(W.shape[1]) for W, _ in branch]
         tw = [int(trunk[0][0].shape[0])] + [int(W.shape[1]) for W, _ in trunk]
         bg = list(branch_grid) + [1] * (3 - len(branch_grid))
@@ -270,6 +290,15 @@ class DeepONet:
     def trunk(self, op: Op, out=None, stream=None):
         out = torch.empty(op.size * self.p, dtype=rdtype(self.dtype), device="cuda") if out is None else out
         _check(_lib.deeponet_infer(self.h, op.h, DON_TRUNK, None, 0.0, _ptr(out), _stream(stream)), "deeponet_infer")
+        return out
+
+    def branch_input(self, op: Op, r, k=0.0, out=None, stream=None):
+        """The branch input vector the network would see for r (``DON_BRANCH_INPUT``)."""
+        if out is None:
+            out = torch.empty(self._bw[0] * (2 if self.head == "split_input" else 1), dtype=rdtype(self.dtype),
+                              device="cuda")
+        _check(_lib.deeponet_infer(self.h, op.h, DON_BRANCH_INPUT, _ptr(r), float(k), _ptr(out), _stream(stream)),
+               "deeponet_infer")
         return out
 
     def full(self, op: Op, r, k=0.0, out=None, stream=None):
@@ -350,6 +379,103 @@ def coarse_info(op: Op, net: DeepONet, p_used=None, want_q=False, q_fp32=False, 
                                  r * r, _ptr(q), op.size * r if want_q else 0, _stream(stream)), "meta_coarse_info")
     A = ac.view(np.complex128).reshape(r, r)
     return (r, A, q) if want_q else (r, A)
+
+
+class Trainer:
+    """DeepONet trainer (``don_train_*``): bf16 MFMA forward/backward, Adam.
+
+    X: P x d node coordinates (fp64); the dataset is set with ``data``."""
+
+    def __init__(self, net: DeepONet, X, batch=64, max_steps=64, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        Xd = _dev(X, torch.float64)
+        self.P = int(np.asarray(X.shape)[0]) if hasattr(X, "shape") else len(X)
+        self.S = int(batch)
+        self.max_steps = int(max_steps)
+        o = DonTrainOpts(self.P, self.S, self.max_steps, lr, beta1, beta2, eps)
+        h = _vp()
+        _check(_lib.don_train_create(net.h, C.byref(o), _ptr(Xd), C.byref(h)), "don_train_create")
+        self.h = h
+        self.nparam = int(_lib.don_train_nparam(h))
+        self._Y = None
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.don_train_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def data(self, F, Y):
+        """F: n x K_b fp32 device tensor; Y: n x P complex64 device tensor (kept alive here)."""
+        F = F.to(torch.float32).contiguous()
+        Y = Y.to(torch.complex64).contiguous()
+        self._Y = Y
+        _check(_lib.don_train_data(self.h, int(F.shape[0]), _ptr(F), _ptr(Y)), "don_train_data")
+
+    def _idx(self, idx):
+        return torch.as_tensor(np.asarray(idx, dtype=np.int32) if not torch.is_tensor(idx) else idx,
+                               dtype=torch.int32).to("cuda").contiguous()
+
+    def steps(self, idx):
+        it = self._idx(idx)
+        count = it.numel() // self.S
+        out = (C.c_float * count)()
+        _check(_lib.don_train_steps(self.h, count, _ptr(it), out, None), "don_train_steps")
+        return np.array(out[:], dtype=np.float64)
+
+    def eval(self, idx):
+        it = self._idx(idx)
+        count = it.numel() // self.S
+        out = (C.c_float * count)()
+        _check(_lib.don_train_eval(self.h, count, _ptr(it), out, None), "don_train_eval")
+        return np.array(out[:], dtype=np.float64)
+
+    def grad(self, idx):
+        it = self._idx(idx)
+        g = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        loss = C.c_float()
+        _check(_lib.don_train_grad(self.h, _ptr(it), C.byref(loss), _ptr(g), None), "don_train_grad")
+        return float(loss.value), g
+
+    def apply(self, grads):
+        g = grads.to(device="cuda", dtype=torch.float32).contiguous()
+        _check(_lib.don_train_apply(self.h, _ptr(g), None), "don_train_apply")
+
+    def params(self):
+        out = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        _check(_lib.don_train_params(self.h, _ptr(out), None), "don_train_params")
+        return out
+
+    def layout(self, which: int, layer: int):
+        K, Kp, N = C.c_int(), C.c_int(), C.c_int()
+        oW, ob = C.c_size_t(), C.c_size_t()
+        _check(_lib.don_train_layout(self.h, which, layer, C.byref(K), C.byref(Kp), C.byref(N), C.byref(oW),
+                                     C.byref(ob)), "don_train_layout")
+        return K.value, Kp.value, N.value, oW.value, ob.value
+
+    def unflatten(self, flat, which: int, nlayers: int):
+        """[(W (K x N), b (N))] numpy arrays of the branch (0) or trunk (1) from a flat vector."""
+        f = flat.detach().cpu().numpy() if torch.is_tensor(flat) else np.asarray(flat)
+        out = []
+        for li in range(nlayers):
+            K, Kp, N, oW, ob = self.layout(which, li)
+            out.append((f[oW:oW + Kp * N].reshape(Kp, N)[:K].astype(np.float64), f[ob:ob + N].astype(np.float64)))
+        return out
+
+    def flatten(self, branch, trunk):
+        """Flat fp32 vector (zero padding) from [(W, b)] lists."""
+        f = np.zeros(self.nparam, dtype=np.float32)
+        for which, layers in ((0, branch), (1, trunk)):
+            for li, (W, b) in enumerate(layers):
+                K, Kp, N, oW, ob = self.layout(which, li)
+                blk = np.zeros((Kp, N), dtype=np.float32)
+                blk[:K] = W
+                f[oW:oW + Kp * N] = blk.ravel()
+                f[ob:ob + N] = b
+        return torch.as_tensor(f).to("cuda")
+
+    def export(self, net: DeepONet):
+        _check(_lib.don_train_export(self.h, net.h, None), "don_train_export")
 
 
 def kprof_enable(on: bool = True):

@@ -225,6 +225,50 @@ def random_problem(n, seed: int, mask_frac: float = 0.05, k=None) -> dict:
                 x=x.astype(np.complex128), f=f.astype(np.complex128))
 
 
+def config3(count: int, instance: int = 0, n=(48, 48, 48), k_range=(5.0, 15.0), device="cuda"):
+    """Training set of App. B: ``count`` non-scattering problems on one grid
+    (48^3), homogeneous k ~ U[5, 15], 8-cell sponge, complex GRF sources
+    (l = 0.1) scaled to unit RMS (so a network trained on (f, u) sees the same
+    scaling as the meta-solver's r / s).  The many sources are drawn on the
+    GPU with torch's seeded generator (the same FFT filtering as ``grf``);
+    returns (k array, alpha, f as a count x n complex128 torch tensor)."""
+    import torch
+    g = rng_for(3, instance)
+    ks = g.uniform(*k_range, size=count)
+    n = tuple(int(v) for v in n)
+    alpha = sponge(n)
+    shape = tuple(reversed([2 * a for a in n]))
+    h = [1.0 / (a + 1) for a in n]
+    ker = np.ones(shape)
+    for a, (na, ha) in enumerate(zip([2 * v for v in n], h)):
+        i = np.arange(na)
+        d = np.minimum(i, na - i) * ha
+        sh = [1] * len(n)
+        sh[len(n) - 1 - a] = na
+        ker = ker * np.exp(-(d ** 2) / 0.1 ** 2).reshape(sh)
+    kt = torch.as_tensor(ker, device=device)
+    kf = torch.fft.rfftn(kt)
+    knorm = float(np.sqrt(np.sum(ker ** 2)))
+    tg = torch.Generator(device=device)
+    tg.manual_seed(int(g.integers(0, 2 ** 62)))
+    out = torch.empty((count,) + tuple(reversed(n)), dtype=torch.complex128, device=device)
+    sl = tuple(slice(0, a) for a in reversed(n))
+    chunk = 32
+    for c0 in range(0, count, chunk):
+        c1 = min(count, c0 + chunk)
+        for part in (0, 1):
+            noise = torch.randn((c1 - c0,) + shape, generator=tg, device=device, dtype=torch.float64)
+            fld = torch.fft.irfftn(torch.fft.rfftn(noise, dim=(1, 2, 3)) * kf, s=shape, dim=(1, 2, 3)) / knorm
+            fld = fld[(slice(None),) + sl]
+            if part == 0:
+                out[c0:c1].real = fld
+            else:
+                out[c0:c1].imag = fld
+    rms = torch.sqrt(torch.mean(torch.abs(out.reshape(count, -1)) ** 2, dim=1))
+    out /= rms.reshape((count,) + (1,) * len(n))
+    return ks, alpha, out.reshape(count, -1)
+
+
 def config4(count: int = 64, instance: int = 0, n_range=(48, 128), k_range=(5.0, 25.0)) -> list:
     """Batched case: ``count`` independent cubic problems, n ~ U{48..128}
     nodes per axis, homogeneous k ~ U[5, 25], a sponge of max(8, n / 8) cells
