@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-problem workload")
     ap.add_argument("--no-train", action="store_true", help="skip the DeepONet training workload")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid-preconditioned comparison")
+    ap.add_argument("--mg-n", type=int, default=63, help="grid nodes per axis of the multigrid comparison")
     ap.add_argument("--train-samples", type=int, default=1024, help="non-scattering 48^3 solves in the training set")
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--batch-count", type=int, default=16,
@@ -239,6 +241,10 @@ def main():
         log(f"batched workload: {args.batch_count} problems")
         out["batch"] = batched_solves(helm, I, torch, dev, args.batch_count)
 
+    if not args.no_mg:
+        log(f"multigrid comparison at {args.mg_n}^3")
+        out["multigrid"] = multigrid(helm, I, torch, dev, args.mg_n)
+
     if not args.no_train:
         log(f"training workload: {args.train_samples} samples")
         out["train"] = training(helm, I, torch, dev, args.train_samples, args.train_epochs)
@@ -302,6 +308,40 @@ def batched_solves(helm, I, torch, dev, count):
            "tune_ms": round(tune_ms, 1), "tiles_ty_x_zb": tiles}
     log(f"batch: {res}")
     for op in ops:
+        op.close()
+    net.close()
+    return res
+
+
+def multigrid(helm, I, torch, dev, N):
+    """GMRES(50) to 1e-6 on the cube scatterer of the 3D workload at N^3 (N + 1 a
+    power of two), k = 12 and k = 36 (the paper's multigrid case), with: no
+    preconditioner; a V-cycle with 5 + 5 Jacobi sweeps; the DeepONet-MG V-cycle
+    (2-1-2 smoothing, trunk basis p = 32 on every level); and the single-level
+    DeepONet preconditioner (n_r = 3, p = 128)."""
+    levels = int(round(np.log2(N + 1))) - 2      # coarsest grid 3^3
+    res = {"grid": [N, N, N], "levels": levels, "runs": []}
+    C = I.config2(0, n=(N, N, N))
+    net = helm.DeepONet(helm.C128, C["branch"], C["trunk"], C["p"], head="split_output", branch_grid=(16, 16, 16),
+                        k_input=True)
+    for k in (12.0, 36.0):
+        ksq = np.full_like(C["ksq"], k * k)
+        op = helm.Op(C["n"], helm.C128, ksq, C["alpha"], C["mask"])
+        f = op.field(C["f"])
+        for name, use_net, kw in [("gmres", False, {}),
+                                  ("mg_gmres", False, dict(mg_levels=levels, mg_nu=5)),
+                                  ("deeponet_mg_gmres", True, dict(mg_levels=levels, mg_nu=5, p_used=32)),
+                                  ("deeponet_gmres", True, dict(p_used=128, n_r=3))]:
+            u = op.field()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, st = helm.meta_solve(op, net if use_net else None, f, u, kind="gmres", restart=50, tol=1e-6,
+                                    max_iters=20000, omega=0.5, k=k, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            res["runs"].append({"k": k, "solver": name, "status": s, "iters": st["iters"], "ms": round(ms, 2),
+                                "setup_ms": round(st["setup_ms"], 2), "rel_res": st["rel_res"]})
+            log(f"k={k:g} {name}: {st['iters']} iterations, {ms:.1f} ms (status {s})")
         op.close()
     net.close()
     return res

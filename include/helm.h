@@ -256,6 +256,16 @@ typedef struct {
   int q_fp32;      /* Krylov kinds with a network: store the basis Q in fp32 (C128;
                       always so for C64).  A_c is then the Galerkin matrix of the
                       stored basis; halves the bytes of the coarse correction.      */
+  int mg_levels;   /* Krylov kinds: 0 = the preconditioner above; L > 0 = one
+                      geometric multigrid V-cycle with L coarsenings (§4.2,
+                      DeepONet-MG-Krylov): every second node per level, coefficient
+                      and mask injected, full weighting, multilinear prolongation,
+                      exact solve on the coarsest grid (<= 128 nodes); each n_a + 1
+                      must be divisible by 2^L.                                     */
+  int mg_nu;       /* smoothing steps before and after the coarse correction: Jacobi
+                      sweeps (net == NULL), or with a network a sweeps, one trunk-basis
+                      correction of that level with min(p_used, nodes) columns, b
+                      sweeps (a = mg_nu / 2, b = mg_nu - a - 1: 2-1-2 for 5)         */
 } meta_opts;
 
 typedef struct {

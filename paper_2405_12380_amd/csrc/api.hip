@@ -187,6 +187,7 @@ helm_status helm_set_ksq(helm_op op, const double* ksq, void* stream) {
 
 void helm_destroy(helm_op op) {
   if (!op) return;
+  mg_release(op);
   coarse_release(op);
   dfree(op->sc);
   dfree(op->mask);

@@ -834,6 +834,7 @@ extern "C" helm_status meta_solve_batch(int count, const helm_op* ops, don_net n
   if (count <= 0 || !ops || !o || !f || !u || !st) return fail(HELM_E_INVAL, "meta_solve_batch: bad argument");
   if (o->kind != META_BICGSTAB) return fail(HELM_E_INVAL, "meta_solve_batch: kind must be META_BICGSTAB");
   if (o->smoother != HELM_JACOBI) return fail(HELM_E_INVAL, "meta_solve_batch: the smoother must be HELM_JACOBI");
+  if (o->mg_levels != 0) return fail(HELM_E_INVAL, "meta_solve_batch: the multigrid preconditioner is not batched");
   for (int i = 0; i < count; ++i) {
     if (!ops[i] || !f[i] || !u[i]) return fail(HELM_E_INVAL, "meta_solve_batch: NULL entry %d", i);
     if (f[i] == u[i]) return fail(HELM_E_INVAL, "meta_solve_batch: f and u alias in problem %d", i);

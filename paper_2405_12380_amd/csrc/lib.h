@@ -13,6 +13,7 @@
 
 namespace helm {
 
+struct Mg;
 helm_status fail(helm_status s, const char* fmt, ...);
 helm_status hip_fail(hipError_t e, const char* what);
 helm_status dalloc(void** p, size_t bytes);
@@ -69,6 +70,7 @@ struct helm_op_s {
   helm::Buffer ws;           // solver workspace
   helm::Buffer adj;          // one field: the conjugated right-hand side of an adjoint solve
   helm::Coarse coarse;
+  helm::Mg* mg = nullptr;    // multigrid hierarchy (mg.hip), built on demand
 };
 
 // A loaded DeepONet (deeponet.hip): widths, weights on the device in the
@@ -111,6 +113,12 @@ void coarse_release(helm_op_s* op);
 void coarse_trim(helm_op_s* op);
 // Validation of meta_opts against an op and a network (meta.hip).
 helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o);
+// Multigrid (mg.hip): option checks, hierarchy (cached on the op), one V-cycle.
+helm_status mg_check(const helm_op_s* op, const meta_opts* o);
+helm_status mg_ensure(helm_op_s* op, don_s* net, const meta_opts* o, hipStream_t st);
+template <typename S>
+helm_status mg_apply(helm_op_s* op, don_s* net, const meta_opts* o, const void* v, void* z, hipStream_t st);
+void mg_release(helm_op_s* op);
 
 // ---- shared driver pieces ----
 template <typename S>

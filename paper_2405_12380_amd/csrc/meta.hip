@@ -58,6 +58,7 @@ struct MetaCtx {
 template <typename S>
 helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* z, hipStream_t st) {
   const meta_opts* o = c.o;
+  if (o->mg_levels > 0) return mg_apply<S>(op, c.net, o, v, z, st);
   const size_t n = op->nn;
   helm_status s;
   if (o->n_r > 0) {
@@ -457,6 +458,13 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
     st_out->rank_used = op->coarse.rank;
     st_out->cond_Ac_est = op->coarse.cond_est;
   }
+  if (o->mg_levels > 0 && (s = mg_ensure(op, net, o, st))) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    return s;
+  }
+  if (o->mg_levels > 0) c.use_M = true;
   (void)hipEventRecord(e1, st);
   if (o->kind == META_GMRES) s = gmres_drive<S>(op, c, f, u, st_out, st);
   else if (o->kind == META_BICGSTAB) s = bicgstab_drive<S>(op, c, f, u, st_out, st);
@@ -493,7 +501,7 @@ helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o) {
     helm_status s = check_net_for_op(net, op, 1);
     if (s) return s;
   }
-  return HELM_OK;
+  return mg_check(op, o);
 }
 
 }  // namespace helm
@@ -549,6 +557,7 @@ helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void
   if (s) return s;
   hipStream_t hs = (hipStream_t)stream;
   if (net && (s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, hs))) return s;
+  if (o->mg_levels > 0 && (s = mg_ensure(op, net, o, hs))) return s;
   const size_t fld = op->nn * op_esz(op);
   if ((s = op->ws.ensure(fld))) return s;
   MetaCtx c{o, net, true, op->ws.ptr};

@@ -9,11 +9,15 @@
 //   back:    dT = dUt^T Bc, dBc = dUt T, then per layer dW = H^T dZ, db = colsum dZ,
 //            dZ_below = (dZ W^T) * (1 - H^2)
 //   Adam on the flat fp32 parameters; bf16 copies feed the next step's GEMMs.
-// Every matrix product runs in one bf16 GEMM kernel (v_mfma_f32_16x16x32_bf16,
-// 128 x 128 tile per 256-thread workgroup, 32-deep k steps staged in LDS, either
-// operand read as stored or transposed while staging) with fused epilogues
-// (bias + tanh, bias, tanh derivative, fp32) or split-k partials reduced in a
-// fixed order.  A step is captured once as a HIP graph and replayed; the
+// Every matrix product runs in one bf16 GEMM kernel, C = A B^T with both
+// operands k-contiguous (v_mfma_f32_16x16x32_bf16, 128 x 128 tile per
+// 256-thread workgroup, 64-deep k steps through LDS with the next step's
+// operands prefetched into registers), with fused epilogues (bias + tanh, bias,
+// tanh derivative, fp32) or split-k partials reduced in a fixed order.  So that
+// every product is of that form, the epilogues also write a transposed copy of
+// each activation and each gradient (the backward products reduce over the
+// points, which must then be contiguous), and Adam refreshes both W and W^T in
+// bf16.  A step is captured once as a HIP graph and replayed; the
 // sample indices and the step counter live on the device.
 #include <hip/hip_runtime.h>
 
@@ -34,20 +38,21 @@ namespace helm {
 
 namespace {
 
-constexpr int TM = 128, TN = 128, TK = 32, LDSW = 40;  // tile and LDS row stride (bf16 elements, 80 B)
+constexpr int TM = 128, TN = 128, BK = 64, LDSW = 72;  // tile, k step, LDS row stride (bf16, 144 B)
 
 enum { EP_F32 = 0, EP_BF16 = 1, EP_BIAS_BF16 = 2, EP_BIAS_TANH_BF16 = 3, EP_DTANH_BF16 = 4, EP_PART = 5 };
 
+// C (M x N) = A (M x K) B (N x K)^T: both operands k-contiguous ("NT").
 struct GemmArgs {
   const __bf16* A;
   long lda;
-  int ta;  // 0: A is M x K (k contiguous); 1: A is stored K x M
   const __bf16* B;
   long ldb;
-  int tb;  // 0: B is stored N x K (k contiguous); 1: B is stored K x N
   int M, N, K, kchunk;
   void* C;
   long ldc;
+  __bf16* CT;  // optional transposed bf16 copy of the result (N x M, leading dimension ldct)
+  long ldct;
   const float* bias;
   const __bf16* aux;  // EP_DTANH_BF16: the activation h (M x N, leading dimension ldc)
   int ep;
@@ -55,168 +60,223 @@ struct GemmArgs {
 
 __device__ __forceinline__ float bf2f(__bf16 v) { return (float)v; }
 
-// Apply an epilogue to one value of C(row, col).
-__device__ __forceinline__ void ep_store(const GemmArgs& g, int row, int col, float v) {
+// tanh x = 1 - 2 / (1 + e^{2x}) with the hardware exponential (saturates to +-1)
+__device__ __forceinline__ float fast_tanh(float x) { return 1.0f - __fdividef(2.0f, 1.0f + __expf(2.0f * x)); }
+
+// Epilogue of one value of C(row, col); returns the stored bf16 value for the transposed copy.
+__device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, float v) {
   const long o = (long)row * g.ldc + col;
+  __bf16 r = (__bf16)0.0f;
   switch (g.ep) {
     case EP_F32:
       ((float*)g.C)[o] = v;
       break;
     case EP_BF16:
-      ((__bf16*)g.C)[o] = (__bf16)v;
+      r = (__bf16)v;
+      ((__bf16*)g.C)[o] = r;
       break;
     case EP_BIAS_BF16:
-      ((__bf16*)g.C)[o] = (__bf16)(v + g.bias[col]);
+      r = (__bf16)(v + g.bias[col]);
+      ((__bf16*)g.C)[o] = r;
       break;
     case EP_BIAS_TANH_BF16:
-      ((__bf16*)g.C)[o] = (__bf16)tanhf(v + g.bias[col]);
+      r = (__bf16)fast_tanh(v + g.bias[col]);
+      ((__bf16*)g.C)[o] = r;
       break;
     case EP_DTANH_BF16: {
       const float h = bf2f(g.aux[o]);
-      ((__bf16*)g.C)[o] = (__bf16)(v * (1.0f - h * h));
+      r = (__bf16)(v * (1.0f - h * h));
+      ((__bf16*)g.C)[o] = r;
       break;
     }
     default:  // EP_PART: split-k slice blockIdx.z of an M x N fp32 array
       ((float*)g.C)[(long)blockIdx.z * g.M * g.N + (long)row * g.N + col] = v;
   }
+  return r;
 }
 
-// Stage a 128-row x 32-k tile of an operand into LDS as [row][k] (k contiguous).
-// trans = 0: rows of G are the tile rows (k contiguous, ld elements apart);
-// trans = 1: G is stored k-major (row index = k), the tile is transposed on the way.
-__device__ __forceinline__ void stage(const __bf16* __restrict__ G, long ld, int trans, int r0, int R, int k0, int K,
-                                      __bf16* __restrict__ S) {
-  const int t = threadIdx.x;
-  bf8 z;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) z[j] = (__bf16)0.0f;
-  if (!trans) {
-#pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-      const int row = (t >> 2) + 64 * pass, kq = (t & 3) * 8;
-      bf8 v = z;
-      if (r0 + row < R && k0 + kq < K) v = *(const bf8*)(G + (long)(r0 + row) * ld + k0 + kq);
-      *(bf8*)(S + row * LDSW + kq) = v;
-    }
-  } else {
-#pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-      const int kr = (t >> 4) + 16 * pass, rq = (t & 15) * 8;
-      bf8 v = z;
-      if (k0 + kr < K) {
-        const long base = (long)(k0 + kr) * ld + r0 + rq;
-        if (r0 + rq + 8 <= R) {
-          v = *(const bf8*)(G + base);
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (r0 + rq + j < R) v[j] = G[base + j];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) S[(rq + j) * LDSW + kr] = v[j];
-    }
-  }
-}
+// 128 x 128 output tile per 256-thread workgroup over this workgroup's k slice.
+// Each thread moves four 16-byte chunks of each operand per 64-deep k step
+// (8 threads per 128-byte row segment); the next step's chunks are loaded into
+// registers while the current step's 32 MFMAs per wavefront run from LDS.
+// Wavefront w owns the 64 x 64 quadrant (w / 2, w % 2) as 4 x 4 tiles of
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][8 (l / 16) .. +7],
+// B[l % 16][8 (l / 16) .. +7] (B stored n-major) and C[4 (l / 16) + i][l % 16].
+constexpr int CTW = TN + 8;  // LDS row stride of the staged output tile (bf16)
 
-// C (M x N) = sum_k A(m, k) B(k, n) over this workgroup's k slice, epilogue g.ep.
-// Wavefront w owns the 64 x 64 quadrant (w / 2, w % 2) as 4 x 4 MFMA tiles;
-// lane l holds A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and
-// C[4 (l / 16) + i][l % 16] of a 16 x 16 x 32 product.
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[TM * LDSW];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[TN * LDSW];
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+  // operand tiles during the k loop; the output tile and its transpose afterwards
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * TM * CTW];
+  __bf16* As = smem;
+  __bf16* Bs = smem + TM * LDSW;
   const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
   const int kb = blockIdx.z * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int wm = w >> 1, wn = w & 1;
+  bf8 zero;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
+  bf8 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = t + 256 * j, row = c >> 3, kq = (c & 7) * 8;
+      ra[j] = m0 + row < g.M ? *(const bf8*)(g.A + (long)(m0 + row) * g.lda + k0 + kq) : zero;
+      rb[j] = n0 + row < g.N ? *(const bf8*)(g.B + (long)(n0 + row) * g.ldb + k0 + kq) : zero;
+    }
+  };
   f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += TK) {
-    stage(g.A, g.lda, g.ta, m0, g.M, k0, ke, As);
-    stage(g.B, g.ldb, g.tb, n0, g.N, k0, ke, Bs);
-    __syncthreads();
-    bf8 a[4], b[4];
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a[i] = *(const bf8*)(As + (wm * 64 + i * 16 + (l & 15)) * LDSW + 8 * (l >> 4));
-      b[i] = *(const bf8*)(Bs + (wn * 64 + i * 16 + (l & 15)) * LDSW + 8 * (l >> 4));
+    for (int j = 0; j < 4; ++j) {
+      const int c = t + 256 * j, row = c >> 3, kq = (c & 7) * 8;
+      *(bf8*)(As + row * LDSW + kq) = ra[j];
+      *(bf8*)(Bs + row * LDSW + kq) = rb[j];
     }
+    __syncthreads();
+    if (k0 + BK < ke) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      bf8 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = *(const bf8*)(As + (wm * 64 + i * 16 + (l & 15)) * LDSW + kk + 8 * (l >> 4));
+        b[i] = *(const bf8*)(Bs + (wn * 64 + i * 16 + (l & 15)) * LDSW + kk + 8 * (l >> 4));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (g.ep == EP_F32 || g.ep == EP_PART) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+      for (int j = 0; j < 4; ++j) {
+        const int row0 = m0 + wm * 64 + i * 16 + 4 * (l >> 4);
+        const int col = n0 + wn * 64 + j * 16 + (l & 15);
+        if (col >= g.N) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (row0 + q < g.M) ep_store(g, row0 + q, col, acc[i][j][q]);
+      }
+    return;
   }
+  // bf16 results: the tile goes to LDS twice, row-major (C) and column-major
+  // (C^T; a lane's four rows of one column are 8 contiguous bytes there), and
+  // both are written out as 16-byte chunks of contiguous rows
+  __bf16* Cs = smem;             // TM x CTW, reuses the operand tiles (the k loop ended with a barrier)
+  __bf16* CsT = smem + TM * CTW;  // TN x CTW
+  typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < 4; ++j) {
+    const int cl = wn * 64 + j * 16 + (l & 15), col = n0 + cl;
+    const bool cin = col < g.N;
+    const float bias = (cin && (g.ep == EP_BIAS_BF16 || g.ep == EP_BIAS_TANH_BF16)) ? g.bias[col] : 0.0f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i) {
+      const int rl0 = wm * 64 + i * 16 + 4 * (l >> 4);
+      const int row0 = m0 + rl0;
+      bf4 r4;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + q;
-        const int col = n0 + wn * 64 + j * 16 + (l & 15);
-        if (row < g.M && col < g.N) ep_store(g, row, col, acc[i][j][q]);
+        float v = acc[i][j][q] + bias;
+        if (g.ep == EP_BIAS_TANH_BF16) v = fast_tanh(v);
+        else if (g.ep == EP_DTANH_BF16 && cin && row0 + q < g.M) {
+          const float h = bf2f(g.aux[(long)(row0 + q) * g.ldc + col]);
+          v *= 1.0f - h * h;
+        }
+        r4[q] = (__bf16)v;
+        Cs[(rl0 + q) * CTW + cl] = r4[q];
       }
+      *(bf4*)(CsT + cl * CTW + rl0) = r4;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int c = t + 256 * k, rl = c >> 4, cq = (c & 15) * 8;
+    const int row = m0 + rl, col = n0 + cq;
+    if (row < g.M && col + 8 <= g.N)
+      *(bf8*)((__bf16*)g.C + (long)row * g.ldc + col) = *(const bf8*)(Cs + rl * CTW + cq);
+  }
+  if (g.CT) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = t + 256 * k, cl = c >> 4, rq = (c & 15) * 8;
+      const int col = n0 + cl, row = m0 + rq;
+      if (col < g.N && row + 8 <= g.M) *(bf8*)(g.CT + (long)col * g.ldct + row) = *(const bf8*)(CsT + cl * CTW + rq);
+    }
+  }
 }
 
-// sum of split-k slices in a fixed order, then the epilogue
+// sum of split-k slices in a fixed order, then the epilogue (and the transposed copy)
 __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g, const float* __restrict__ part, int splits) {
   const long MN = (long)g.M * g.N;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)gridDim.x * 256) {
     float v = 0.f;
     for (int z = 0; z < splits; ++z) v += part[z * MN + e];
-    ep_store(g, (int)(e / g.N), (int)(e % g.N), v);
+    const int row = (int)(e / g.N), col = (int)(e % g.N);
+    const __bf16 r = ep_store(g, row, col, v);
+    if (g.CT) g.CT[(long)col * g.ldct + row] = r;
   }
 }
 
-// partial column sums of a bf16 M x N matrix (N <= 256): part[b][col]
-__global__ __launch_bounds__(256) void k_colsum(const __bf16* __restrict__ D, int M, int N, int rows,
-                                                float* __restrict__ part) {
-  const int col = threadIdx.x;
-  if (col >= N) return;
-  const int r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
-  float a = 0.f;
-  for (int r = r0; r < r1; ++r) a += bf2f(D[(long)r * N + col]);
-  part[(long)blockIdx.x * N + col] = a;
-}
-
-// fixed-order sum of nb partial rows of width N into out (optionally accumulated to a scalar)
-__global__ void k_rows_sum(const float* __restrict__ part, int nb, int N, float* __restrict__ out) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
-    float a = 0.f;
-    for (int b = 0; b < nb; ++b) a += part[(long)b * N + c];
-    out[c] = a;
+// out[r] = sum of row r of a bf16 R x M matrix (fixed order: per-thread strided sums, then a tree)
+__global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ D, long M, float* __restrict__ out) {
+  __shared__ double sh[16];
+  const __bf16* row = D + (long)blockIdx.x * M;
+  double a = 0.0;
+  for (long c = threadIdx.x * 8L; c < M; c += 256 * 8L) {
+    const bf8 v = *(const bf8*)(row + c);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a += (double)bf2f(v[j]);
   }
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = (float)a;
 }
 
-// Branch inputs of the batch: rows idx[step S + s] of the dataset (bf16, padded).
+// Branch inputs of the batch: rows idx[step S + s] of the dataset (bf16, padded), and the transpose
 __global__ __launch_bounds__(256) void k_gather(const __bf16* __restrict__ F, long ldf, const int* __restrict__ idx,
-                                                const int* __restrict__ step, int S, __bf16* __restrict__ out) {
+                                                const int* __restrict__ step, int S, __bf16* __restrict__ out,
+                                                __bf16* __restrict__ outT) {
   const int s = blockIdx.y;
   const int src = idx[(long)step[0] * S + s];
-  for (long c = blockIdx.x * 256L + threadIdx.x; c < ldf; c += (long)gridDim.x * 256)
-    out[(long)s * ldf + c] = F[(long)src * ldf + c];
+  for (long c = blockIdx.x * 256L + threadIdx.x; c < ldf; c += (long)gridDim.x * 256) {
+    const __bf16 v = F[(long)src * ldf + c];
+    out[(long)s * ldf + c] = v;
+    outT[c * S + s] = v;
+  }
 }
 
-// Bc (2S x p): row s = B[s][0:p], row S + s = B[s][p:2p]
-__global__ void k_to_bc(const __bf16* __restrict__ B, int S, int p, __bf16* __restrict__ Bc) {
+// Bc (2S x p): row s = B[s][0:p], row S + s = B[s][p:2p]; BcT its transpose (p x 2S)
+__global__ void k_to_bc(const __bf16* __restrict__ B, int S, int p, __bf16* __restrict__ Bc, __bf16* __restrict__ BcT) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 2 * S * p) return;
   const int r = e / p, c = e % p;
-  Bc[e] = r < S ? B[(long)r * 2 * p + c] : B[(long)(r - S) * 2 * p + p + c];
+  const __bf16 v = r < S ? B[(long)r * 2 * p + c] : B[(long)(r - S) * 2 * p + p + c];
+  Bc[e] = v;
+  BcT[(long)c * 2 * S + r] = v;
 }
 
-// dB (S x 2p, bf16) from dBc (2S x p, fp32)
-__global__ void k_from_dbc(const float* __restrict__ dBc, int S, int p, __bf16* __restrict__ dB) {
+// dB (S x 2p) and its transpose (2p x S), bf16, from dBc (2S x p, fp32)
+__global__ void k_from_dbc(const float* __restrict__ dBc, int S, int p, __bf16* __restrict__ dB,
+                           __bf16* __restrict__ dBT) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 2 * S * p) return;
   const int s = e / (2 * p), c = e % (2 * p);
-  dB[e] = (__bf16)(c < p ? dBc[(long)s * p + c] : dBc[(long)(S + s) * p + (c - p)]);
+  const __bf16 v = (__bf16)(c < p ? dBc[(long)s * p + c] : dBc[(long)(S + s) * p + (c - p)]);
+  dB[e] = v;
+  dBT[(long)c * S + s] = v;
 }
 
 // per (sample, chunk): ||U_s - Y_s||^2 and ||Y_s||^2 over the chunk's points (fp64)
@@ -266,17 +326,36 @@ __global__ void k_loss_final(const double* __restrict__ part, int S, int nch, co
   }
 }
 
-// dUt (2S x P, bf16) = (Ut - Y) w_s
+// dUt (2S x P, bf16) = (Ut - Y) w_s, and its transpose dUtT (P x 2S): a workgroup
+// takes 64 points, reads the 2S rows coalesced and writes the point-major copy
+// through LDS
 __global__ __launch_bounds__(256) void k_dU(const float* __restrict__ Ut, const float2* __restrict__ Y,
                                             const int* __restrict__ idx, const int* __restrict__ step,
-                                            const float* __restrict__ w, int S, int P, __bf16* __restrict__ dUt) {
-  const int s = blockIdx.y;
-  const long src = idx[(long)step[0] * S + s];
-  const float ws = w[s];
-  for (long q = blockIdx.x * 256L + threadIdx.x; q < P; q += (long)gridDim.x * 256) {
-    const float2 y = Y[src * P + q];
-    dUt[(long)s * P + q] = (__bf16)((Ut[(long)s * P + q] - y.x) * ws);
-    dUt[(long)(S + s) * P + q] = (__bf16)((Ut[(long)(S + s) * P + q] - y.y) * ws);
+                                            const float* __restrict__ w, int S, int P, __bf16* __restrict__ dUt,
+                                            __bf16* __restrict__ dUtT) {
+  __shared__ __attribute__((aligned(16))) __bf16 tile[64 * (256 + 8)];
+  const int q0 = blockIdx.x * 64, t = threadIdx.x, pl = t & 63;
+  const int R = 2 * S, ld = R + 8;
+  for (int s = t >> 6; s < S; s += 4) {
+    const long src = idx[(long)step[0] * S + s];
+    const float ws = w[s];
+    const int q = q0 + pl;
+    __bf16 re = (__bf16)0.0f, im = (__bf16)0.0f;
+    if (q < P) {
+      const float2 y = Y[src * P + q];
+      re = (__bf16)((Ut[(long)s * P + q] - y.x) * ws);
+      im = (__bf16)((Ut[(long)(S + s) * P + q] - y.y) * ws);
+      dUt[(long)s * P + q] = re;
+      dUt[(long)(S + s) * P + q] = im;
+    }
+    tile[pl * ld + s] = re;
+    tile[pl * ld + S + s] = im;
+  }
+  __syncthreads();
+  const int chunks = R / 8;
+  for (int c = t; c < 64 * chunks; c += 256) {
+    const int pt = c / chunks, rq = (c % chunks) * 8;
+    if (q0 + pt < P) *(bf8*)(dUtT + (long)(q0 + pt) * R + rq) = *(const bf8*)(tile + pt * ld + rq);
   }
 }
 
@@ -299,6 +378,15 @@ __global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ w, con
   }
 }
 
+// W^T (N x Kp) from W (Kp x N), bf16
+__global__ void k_transpose(int Kp, int N, const __bf16* __restrict__ W, __bf16* __restrict__ WT) {
+  const long n = (long)Kp * N;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    const long r = e / N, c = e % N;
+    WT[c * Kp + r] = W[e];
+  }
+}
+
 // step index within the call; Adam's step count only when the parameters moved
 __global__ void k_tick(int* __restrict__ step, int* __restrict__ tstep, int updated) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -311,13 +399,16 @@ __global__ void k_f32_to_bf16(long n, const float* __restrict__ a, __bf16* __res
   for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) b[e] = (__bf16)a[e];
 }
 
-// padded bf16 rows (ld columns) from fp32 rows (cols columns)
-__global__ void k_pad_rows(long rows, int cols, const float* __restrict__ a, int ld, __bf16* __restrict__ b) {
+// padded bf16 rows (ld columns) from fp32 rows (cols columns); optional transpose (ld x rows)
+__global__ void k_pad_rows(long rows, int cols, const float* __restrict__ a, int ld, __bf16* __restrict__ b,
+                           __bf16* __restrict__ bT) {
   const long n = rows * ld;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
     const long r = e / ld;
     const int c = (int)(e % ld);
-    b[e] = (__bf16)(c < cols ? a[r * cols + c] : 0.0f);
+    const __bf16 v = (__bf16)(c < cols ? a[r * cols + c] : 0.0f);
+    b[e] = v;
+    if (bT) bT[(long)c * rows + r] = v;
   }
 }
 
@@ -343,7 +434,7 @@ static unsigned grid_for(long n) {
   return (unsigned)b;
 }
 
-static int pad32(int k) { return (k + 31) / 32 * 32; }
+static int pad64(int k) { return (k + 63) / 64 * 64; }
 
 }  // namespace
 
@@ -356,60 +447,68 @@ struct Layer {
   size_t offW, offb;  // offsets in the flat parameter arrays (elements)
 };
 
+// Activations of one MLP: every layer's output row-major (M x N) and transposed (N x M).
+struct Acts {
+  Buffer h, hT;
+  std::vector<size_t> off;  // per layer, elements
+};
+
 struct don_trainer_s {
   int S = 0, P = 0, d = 0, p = 0;
   float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   std::vector<Layer> bl, tl;  // branch, trunk
   size_t nparam = 0;
   int max_steps = 0;
-  Buffer master, grad, mom, var, wbf;  // flat fp32 / bf16 parameters
-  Buffer X;                            // P x Kp trunk inputs (bf16)
-  Buffer bact, tact;                   // activations: branch S x (sum of widths), trunk P x (sum of widths)
-  Buffer dz0, dz1;                     // trunk backward ping-pong (P x 256 bf16)
-  Buffer bdz0, bdz1;                   // branch backward ping-pong
-  Buffer Bc, Ut, dUt, dBcp, dBc, dW, cs, lpart, wv, ctr, losses, idx;
-  Buffer Fdata;                        // n x Kb_pad bf16
-  const float2* Y = nullptr;           // n x P complex64 labels (caller's)
+  Buffer master, grad, mom, var, wbf, wtb;  // flat fp32 parameters, Adam moments, bf16 W and W^T copies
+  Buffer X, XT;                             // P x Kp trunk inputs (bf16) and transpose
+  Buffer Fb, FbT;                           // S x Kp branch inputs of the batch and transpose
+  Acts ba, ta;                              // branch and trunk activations
+  Buffer dz[2], dzT[2], bdz[2], bdzT[2];    // backward ping-pong (trunk, branch)
+  Buffer Bc, BcT, Ut, dUt, dUtT, dBc, part, lpart, wv, ctr, losses, idx;
+  Buffer Fdata;                             // n x Kb_pad bf16
+  const float2* Y = nullptr;                // n x P complex64 labels (caller's)
   int ndata = 0;
-  size_t tact_off[8] = {0}, bact_off[8] = {0};
-  size_t dw_slices = 0;
+  size_t part_floats = 0;
   hipStream_t st = nullptr;
   hipGraphExec_t step_exec = nullptr;
   ~don_trainer_s() {
     if (step_exec) (void)hipGraphExecDestroy(step_exec);
     if (st) (void)hipStreamDestroy(st);
-    for (Buffer* b : {&master, &grad, &mom, &var, &wbf, &X, &bact, &tact, &dz0, &dz1, &bdz0, &bdz1, &Bc, &Ut, &dUt,
-                      &dBcp, &dBc, &dW, &cs, &lpart, &wv, &ctr, &losses, &idx, &Fdata})
+    for (Buffer* b : {&master, &grad, &mom, &var, &wbf, &wtb, &X, &XT, &Fb, &FbT, &ba.h, &ba.hT, &ta.h, &ta.hT, &dz[0],
+                      &dz[1], &dzT[0], &dzT[1], &bdz[0], &bdz[1], &bdzT[0], &bdzT[1], &Bc, &BcT, &Ut, &dUt, &dUtT,
+                      &dBc, &part, &lpart, &wv, &ctr, &losses, &idx, &Fdata})
       b->release();
   }
 };
 
 namespace {
 
-void gemm(hipStream_t st, const __bf16* A, long lda, int ta, const __bf16* B, long ldb, int tb, int M, int N, int K,
-          void* C, long ldc, int ep, const float* bias = nullptr, const __bf16* aux = nullptr, int splits = 1,
-          float* part = nullptr) {
-  GemmArgs g{A, lda, ta, B, ldb, tb, M, N, K, 0, C, ldc, bias, aux, ep};
-  const int kblocks = K / TK;
+// C = A B^T (both k-contiguous), split over k when splits > 1 (partials in `part`)
+void gemm(hipStream_t st, const __bf16* A, long lda, const __bf16* B, long ldb, int M, int N, int K, void* C,
+          long ldc, int ep, const float* bias = nullptr, const __bf16* aux = nullptr, __bf16* CT = nullptr,
+          long ldct = 0, int splits = 1, float* part = nullptr) {
+  GemmArgs g{A, lda, B, ldb, M, N, K, 0, C, ldc, CT, ldct, bias, aux, ep};
+  const int kblocks = K / BK;
   if (splits > kblocks) splits = kblocks;
   if (splits < 1) splits = 1;
   const int per = (kblocks + splits - 1) / splits;
   splits = (kblocks + per - 1) / per;
-  g.kchunk = per * TK;
+  g.kchunk = per * BK;
   dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN, splits);
   if (splits == 1) {
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, g);
     return;
   }
   GemmArgs gp = g;
   gp.ep = EP_PART;
   gp.C = part;
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, gp);
+  gp.CT = nullptr;
+  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, st, gp);
   hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for((long)M * N)), dim3(256), 0, st, g, (const float*)part, splits);
 }
 
-// split count so that about `target` workgroups run (k-slices of at least 256)
-int splits_for(int M, int N, int K, int target = 512) {
+// k-splits so that about `target` workgroups run, each slice at least 256 deep
+int splits_for(int M, int N, int K, int target) {
   const int tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
   int s = target / (tiles > 0 ? tiles : 1);
   const int maxs = K / 256 > 0 ? K / 256 : 1;
@@ -417,56 +516,48 @@ int splits_for(int M, int N, int K, int target = 512) {
   return s < 1 ? 1 : s;
 }
 
-// forward through one MLP; acts holds every layer's output (bf16), input H0 given
-void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, long ld0, int M, __bf16* acts,
-             const size_t* off, float* part) {
-  const __bf16* wb = (const __bf16*)t->wbf.ptr;
+// forward through one MLP from H0 (M x Kp0) and its transpose
+void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, Acts& a) {
+  const __bf16* wt = (const __bf16*)t->wtb.ptr;
   const float* mw = (const float*)t->master.ptr;
-  const __bf16* H = H0;
-  long ld = ld0;
+  __bf16* h = (__bf16*)a.h.ptr;
+  __bf16* hT = (__bf16*)a.hT.ptr;
+  const __bf16* in = H0;
   for (size_t li = 0; li < L.size(); ++li) {
     const Layer& y = L[li];
-    __bf16* out = acts + off[li];
     const bool last = li + 1 == L.size();
-    const int sp = splits_for(M, y.N, y.Kp, 256);
-    gemm(t->st, H, ld, 0, wb + y.offW, y.N, 1, M, y.N, y.Kp, out, y.N, last ? EP_BIAS_BF16 : EP_BIAS_TANH_BF16,
-         mw + y.offb, nullptr, sp, part);
-    H = out;
-    ld = y.N;
+    gemm(t->st, in, y.Kp, wt + y.offW, y.Kp, M, y.N, y.Kp, h + a.off[li], y.N, last ? EP_BIAS_BF16 : EP_BIAS_TANH_BF16,
+         mw + y.offb, nullptr, hT + a.off[li], M, splits_for(M, y.N, y.Kp, 256), (float*)t->part.ptr);
+    in = h + a.off[li];
   }
 }
 
-// backward through one MLP given dZ of its last layer (bf16, M x N_last, in dz_a)
-void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, long ld0, int M, const __bf16* acts,
-             const size_t* off, __bf16* dz_a, __bf16* dz_b) {
+// backward through one MLP given dZ of its last layer (row-major dz[0], transposed dzT[0])
+void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, Acts& a, Buffer* dz, Buffer* dzT) {
   const __bf16* wb = (const __bf16*)t->wbf.ptr;
   float* g = (float*)t->grad.ptr;
-  float* dwp = (float*)t->dW.ptr;
-  float* csp = (float*)t->cs.ptr;
-  __bf16* dz = dz_a;
-  __bf16* other = dz_b;
+  const __bf16* h = (const __bf16*)a.h.ptr;
+  const __bf16* hT = (const __bf16*)a.hT.ptr;
+  int cur = 0;
   for (int li = (int)L.size() - 1; li >= 0; --li) {
     const Layer& y = L[li];
-    const __bf16* Hin = li == 0 ? H0 : acts + off[li - 1];
-    const long ldin = li == 0 ? ld0 : L[li - 1].N;
-    // dW = H^T dZ (reduction over the M rows, split)
-    int sp = (int)((size_t)M / 1024);
-    if (sp < 1) sp = 1;
-    const size_t cap = t->dw_slices;
-    const size_t per_slice = (size_t)y.Kp * y.N;
-    if ((size_t)sp * per_slice > cap) sp = (int)(cap / per_slice);
-    gemm(t->st, Hin, ldin, 1, dz, y.N, 1, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, sp, dwp);
-    // db = column sums of dZ
-    const int rows = 1024;
-    const int nb = (M + rows - 1) / rows;
-    hipLaunchKernelGGL(k_colsum, dim3(nb), dim3(256), 0, t->st, dz, M, y.N, rows, csp);
-    hipLaunchKernelGGL(k_rows_sum, dim3(1), dim3(256), 0, t->st, (const float*)csp, nb, y.N, g + y.offb);
+    const __bf16* inT = li == 0 ? H0T : hT + a.off[li - 1];
+    __bf16* d = (__bf16*)dz[cur].ptr;
+    __bf16* dT = (__bf16*)dzT[cur].ptr;
+    // dW = H^T dZ (Kp x N): A = H^T (Kp x M), B = dZ^T (N x M), reduction over the M rows
+    int sp = splits_for(y.Kp, y.N, M, 512);
+    while ((size_t)sp * y.Kp * y.N > t->part_floats && sp > 1) --sp;
+    gemm(t->st, inT, M, dT, M, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, nullptr, 0, sp,
+         (float*)t->part.ptr);
+    // db = row sums of dZ^T
+    hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, t->st, (const __bf16*)dT, (long)M, g + y.offb);
     if (li > 0) {
-      // dZ_below = (dZ W^T) * (1 - H_below^2)
+      // dZ_below = (dZ W^T) * (1 - H_below^2): A = dZ (M x N), B = W (Kp x N, n-major = k-contiguous)
       const Layer& z = L[li - 1];
-      gemm(t->st, dz, y.N, 0, wb + y.offW, y.N, 0, M, z.N, y.N, other, z.N, EP_DTANH_BF16, nullptr,
-           acts + off[li - 1]);
-      std::swap(dz, other);
+      __bf16* dn = (__bf16*)dz[1 - cur].ptr;
+      __bf16* dnT = (__bf16*)dzT[1 - cur].ptr;
+      gemm(t->st, d, y.N, wb + y.offW, y.N, M, z.N, y.N, dn, z.N, EP_DTANH_BF16, nullptr, h + a.off[li - 1], dnT, M);
+      cur = 1 - cur;
     }
   }
 }
@@ -475,23 +566,23 @@ void train_step(don_trainer_s* t, bool update) {
   const int S = t->S, P = t->P, p = t->p;
   const int* ctr = (const int*)t->ctr.ptr;
   const int* idx = (const int*)t->idx.ptr;
-  float* part = (float*)t->dW.ptr;
   const Layer& b0 = t->bl[0];
-  __bf16* bact = (__bf16*)t->bact.ptr;
-  __bf16* tact = (__bf16*)t->tact.ptr;
-  // branch inputs of the batch occupy the front of the branch activation buffer
-  __bf16* Fb = bact;
+  __bf16* Fb = (__bf16*)t->Fb.ptr;
+  __bf16* FbT = (__bf16*)t->FbT.ptr;
   hipLaunchKernelGGL(k_gather, dim3(grid_for(b0.Kp) < 64 ? grid_for(b0.Kp) : 64, S), dim3(256), 0, t->st,
-                     (const __bf16*)t->Fdata.ptr, (long)b0.Kp, idx, ctr, S, Fb);
-  mlp_fwd(t, t->bl, Fb, b0.Kp, S, bact, t->bact_off, part);
-  mlp_fwd(t, t->tl, (const __bf16*)t->X.ptr, t->tl[0].Kp, P, tact, t->tact_off, part);
-  const __bf16* Bout = bact + t->bact_off[t->bl.size() - 1];
-  const __bf16* T = tact + t->tact_off[t->tl.size() - 1];
+                     (const __bf16*)t->Fdata.ptr, (long)b0.Kp, idx, ctr, S, Fb, FbT);
+  mlp_fwd(t, t->bl, Fb, S, t->ba);
+  mlp_fwd(t, t->tl, (const __bf16*)t->X.ptr, P, t->ta);
+  const size_t lb = t->bl.size() - 1, lt = t->tl.size() - 1;
+  const __bf16* Bout = (const __bf16*)t->ba.h.ptr + t->ba.off[lb];
+  const __bf16* T = (const __bf16*)t->ta.h.ptr + t->ta.off[lt];
+  const __bf16* TT = (const __bf16*)t->ta.hT.ptr + t->ta.off[lt];
   __bf16* Bc = (__bf16*)t->Bc.ptr;
-  hipLaunchKernelGGL(k_to_bc, dim3((2 * S * p + 255) / 256), dim3(256), 0, t->st, Bout, S, p, Bc);
+  __bf16* BcT = (__bf16*)t->BcT.ptr;
+  hipLaunchKernelGGL(k_to_bc, dim3((2 * S * p + 255) / 256), dim3(256), 0, t->st, Bout, S, p, Bc, BcT);
   // Ut = Bc T^T (2S x P)
   float* Ut = (float*)t->Ut.ptr;
-  gemm(t->st, Bc, p, 0, T, p, 0, 2 * S, P, p, Ut, P, EP_F32);
+  gemm(t->st, Bc, p, T, p, 2 * S, P, p, Ut, P, EP_F32);
   // loss and dUt
   const int chunk = 4096, nch = (P + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_loss_part, dim3(nch, S), dim3(256), 0, t->st, (const float*)Ut, t->Y, idx, ctr, S, P, chunk,
@@ -499,22 +590,29 @@ void train_step(don_trainer_s* t, bool update) {
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, t->st, (const double*)t->lpart.ptr, S, nch, ctr,
                      (float*)t->wv.ptr, (float*)t->losses.ptr);
   __bf16* dUt = (__bf16*)t->dUt.ptr;
-  hipLaunchKernelGGL(k_dU, dim3(64, S), dim3(256), 0, t->st, (const float*)Ut, t->Y, idx, ctr, (const float*)t->wv.ptr,
-                     S, P, dUt);
-  // dT = dUt^T Bc (P x p) -> dZ of the trunk's last layer; dBc = dUt T (2S x p)
-  __bf16* dz0 = (__bf16*)t->dz0.ptr;
-  gemm(t->st, dUt, P, 1, Bc, p, 1, P, p, 2 * S, dz0, p, EP_BF16);
+  __bf16* dUtT = (__bf16*)t->dUtT.ptr;
+  hipLaunchKernelGGL(k_dU, dim3((P + 63) / 64), dim3(256), 0, t->st, (const float*)Ut, t->Y, idx, ctr,
+                     (const float*)t->wv.ptr, S, P, dUt, dUtT);
+  // dT = dUt^T Bc (P x p): A = dUt^T (P x 2S), B = Bc^T (p x 2S) -> dZ of the trunk's last layer
+  gemm(t->st, dUtT, 2 * S, BcT, 2 * S, P, p, 2 * S, t->dz[0].ptr, p, EP_BF16, nullptr, nullptr,
+       (__bf16*)t->dzT[0].ptr, P);
+  // dBc = dUt T (2S x p): A = dUt (2S x P), B = T^T (p x P), reduction over the points
   float* dBc = (float*)t->dBc.ptr;
-  gemm(t->st, dUt, P, 0, T, p, 1, 2 * S, p, P, dBc, p, EP_F32, nullptr, nullptr, splits_for(2 * S, p, P, 512),
-       (float*)t->dBcp.ptr);
-  __bf16* bdz0 = (__bf16*)t->bdz0.ptr;
-  hipLaunchKernelGGL(k_from_dbc, dim3((2 * S * p + 255) / 256), dim3(256), 0, t->st, (const float*)dBc, S, p, bdz0);
-  mlp_bwd(t, t->tl, (const __bf16*)t->X.ptr, t->tl[0].Kp, P, tact, t->tact_off, dz0, (__bf16*)t->dz1.ptr);
-  mlp_bwd(t, t->bl, Fb, b0.Kp, S, bact, t->bact_off, bdz0, (__bf16*)t->bdz1.ptr);
-  if (update)
+  gemm(t->st, dUt, P, TT, P, 2 * S, p, P, dBc, p, EP_F32, nullptr, nullptr, nullptr, 0, splits_for(2 * S, p, P, 128),
+       (float*)t->part.ptr);
+  hipLaunchKernelGGL(k_from_dbc, dim3((2 * S * p + 255) / 256), dim3(256), 0, t->st, (const float*)dBc, S, p,
+                     (__bf16*)t->bdz[0].ptr, (__bf16*)t->bdzT[0].ptr);
+  mlp_bwd(t, t->tl, (const __bf16*)t->XT.ptr, P, t->ta, t->dz, t->dzT);
+  mlp_bwd(t, t->bl, FbT, S, t->ba, t->bdz, t->bdzT);
+  if (update) {
     hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
                        (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
                        (__bf16*)t->wbf.ptr, t->lr, t->b1, t->b2, t->eps, ctr + 1);
+    for (auto* L : {&t->bl, &t->tl})
+      for (const Layer& y : *L)
+        hipLaunchKernelGGL(k_transpose, dim3(grid_for((long)y.Kp * y.N)), dim3(256), 0, t->st, y.Kp, y.N,
+                           (const __bf16*)t->wbf.ptr + y.offW, (__bf16*)t->wtb.ptr + y.offW);
+  }
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, t->st, (int*)t->ctr.ptr, (int*)t->ctr.ptr + 1, update ? 1 : 0);
 }
 
@@ -530,17 +628,17 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   if (!net || !o || !X) return fail(HELM_E_INVAL, "don_train_create: NULL argument");
   if (net->head != DON_SPLIT_OUTPUT || net->act != DON_TANH)
     return fail(HELM_E_INVAL, "don_train_create: training needs the SPLIT_OUTPUT head and tanh");
-  if (o->batch < 32 || o->batch > 128 || o->batch % 32)
-    return fail(HELM_E_INVAL, "don_train_create: batch %d must be 32, 64, 96 or 128", o->batch);
-  if (o->n_points < 32 || o->n_points % 32)
-    return fail(HELM_E_INVAL, "don_train_create: n_points must be a positive multiple of 32");
+  if (o->batch != 64 && o->batch != 128) return fail(HELM_E_INVAL, "don_train_create: batch %d must be 64 or 128", o->batch);
+  if (o->n_points < 64 || o->n_points % 64)
+    return fail(HELM_E_INVAL, "don_train_create: n_points must be a positive multiple of 64");
   if (o->max_steps < 1) return fail(HELM_E_INVAL, "don_train_create: max_steps < 1");
+  if (net->p % 64) return fail(HELM_E_INVAL, "don_train_create: p must be a multiple of 64");
   for (size_t i = 1; i < net->bw.size(); ++i)
-    if (net->bw[i] > 256 || net->bw[i] % 32)
-      return fail(HELM_E_INVAL, "don_train_create: branch widths after the input must be multiples of 32, <= 256");
+    if (net->bw[i] > 256 || net->bw[i] % 64)
+      return fail(HELM_E_INVAL, "don_train_create: branch widths after the input must be multiples of 64, <= 256");
   for (size_t i = 1; i < net->tw.size(); ++i)
-    if (net->tw[i] > 256 || net->tw[i] % 32)
-      return fail(HELM_E_INVAL, "don_train_create: trunk widths after the input must be multiples of 32, <= 256");
+    if (net->tw[i] > 256 || net->tw[i] % 64)
+      return fail(HELM_E_INVAL, "don_train_create: trunk widths after the input must be multiples of 64, <= 256");
   don_trainer_s* t = new don_trainer_s();
   t->S = o->batch;
   t->P = o->n_points;
@@ -556,7 +654,7 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
     for (size_t i = 0; i + 1 < wd.size(); ++i) {
       Layer y;
       y.K = wd[i];
-      y.Kp = pad32(wd[i]);
+      y.Kp = pad64(wd[i]);
       y.N = wd[i + 1];
       y.offW = off;
       off += ((size_t)y.Kp * y.N + 63) / 64 * 64;
@@ -576,37 +674,41 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   if (hipStreamCreateWithFlags(&t->st, hipStreamNonBlocking) != hipSuccess)
     return fin(fail(HELM_E_HIP, "don_train_create: stream"));
   const size_t S = t->S, P = t->P;
-  size_t bsum = 0, tsum = 0;
-  t->bact_off[0] = (size_t)S * t->bl[0].Kp;  // the gathered inputs come first
-  for (size_t i = 0; i < t->bl.size(); ++i) {
-    t->bact_off[i] = t->bact_off[0] + bsum;
-    bsum += S * t->bl[i].N;
-  }
-  for (size_t i = 0; i < t->tl.size(); ++i) {
-    t->tact_off[i] = tsum;
-    tsum += P * t->tl[i].N;
-  }
+  auto acts = [&](Acts& a, std::vector<Layer>& L, size_t M) -> helm_status {
+    size_t sum = 0;
+    for (auto& y : L) {
+      a.off.push_back(sum);
+      sum += M * y.N;
+    }
+    helm_status e = a.h.ensure(2 * sum);
+    return e ? e : a.hT.ensure(2 * sum);
+  };
   int maxw = 0;
-  for (auto& y : t->tl) maxw = std::max(maxw, std::max(y.N, y.Kp));
-  int maxbw = 0;
-  for (auto& y : t->bl) maxbw = std::max(maxbw, std::max(y.N, y.Kp));
+  for (auto* L : {&t->bl, &t->tl})
+    for (auto& y : *L) maxw = std::max(maxw, y.N);
   size_t maxkn = 0;
-  for (auto& y : t->tl) maxkn = std::max(maxkn, (size_t)y.Kp * y.N);
-  for (auto& y : t->bl) maxkn = std::max(maxkn, (size_t)y.Kp * y.N);
-  // split-k partial space: the largest of the dW slices, the forward splits and dBc's
-  t->dw_slices = std::max<size_t>(maxkn * 128, (size_t)2 * S * t->p * 512);
-  t->dw_slices = std::max<size_t>(t->dw_slices, (size_t)S * 256 * 256);
+  for (auto* L : {&t->bl, &t->tl})
+    for (auto& y : *L) maxkn = std::max(maxkn, (size_t)y.Kp * y.N);
+  // split-k partials: every split product runs at most 512 workgroups of 128 x 128 tiles
+  (void)maxkn;
+  t->part_floats = std::max<size_t>((size_t)512 * TM * TN, (size_t)2 * S * t->p * 512);
   const size_t nch = (P + 4095) / 4096;
+  const size_t Kb = t->bl[0].Kp, Kt = t->tl[0].Kp;
   if ((s = t->master.ensure(4 * t->nparam)) || (s = t->grad.ensure(4 * t->nparam)) ||
       (s = t->mom.ensure(4 * t->nparam)) || (s = t->var.ensure(4 * t->nparam)) || (s = t->wbf.ensure(2 * t->nparam)) ||
-      (s = t->X.ensure(2 * P * t->tl[0].Kp)) || (s = t->bact.ensure(2 * (t->bact_off[0] + bsum))) ||
-      (s = t->tact.ensure(2 * tsum)) || (s = t->dz0.ensure(2 * P * maxw)) || (s = t->dz1.ensure(2 * P * maxw)) ||
-      (s = t->bdz0.ensure(2 * S * maxbw)) || (s = t->bdz1.ensure(2 * S * maxbw)) ||
-      (s = t->Bc.ensure(2 * 2 * S * t->p)) || (s = t->Ut.ensure(4 * 2 * S * P)) || (s = t->dUt.ensure(2 * 2 * S * P)) ||
-      (s = t->dBcp.ensure(4 * (size_t)2 * S * t->p * 512)) || (s = t->dBc.ensure(4 * 2 * S * t->p)) ||
-      (s = t->dW.ensure(4 * t->dw_slices)) || (s = t->cs.ensure(4 * ((P + 1023) / 1024 + 1) * 256)) ||
-      (s = t->lpart.ensure(8 * 2 * S * nch)) || (s = t->wv.ensure(4 * S)) || (s = t->ctr.ensure(64)) ||
-      (s = t->losses.ensure(4 * (size_t)o->max_steps)) || (s = t->idx.ensure(4 * (size_t)o->max_steps * S)))
+      (s = t->wtb.ensure(2 * t->nparam)) || (s = t->X.ensure(2 * P * Kt)) || (s = t->XT.ensure(2 * P * Kt)) ||
+      (s = t->Fb.ensure(2 * S * Kb)) || (s = t->FbT.ensure(2 * S * Kb)) || (s = acts(t->ba, t->bl, S)) ||
+      (s = acts(t->ta, t->tl, P)))
+    return fin(s);
+  for (int k = 0; k < 2; ++k)
+    if ((s = t->dz[k].ensure(2 * P * maxw)) || (s = t->dzT[k].ensure(2 * P * maxw)) ||
+        (s = t->bdz[k].ensure(2 * S * std::max(maxw, 2 * t->p))) || (s = t->bdzT[k].ensure(2 * S * std::max(maxw, 2 * t->p))))
+      return fin(s);
+  if ((s = t->Bc.ensure(2 * 2 * S * t->p)) || (s = t->BcT.ensure(2 * 2 * S * t->p)) || (s = t->Ut.ensure(4 * 2 * S * P)) ||
+      (s = t->dUt.ensure(2 * 2 * S * P)) || (s = t->dUtT.ensure(2 * 2 * S * P)) || (s = t->dBc.ensure(4 * 2 * S * t->p)) ||
+      (s = t->part.ensure(4 * t->part_floats)) || (s = t->lpart.ensure(8 * 2 * S * nch)) || (s = t->wv.ensure(4 * S)) ||
+      (s = t->ctr.ensure(64)) || (s = t->losses.ensure(4 * (size_t)o->max_steps)) ||
+      (s = t->idx.ensure(4 * (size_t)o->max_steps * S)))
     return fin(s);
   // zero the whole flat state (padding rows stay zero), then copy the weights
   hipError_t e = hipMemsetAsync(t->master.ptr, 0, 4 * t->nparam, t->st);
@@ -634,7 +736,11 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   load(t->tl, net->tW, net->tB);
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
                      (const float*)t->master.ptr, (__bf16*)t->wbf.ptr);
-  // trunk inputs: fp64 P x d -> bf16 padded rows
+  for (auto* L : {&t->bl, &t->tl})
+    for (const Layer& y : *L)
+      hipLaunchKernelGGL(k_transpose, dim3(grid_for((long)y.Kp * y.N)), dim3(256), 0, t->st, y.Kp, y.N,
+                         (const __bf16*)t->wbf.ptr + y.offW, (__bf16*)t->wtb.ptr + y.offW);
+  // trunk inputs: fp64 P x d -> bf16 padded rows and their transpose
   {
     Buffer tmp;
     if ((s = tmp.ensure(4 * P * t->d))) return fin(s);
@@ -647,8 +753,8 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
     std::vector<float> fx(hx.begin(), hx.end());
     e = hipMemcpy(tmp.ptr, fx.data(), sizeof(float) * fx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-      hipLaunchKernelGGL(k_pad_rows, dim3(grid_for((long)P * t->tl[0].Kp)), dim3(256), 0, t->st, (long)P, t->d,
-                         (const float*)tmp.ptr, t->tl[0].Kp, (__bf16*)t->X.ptr);
+      hipLaunchKernelGGL(k_pad_rows, dim3(grid_for((long)P * Kt)), dim3(256), 0, t->st, (long)P, t->d,
+                         (const float*)tmp.ptr, (int)Kt, (__bf16*)t->X.ptr, (__bf16*)t->XT.ptr);
     s = e == hipSuccess ? sync(t, "don_train_create") : hip_fail(e, "don_train_create: X");
     tmp.release();
     if (s) return fin(s);
@@ -663,7 +769,7 @@ helm_status don_train_data(don_trainer t, int n, const float* F, const void* Y) 
   helm_status s = t->Fdata.ensure((size_t)2 * n * b0.Kp);
   if (s) return s;
   hipLaunchKernelGGL(k_pad_rows, dim3(grid_for((long)n * b0.Kp)), dim3(256), 0, t->st, (long)n, b0.K, F, b0.Kp,
-                     (__bf16*)t->Fdata.ptr);
+                     (__bf16*)t->Fdata.ptr, (__bf16*)nullptr);
   t->Y = (const float2*)Y;
   t->ndata = n;
   return sync(t, "don_train_data");
@@ -733,6 +839,10 @@ helm_status don_train_apply(don_trainer t, const float* grads, void* stream) {
   hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
                      (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
                      (__bf16*)t->wbf.ptr, t->lr, t->b1, t->b2, t->eps, (const int*)(ctr + 1));
+  for (auto* L : {&t->bl, &t->tl})
+    for (const Layer& y : *L)
+      hipLaunchKernelGGL(k_transpose, dim3(grid_for((long)y.Kp * y.N)), dim3(256), 0, t->st, y.Kp, y.N,
+                         (const __bf16*)t->wbf.ptr + y.offW, (__bf16*)t->wtb.ptr + y.offW);
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, t->st, ctr, ctr + 1, 1);
   return sync(t, "don_train_apply");
 }

@@ -25,10 +25,10 @@ helm = pytest.importorskip("paper_2405_12380_amd.helm")
 NPTS = (16, 16, 16)
 
 
-def _net_and_data(seed=0, n=64, P=None):
+def _net_and_data(seed=0, n=128, P=None):
     g = np.random.default_rng([77, seed])
-    branch = I.glorot_mlp([129, 64, 64, 64], g)
-    trunk = I.glorot_mlp([3, 64, 64, 32], g, first_gain=4.0)
+    branch = I.glorot_mlp([129, 64, 64, 128], g)
+    trunk = I.glorot_mlp([3, 64, 64, 64], g, first_gain=4.0)
     X = I.node_points(NPTS)
     F = g.standard_normal((n, 129)).astype(np.float32)
     Y = (g.standard_normal((n, X.shape[0])) + 1j * g.standard_normal((n, X.shape[0]))).astype(np.complex64)
@@ -36,7 +36,7 @@ def _net_and_data(seed=0, n=64, P=None):
 
 
 def _load(branch, trunk, dtype=None):
-    return helm.DeepONet(dtype or helm.C128, branch, trunk, 32, head="split_output", branch_grid=(4, 4, 4),
+    return helm.DeepONet(dtype or helm.C128, branch, trunk, 64, head="split_output", branch_grid=(4, 4, 4),
                          k_input=True)
 
 
@@ -47,9 +47,9 @@ def _f32(layers):
 def test_grad_parity_with_bf16_oracle():
     branch, trunk, X, F, Y = _net_and_data()
     net = _load(branch, trunk)
-    tr = helm.Trainer(net, X, batch=32, max_steps=4)
+    tr = helm.Trainer(net, X, batch=64, max_steps=4)
     tr.data(torch.as_tensor(F).cuda(), torch.as_tensor(Y).cuda())
-    idx = np.random.default_rng(5).permutation(64)[:32]
+    idx = np.random.default_rng(5).permutation(128)[:64]
     loss, g = tr.grad(idx)
     L_or, gb, gt, _ = T.loss_and_grads(F[idx].astype(np.float64), X, Y[idx].T.astype(np.complex128),
                                        _f32(branch), _f32(trunk), rnd=T.bf16)
@@ -68,7 +68,7 @@ def test_grad_parity_with_bf16_oracle():
 def test_adam_parity():
     branch, trunk, X, F, Y = _net_and_data(1)
     net = _load(branch, trunk)
-    tr = helm.Trainer(net, X, batch=32, max_steps=4, lr=1e-3)
+    tr = helm.Trainer(net, X, batch=64, max_steps=4, lr=1e-3)
     tr.data(torch.as_tensor(F).cuda(), torch.as_tensor(Y).cuda())
     params = T.flat_params(_f32(branch), _f32(trunk))
     params = [p.copy() for p in params]
@@ -93,34 +93,34 @@ def test_training_reduces_loss_on_a_teacher_task():
     must fall over 48 Adam steps."""
     branch, trunk, X, F, _ = _net_and_data(2)
     gt = np.random.default_rng(3)
-    tb = I.glorot_mlp([129, 64, 64, 64], gt)
-    tt = I.glorot_mlp([3, 64, 64, 32], gt, first_gain=4.0)
+    tb = I.glorot_mlp([129, 64, 64, 128], gt)
+    tt = I.glorot_mlp([3, 64, 64, 64], gt, first_gain=4.0)
     Tm = T.mlp_forward(X, tt)[-1]
     Bm = T.mlp_forward(F.astype(np.float64), tb)[-1]
-    Y = (Tm @ Bm[:, :32].T + 1j * (Tm @ Bm[:, 32:].T)).T.astype(np.complex64)
+    Y = (Tm @ Bm[:, :64].T + 1j * (Tm @ Bm[:, 64:].T)).T.astype(np.complex64)
     net = _load(branch, trunk)
-    tr = helm.Trainer(net, X, batch=32, max_steps=48, lr=2e-3)
+    tr = helm.Trainer(net, X, batch=64, max_steps=48, lr=2e-3)
     tr.data(torch.as_tensor(F).cuda(), torch.as_tensor(Y).cuda())
     rng = np.random.default_rng(4)
-    idx = np.concatenate([rng.permutation(64) for _ in range(24)])[:48 * 32]
+    idx = np.concatenate([rng.permutation(128) for _ in range(24)])[:48 * 64]
     losses = tr.steps(idx)
     assert np.all(np.isfinite(losses))
     assert losses[-6:].mean() < 0.7 * losses[:6].mean(), losses
-    ev = tr.eval(np.arange(64))
+    ev = tr.eval(np.arange(128))
     assert ev.mean() < losses[:6].mean()
 
 
 def test_export_updates_inference_and_invalidates_caches():
     branch, trunk, X, F, Y = _net_and_data(3)
     net = _load(branch, trunk)
-    tr = helm.Trainer(net, X, batch=32, max_steps=4)
+    tr = helm.Trainer(net, X, batch=64, max_steps=4)
     tr.data(torch.as_tensor(F).cuda(), torch.as_tensor(Y).cuda())
-    tr.steps(np.arange(64))
+    tr.steps(np.arange(128))
     P2 = I.random_problem(NPTS, seed=2)
     op = helm.Op(NPTS, helm.C128, P2["ksq"], P2["alpha"], P2["mask"])
     r0, Ac0 = helm.coarse_info(op, net, p_used=16)
     tr.export(net)
-    Tg = to_np(net.trunk(op)).reshape(-1, 32)
+    Tg = to_np(net.trunk(op)).reshape(-1, 64)
     trained = tr.unflatten(tr.params(), 1, 3)
     assert rel_err(Tg, don_or.trunk_matrix(X, trained)) <= 1e-12
     r1, Ac1 = helm.coarse_info(op, net, p_used=16)
