@@ -318,7 +318,8 @@ def multigrid(helm, I, torch, dev, N):
     power of two), k = 12 and k = 36 (the paper's multigrid case), with: no
     preconditioner; a V-cycle with 5 + 5 Jacobi sweeps; the DeepONet-MG V-cycle
     (2-1-2 smoothing, trunk basis p = 32 on every level); and the single-level
-    DeepONet preconditioner (n_r = 3, p = 128)."""
+    DeepONet preconditioner (n_r = 3, p = 128).  The V-cycle runs are capped at
+    2000 iterations (plain Jacobi-smoothed coarse grids do not resolve k = 36)."""
     levels = int(round(np.log2(N + 1))) - 2      # coarsest grid 3^3
     res = {"grid": [N, N, N], "levels": levels, "runs": []}
     C = I.config2(0, n=(N, N, N))
@@ -336,7 +337,7 @@ def multigrid(helm, I, torch, dev, N):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s, st = helm.meta_solve(op, net if use_net else None, f, u, kind="gmres", restart=50, tol=1e-6,
-                                    max_iters=20000, omega=0.5, k=k, **kw)
+                                    max_iters=20000 if "mg" not in name else 2000, omega=0.5, k=k, **kw)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
             res["runs"].append({"k": k, "solver": name, "status": s, "iters": st["iters"], "ms": round(ms, 2),
