@@ -494,7 +494,8 @@ def adjoint_gradient(helm, I, torch, dev, N, fd_dirs):
 def stencil_bandwidth(helm, I, torch, dev, N, reps=40):
     """Per-launch duration of each stencil kernel at N^3 (complex128), from the
     library's event timing, against algorithmic bytes (49 B/node for apply,
-    65 B/node for residual, a Jacobi sweep and a fused-colour red-black sweep)."""
+    65 B/node for residual, a Jacobi sweep and a red-black sweep, which runs as
+    one fused pass)."""
     n = (N, N, N)
     nn = N ** 3
     g = np.random.default_rng(1)
@@ -505,7 +506,7 @@ def stencil_bandwidth(helm, I, torch, dev, N, reps=40):
     y = torch.empty_like(x)
     runs = {"apply": lambda: op.apply(x, y), "residual": lambda: op.residual(f, x, y),
             "jacobi": lambda: op.relax(helm.JACOBI, 0.5, 2, f, x),
-            "rbgs": lambda: op.relax(helm.RBGS, 1.0, 1, f, x)}
+            "rbgs": lambda: op.relax(helm.RBGS, 1.0, 2, f, x)}
     by = {"apply": 49.0, "residual": 65.0, "jacobi": 65.0, "rbgs": 65.0}
     out = {"grid": N}
     for name, fn in runs.items():
@@ -517,8 +518,7 @@ def stencil_bandwidth(helm, I, torch, dev, N, reps=40):
         torch.cuda.synchronize()
         cnt, ms, tot = helm.kprof_read(helm.KP_STENCIL)
         helm.kprof_enable(False)
-        sweeps = cnt if name != "rbgs" else cnt / 2
-        us = 1e3 * ms / sweeps
+        us = 1e3 * ms / cnt   # one launch per sweep (red-black: one fused pass)
         gbs = by[name] * nn / (us * 1e-6) / 1e9
         out[name] = {"us": round(us, 1), "GBps": round(gbs, 1), "frac_peak": round(gbs / HBM_PEAK_GBS, 3)}
     buf = torch.empty(2 * 1024 ** 3 // 16, dtype=torch.complex128, device=dev)

@@ -33,9 +33,10 @@ void stencil_resid(const StencilGeom& g, const void* sc, const uint8_t* code, co
 template <typename S>
 void stencil_jacobi(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, const void* u,
                     void* unew, double omega, hipStream_t st);
+// one red-black sweep in a single pass, uin -> uout (must differ)
 template <typename S>
-void stencil_rbgs(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* u,
-                  double omega, hipStream_t st);
+void stencil_rbgs_fused(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, const void* uin,
+                        void* uout, double omega, hipStream_t st);
 template <typename S>
 void jacobi_from_zero(size_t n, double dsum, const void* sc, const uint8_t* mask, const void* f, void* z,
                       double omega, hipStream_t st);

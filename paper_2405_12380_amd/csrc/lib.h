@@ -153,26 +153,24 @@ helm_status vec_norm(helm_op_s* op, const void* x, double* out, hipStream_t st) 
   return HELM_OK;
 }
 
-// `sweeps` relaxation steps in place on u; Jacobi ping-pongs through op->tmp.
+// `sweeps` relaxation steps in place on u; both kinds ping-pong through op->tmp
+// (a red-black sweep is one fused out-of-place pass).
 template <typename S>
 helm_status relax(helm_op_s* op, int kind, double omega, int sweeps, const void* f, void* u, hipStream_t st) {
   if (sweeps <= 0) return HELM_OK;
-  if (kind == HELM_RBGS) {
-    for (int k = 0; k < sweeps; ++k) stencil_rbgs<S>(op->geom, op->sc, op->code, f, u, omega, st);
-    return launch_check("rbgs");
-  }
   helm_status s = op->tmp.ensure(op->nn * op_esz(op));
   if (s) return s;
   void* a = u;
   void* b = op->tmp.ptr;
   for (int k = 0; k < sweeps; ++k) {
-    stencil_jacobi<S>(op->geom, op->sc, op->code, f, a, b, omega, st);
+    if (kind == HELM_RBGS) stencil_rbgs_fused<S>(op->geom, op->sc, op->code, f, a, b, omega, st);
+    else stencil_jacobi<S>(op->geom, op->sc, op->code, f, a, b, omega, st);
     void* t = a;
     a = b;
     b = t;
   }
   if (a != u) copy_vec<S>(op->nn, a, u, st);
-  return launch_check("jacobi");
+  return launch_check("relax");
 }
 
 }  // namespace helm

@@ -81,8 +81,17 @@ helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* 
         }
       }
     } else {
-      zero_vec<S>(n, z, st);
-      for (int k = 0; k < o->n_r; ++k) stencil_rbgs<S>(op->geom, op->sc, op->code, v, z, o->omega, st);
+      // red-black sweeps from zero, ping-ponging so that the last lands in z
+      if ((s = op->tmp.ensure(n * op_esz(op)))) return s;
+      void* a = (o->n_r & 1) ? op->tmp.ptr : z;
+      void* b = (o->n_r & 1) ? z : op->tmp.ptr;
+      zero_vec<S>(n, a, st);
+      for (int k = 0; k < o->n_r; ++k) {
+        stencil_rbgs_fused<S>(op->geom, op->sc, op->code, v, a, b, o->omega, st);
+        void* t = a;
+        a = b;
+        b = t;
+      }
     }
   } else {
     zero_vec<S>(n, z, st);

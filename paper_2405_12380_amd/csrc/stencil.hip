@@ -61,6 +61,148 @@ __global__ __launch_bounds__(512) void k_jacobi2z(StencilGeom g, const cplx_t<S>
   jacobi2z_tile<S, DIM>(g, xcd_remap(blockIdx.x, gridDim.x), sc, code, f, y, omega);
 }
 
+// One red-black Gauss-Seidel sweep in a single pass, out of place (uin -> uout):
+// red nodes ((i + j + z) even) get the relaxation update from uin; black nodes
+// get it from the red values just computed at their six neighbours.  Every
+// thread keeps the new red values of its own column at z - 1, z and z + 1 in
+// registers; the in-plane ones are exchanged through LDS, and threads on the
+// tile's rim recompute the red value of the neighbouring tile's node (from uin,
+// so no other workgroup's output is ever read).  The per-node arithmetic is that
+// of the two colour passes of k_stencil<RBGS>, so the result is the same; HBM
+// sees one pass (uin, f, s and the code byte read, uout written).
+template <typename S>
+__device__ __forceinline__ double2 relax_upd(const StencilGeom& g, unsigned cd, double2 c, double2 a, double2 b,
+                                             double2 e, double2 h, double2 q, double2 w, double2 sp, double2 fp,
+                                             double omega, bool dim3) {
+  double2 ax;
+  if (cd & NB_SELF) {
+    ax = c;
+  } else {
+    a = sel0(cd & NB_XM, a);
+    b = sel0(cd & NB_XP, b);
+    e = sel0(cd & NB_YM, e);
+    h = sel0(cd & NB_YP, h);
+    double2 acc;
+    acc.x = ((c.x - a.x) + (c.x - b.x)) * g.ih2[0];
+    acc.y = ((c.y - a.y) + (c.y - b.y)) * g.ih2[0];
+    acc.x = acc.x + ((c.x - e.x) + (c.x - h.x)) * g.ih2[1];
+    acc.y = acc.y + ((c.y - e.y) + (c.y - h.y)) * g.ih2[1];
+    if (dim3) {
+      q = sel0(cd & NB_ZM, q);
+      w = sel0(cd & NB_ZP, w);
+      acc.x = acc.x + ((c.x - q.x) + (c.x - w.x)) * g.ih2[2];
+      acc.y = acc.y + ((c.y - q.y) + (c.y - w.y)) * g.ih2[2];
+    }
+    ax = csub(acc, cmul(sp, c));
+  }
+  const double2 r = csub(fp, ax);
+  const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
+  const double2 qq = cdiv(r, d);
+  return make_double2(c.x + omega * qq.x, c.y + omega * qq.y);
+}
+
+// the relaxation update at node (i, j, z) from the values of x alone (a red node)
+template <typename S, int DIM>
+__device__ __forceinline__ double2 red_at(const StencilGeom& g, const cplx_t<S>* __restrict__ sc,
+                                          const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ x,
+                                          const cplx_t<S>* __restrict__ f, int i, int j, int z, double omega) {
+  const size_t plane = (size_t)g.nx * g.ny;
+  const size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z);
+  const unsigned cd = code[p];
+  const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
+  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
+  double2 q = czero(), w = czero();
+  if (DIM == 3) {
+    if (z > 0) q = ldc(x, p - plane);
+    if (z + 1 < g.nz) w = ldc(x, p + plane);
+  }
+  return relax_upd<S>(g, cd, ldc(x, p), ldc(x, p + oxm), ldc(x, p + oxp), ldc(x, p + oym), ldc(x, p + oyp), q, w,
+                      ldc(sc, p), ldc(f, p), omega, DIM == 3);
+}
+
+// Thread (tx, ty) owns the node pair x = 2 tx, 2 tx + 1 of row j in a 128 x ty
+// tile: in every plane one of the pair is red and the other black, so every
+// lane does one red and one black update (no checkerboard divergence).  The
+// black node's red neighbours: along x its own red node and the neighbouring
+// lane's (a wavefront is one row; the tile's outer neighbours are recomputed by
+// lanes 0 and 63), along y the red nodes of the rows above and below (LDS; the
+// tile's outer rows recomputed by the first and last row), along z the red
+// values of its own column below and above (the one above is also the red node
+// of the next plane, computed once).
+template <typename S, int DIM>
+__global__ __launch_bounds__(512) void k_rbgs_fused(StencilGeom g, const cplx_t<S>* __restrict__ sc,
+                                                    const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ uin,
+                                                    const cplx_t<S>* __restrict__ f, cplx_t<S>* __restrict__ uout,
+                                                    double omega) {
+  __shared__ double2 red[8][128];  // new red values of the current plane (ty <= 8)
+  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned nbx = (g.nx + 127) / 128, nby = (g.ny + g.ty - 1) / g.ty;
+  const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+  const int tx = threadIdx.x, tyi = threadIdx.y;
+  const int x0 = bx * 128 + 2 * tx;
+  const int j = by * g.ty + tyi;
+  const int z0 = bz * g.zb;
+  const int z1 = min(g.nz, z0 + g.zb);
+  const bool rowin = j < g.ny;
+  // the pair's red node sits at x0 + ((x0 + j + z) & 1); its black node at the other
+  auto xr = [&](int z) { return x0 + ((x0 + j + z) & 1); };
+  auto xb = [&](int z) { return x0 + 1 - ((x0 + j + z) & 1); };
+  auto in = [&](int x) { return rowin && x < g.nx; };
+  // red value of this plane's red node, and of the red node below this plane's black node
+  double2 rcur = czero(), rbelow = czero();
+  if (z0 < z1) {
+    if (in(xr(z0))) rcur = red_at<S, DIM>(g, sc, code, uin, f, xr(z0), j, z0, omega);
+    if (DIM == 3 && z0 > 0 && in(xb(z0))) rbelow = red_at<S, DIM>(g, sc, code, uin, f, xb(z0), j, z0 - 1, omega);
+  }
+  for (int z = z0; z < z1; ++z) {
+    const int r_x = xr(z), b_x = xb(z);
+    // the black node's own inputs, issued first
+    const bool bin = in(b_x);
+    const size_t pb = (size_t)b_x + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z);
+    unsigned cdb = 0;
+    double2 ub = czero(), sb = czero(), fb = czero();
+    if (bin) {
+      cdb = code[pb];
+      ub = ldc(uin, pb);
+      sb = ldc(sc, pb);
+      fb = ldc(f, pb);
+    }
+    // red of the column above the black node: next plane's red node of this pair
+    double2 rabove = czero();
+    if (DIM == 3 && z + 1 < g.nz && in(b_x)) rabove = red_at<S, DIM>(g, sc, code, uin, f, b_x, j, z + 1, omega);
+    // x neighbours of the black node: its own pair's red node and the adjacent lane's
+    const bool red_left = r_x < b_x;  // red at x0, black at x0 + 1: the right neighbour is lane tx + 1's red
+    const double2 nb = make_double2(__shfl(rcur.x, red_left ? (tx + 1) & 63 : (tx + 63) & 63, 64),
+                                    __shfl(rcur.y, red_left ? (tx + 1) & 63 : (tx + 63) & 63, 64));
+    double2 xo = nb;  // the red node on the far side of the black node
+    if (red_left && tx == 63 && in(b_x + 1)) xo = red_at<S, DIM>(g, sc, code, uin, f, b_x + 1, j, z, omega);
+    if (!red_left && tx == 0 && b_x > 0 && rowin) xo = red_at<S, DIM>(g, sc, code, uin, f, b_x - 1, j, z, omega);
+    // y neighbours (same x as the black node) through LDS; the tile's outer rows recomputed
+    red[tyi][r_x - bx * 128] = rcur;
+    double2 ym = czero(), yp = czero();
+    if (tyi == 0 && j > 0 && in(b_x)) ym = red_at<S, DIM>(g, sc, code, uin, f, b_x, j - 1, z, omega);
+    if (tyi == g.ty - 1 && j + 1 < g.ny && in(b_x)) yp = red_at<S, DIM>(g, sc, code, uin, f, b_x, j + 1, z, omega);
+    __syncthreads();
+    if (tyi > 0) ym = red[tyi - 1][b_x - bx * 128];
+    if (tyi < g.ty - 1) yp = red[tyi + 1][b_x - bx * 128];
+    if (in(r_x)) {
+      const size_t pr = (size_t)r_x + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z);
+      stc_out(uout, pr, rcur, g.nt);
+    }
+    if (bin) {
+      const double2 a = red_left ? rcur : xo;   // x - 1
+      const double2 b = red_left ? xo : rcur;   // x + 1
+      const double2 out = relax_upd<S>(g, cdb, ub, a, b, ym, yp, rbelow, rabove, sb, fb, omega, DIM == 3);
+      stc_out(uout, pb, out, g.nt);
+    }
+    __syncthreads();
+    // next plane: this plane's red node is below the next black node (same x), and
+    // the red node above this black node is the next plane's red node
+    rbelow = rcur;
+    rcur = rabove;
+  }
+}
+
 template <typename S>
 void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* z, double omega,
                        hipStream_t st) {
@@ -178,10 +320,22 @@ void stencil_jacobi(const StencilGeom& g, const void* sc, const uint8_t* code, c
   launch_mode<S, ST_JACOBI>(g, sc, code, u, f, unew, omega, 0, nullptr, st);
 }
 template <typename S>
-void stencil_rbgs(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* u, double omega,
-                  hipStream_t st) {
-  launch_mode<S, ST_RBGS>(g, sc, code, u, f, u, omega, 0, nullptr, st);
-  launch_mode<S, ST_RBGS>(g, sc, code, u, f, u, omega, 1, nullptr, st);
+void stencil_rbgs_fused(const StencilGeom& g0, const void* sc, const uint8_t* code, const void* f, const void* uin,
+                        void* uout, double omega, hipStream_t st) {
+  using C = cplx_t<S>;
+  // 128 x 8 tiles: the recomputed rim rows are a quarter of the tile's rows
+  StencilGeom g = g0;
+  g.ty = g.ny >= 8 ? 8 : g0.ty;
+  const int nb = ((g.nx + 127) / 128) * ((g.ny + g.ty - 1) / g.ty) * ((g.nz + g.zb - 1) / g.zb);
+  const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
+  kprof_begin(st);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_rbgs_fused<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)uin,
+                       (const C*)f, (C*)uout, omega);
+  else
+    hipLaunchKernelGGL((k_rbgs_fused<S, 2>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)uin,
+                       (const C*)f, (C*)uout, omega);
+  kprof_end(KP_STENCIL, n * (4 * esz + 1), st);
 }
 template <typename S>
 void jacobi_from_zero(size_t n, double dsum, const void* sc, const uint8_t* mask, const void* f, void* z,
@@ -206,8 +360,8 @@ void build_s(size_t n, const double* ksq, const double* alpha, void* sc, hipStre
                                  void*, double*, hipStream_t);                                              \
   template void stencil_jacobi<S>(const StencilGeom&, const void*, const uint8_t*, const void*, const void*, \
                                   void*, double, hipStream_t);                                              \
-  template void stencil_rbgs<S>(const StencilGeom&, const void*, const uint8_t*, const void*, void*, double, \
-                                hipStream_t);                                                               \
+  template void stencil_rbgs_fused<S>(const StencilGeom&, const void*, const uint8_t*, const void*, const void*, \
+                                      void*, double, hipStream_t);                                          \
   template void jacobi_from_zero<S>(size_t, double, const void*, const uint8_t*, const void*, void*, double,  \
                                     hipStream_t);                                                           \
   template void jacobi2_from_zero<S>(const StencilGeom&, const void*, const uint8_t*, const void*, void*,     \

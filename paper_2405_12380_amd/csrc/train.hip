@@ -105,8 +105,8 @@ __device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, 
 constexpr int CTW = TN + 8;  // LDS row stride of the staged output tile (bf16)
 
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
-  // operand tiles during the k loop; the output tile and its transpose afterwards
-  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * TM * CTW];
+  // operand tiles during the k loop; the output tile (then its transpose) afterwards
+  __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSW];
   __bf16* As = smem;
   __bf16* Bs = smem + TM * LDSW;
   const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
@@ -171,22 +171,19 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
       }
     return;
   }
-  // bf16 results: the tile goes to LDS twice, row-major (C) and column-major
-  // (C^T; a lane's four rows of one column are 8 contiguous bytes there), and
-  // both are written out as 16-byte chunks of contiguous rows
-  __bf16* Cs = smem;             // TM x CTW, reuses the operand tiles (the k loop ended with a barrier)
-  __bf16* CsT = smem + TM * CTW;  // TN x CTW
+  // bf16 results: epilogue math in registers, then the tile goes through LDS
+  // twice, row-major (C) and column-major (C^T; a lane's four rows of one column
+  // are 8 contiguous bytes there), each written out as 16-byte row chunks
+  __bf16* Cs = smem;  // TM x CTW, reuses the operand tiles (the k loop ended with a barrier)
   typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int cl = wn * 64 + j * 16 + (l & 15), col = n0 + cl;
+    const int col = n0 + wn * 64 + j * 16 + (l & 15);
     const bool cin = col < g.N;
     const float bias = (cin && (g.ep == EP_BIAS_BF16 || g.ep == EP_BIAS_TANH_BF16)) ? g.bias[col] : 0.0f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rl0 = wm * 64 + i * 16 + 4 * (l >> 4);
-      const int row0 = m0 + rl0;
-      bf4 r4;
+      const int row0 = m0 + wm * 64 + i * 16 + 4 * (l >> 4);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         float v = acc[i][j][q] + bias;
@@ -195,12 +192,17 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
           const float h = bf2f(g.aux[(long)(row0 + q) * g.ldc + col]);
           v *= 1.0f - h * h;
         }
-        r4[q] = (__bf16)v;
-        Cs[(rl0 + q) * CTW + cl] = r4[q];
+        acc[i][j][q] = v;
       }
-      *(bf4*)(CsT + cl * CTW + rl0) = r4;
     }
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        Cs[(wm * 64 + i * 16 + 4 * (l >> 4) + q) * CTW + wn * 64 + j * 16 + (l & 15)] = (__bf16)acc[i][j][q];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -209,13 +211,21 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     if (row < g.M && col + 8 <= g.N)
       *(bf8*)((__bf16*)g.C + (long)row * g.ldc + col) = *(const bf8*)(Cs + rl * CTW + cq);
   }
-  if (g.CT) {
+  if (!g.CT) return;
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int c = t + 256 * k, cl = c >> 4, rq = (c & 15) * 8;
-      const int col = n0 + cl, row = m0 + rq;
-      if (col < g.N && row + 8 <= g.M) *(bf8*)(g.CT + (long)col * g.ldct + row) = *(const bf8*)(CsT + cl * CTW + rq);
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf4 r4 = {(__bf16)acc[i][j][0], (__bf16)acc[i][j][1], (__bf16)acc[i][j][2], (__bf16)acc[i][j][3]};
+      *(bf4*)(Cs + (wn * 64 + j * 16 + (l & 15)) * CTW + wm * 64 + i * 16 + 4 * (l >> 4)) = r4;
     }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int c = t + 256 * k, cl = c >> 4, rq = (c & 15) * 8;
+    const int col = n0 + cl, row = m0 + rq;
+    if (col < g.N && row + 8 <= g.M) *(bf8*)(g.CT + (long)col * g.ldct + row) = *(const bf8*)(Cs + cl * CTW + rq);
   }
 }
 

@@ -120,6 +120,14 @@ def test_rbgs_tile_independent_and_deterministic():
     op.relax(helm.RBGS, 1.0, 3, f, u1)
     op.relax(helm.RBGS, 1.0, 3, f, u2)
     assert np.array_equal(to_np(u1), to_np(u2))
+    # the fused sweep exchanges red values inside a tile and recomputes them on
+    # the tile's rim: other tilings (8-row tiles, other z-march lengths) must
+    # give the same bits
+    for ty in (8, 4):
+        op.tune(fixed_ty=ty)
+        u3 = op.field(P["x"])
+        op.relax(helm.RBGS, 1.0, 3, f, u3)
+        assert np.array_equal(to_np(u3), to_np(u1))
 
 
 def test_full_size_apply_sampled():
