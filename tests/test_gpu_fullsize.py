@@ -100,7 +100,8 @@ def test_adjoint_gradient_64cube_finite_differences():
     from paper_2405_12380_amd import adjoint as AD
     C = I.config5(n=(64, 64, 64))
     op = make_op(helm, C, helm.C128)
-    sv = AD.Solver(op, _net(C), kind="bicgstab", tol=1e-12, max_iters=40000, n_r=3, omega=0.5, p_used=128, k=C["k"])
+    sv = AD.Solver(op, _net(C), kind="gmres", restart=50, tol=1e-12, max_iters=40000, n_r=3, omega=0.5, p_used=128,
+                   k=C["k"])
     axis, index = C["receiver"]
     f = op.field(C["f"])
     with torch.no_grad():
