@@ -375,11 +375,14 @@ enum { HELM_KP_STENCIL = 0,   /* apply / residual / Jacobi / red-black sweeps   
        HELM_KP_SKINNY = 4,    /* prolongation z += Q c and the DeepONet synthesis   */
        HELM_KP_CGS = 5 };     /* fused CGS pass w -= V h with the partials of V^H w */
 
-/* Enable (1) or disable (0) per-kernel timing for the whole process, clearing
- * earlier records (waits for the device).  While enabled, each launch of a timed
- * kernel is bracketed by two HIP events on its stream, and the algorithmic bytes
- * that launch must move (reads + writes of its operands, each once) are recorded. */
-helm_status helm_kprof_enable(int on);
+/* Per-kernel timing for the whole process: `mask` has bit (1 << HELM_KP_*) set
+ * for each kernel class to time (0 disables, -1 times every class); earlier
+ * records are cleared (waits for the device).  Each launch of an enabled class
+ * is bracketed by two HIP events on its stream, and the algorithmic bytes that
+ * launch must move (reads + writes of its operands, each once) are recorded.
+ * The events themselves lengthen the gap between dependent launches by a few
+ * microseconds, so a timing run enables only the classes it needs. */
+helm_status helm_kprof_enable(int mask);
 /* Totals since the last enable for one kernel class: launches, summed
  * event-measured duration (ms) and summed algorithmic bytes.  Waits for the
  * recorded events. */

@@ -120,7 +120,7 @@ template <typename S>
 void multidot_part(size_t n, const void* V, size_t ldv, int nv, const void* w, double* part, hipStream_t st) {
   using C = cplx_t<S>;
   const int nb = multidot_nblocks(n);
-  kprof_begin(st);
+  kprof_begin(KP_MULTIDOT, st);
   if (md_chunk(n) == 512)
     hipLaunchKernelGGL((k_multidot<S, 512>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, (const C*)w, part);
   else
@@ -165,7 +165,7 @@ void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef,
                 void* out, double* part, hipStream_t st) {
   using C = cplx_t<S>;
   const int nb = red_nblocks(n);
-  kprof_begin(st);
+  kprof_begin(KP_MULTIAXPY, st);
   if (part)
     hipLaunchKernelGGL((k_multi_axpy<S, true>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, coef, sgn,
                        (const C*)base, (C*)out, part);
@@ -177,27 +177,30 @@ void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef,
 
 // ---- fused CGS pass: w' = w - V h and the partials of V^H w' --------------------
 // One element per thread.  The thread's values of every basis vector are
-// loaded once into registers (all loads independent: up to CG_MAX in flight),
-// w' = w - sum_i V_i h_i is formed and stored, and conj(V_i) w' is reduced
-// over the wavefront (butterfly) and then over the four wavefronts of the
-// block in a fixed order: one pass over V instead of two.
+// loaded once into registers (all loads independent), w' = w - sum_i V_i h_i is
+// formed and stored, and conj(V_i) w' is reduced over the wavefront (butterfly)
+// and then over the four wavefronts of the block in a fixed order: one pass over
+// V instead of two.  The kernel is instantiated for NB = 4, 8, ..., 52 register
+// slots and launched with the smallest NB >= nv, so registers, occupancy and the
+// butterfly's length follow the Arnoldi step instead of the longest one.
 constexpr int CG_MAX = 52;
 int cgs_fused_max_nv() { return CG_MAX; }
 int cgs_fused_nblocks(size_t n) { return (int)((n + 255) / 256); }
 
-template <typename S>
+template <typename S, int NB>
 __global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
                                                    const double* __restrict__ h, cplx_t<S>* __restrict__ w,
                                                    double* __restrict__ part) {
-  __shared__ double sh[4][2 * CG_MAX];
+  static_assert(NB % 4 == 0 && NB <= CG_MAX, "slot count: a multiple of 4, at most 52");
+  __shared__ double sh[4][2 * NB];
   const size_t e = blockIdx.x * (size_t)256 + threadIdx.x;
   const bool in = e < n;
-  double2 v[CG_MAX];
+  double2 v[NB];
 #pragma unroll
-  for (int i = 0; i < CG_MAX; ++i) v[i] = (i < nv && in) ? ldc(V + (size_t)i * ldv, e) : czero();
+  for (int i = 0; i < NB; ++i) v[i] = (i < nv && in) ? ldc(V + (size_t)i * ldv, e) : czero();
   double2 s = czero();
 #pragma unroll
-  for (int i = 0; i < CG_MAX; ++i)
+  for (int i = 0; i < NB; ++i)
     if (i < nv) s = cadd(s, cmul(v[i], make_double2(h[2 * i], h[2 * i + 1])));
   double2 wn = czero();
   if (in) {
@@ -207,18 +210,19 @@ __global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __
   }
   // d_i = conj(V_i) w' for all i, reduced over the wavefront by a
   // reduce-scatter butterfly: three halving exchanges (xor 32, 16, 8) leave each
-  // lane 13 of the 104 real values summed over 8 lanes, three plain exchanges
-  // (xor 4, 2, 1) finish them; lane 8g then owns values [13g, 13g + 13).
+  // lane NB/4 of the 2 NB real values summed over 8 lanes, three plain
+  // exchanges (xor 4, 2, 1) finish them; lane 8g then owns values
+  // [g NB/4, (g + 1) NB/4).
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double x[2 * CG_MAX];
+  double x[2 * NB];
 #pragma unroll
-  for (int i = 0; i < CG_MAX; ++i) {
+  for (int i = 0; i < NB; ++i) {
     const double2 d = cconjmul(v[i], wn);  // v[i] = 0 beyond nv
     x[2 * i] = d.x;
     x[2 * i + 1] = d.y;
   }
   const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
-  constexpr int H1 = CG_MAX, H2 = CG_MAX / 2, H3 = CG_MAX / 4;  // 52, 26, 13
+  constexpr int H1 = NB, H2 = NB / 2, H3 = NB / 4;
 #pragma unroll
   for (int q = 0; q < H1; ++q) {
     const double keep = b5 ? x[H1 + q] : x[q], send = b5 ? x[q] : x[H1 + q];
@@ -252,12 +256,22 @@ __global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __
     part[(size_t)blockIdx.x * 2 * nv + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
 }
 
+template <typename S, int NB>
+static void cgs_launch(int nb, size_t n, const cplx_t<S>* V, size_t ldv, int nv, const double* h, cplx_t<S>* w,
+                       double* part, hipStream_t st) {
+  if (nv > NB) {
+    if constexpr (NB < CG_MAX) cgs_launch<S, NB + 4>(nb, n, V, ldv, nv, h, w, part, st);
+    return;
+  }
+  hipLaunchKernelGGL((k_cgs_fused<S, NB>), dim3(nb), dim3(256), 0, st, n, V, ldv, nv, h, w, part);
+}
+
 template <typename S>
 void cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st) {
   using C = cplx_t<S>;
   const int nb = cgs_fused_nblocks(n);
-  kprof_begin(st);
-  hipLaunchKernelGGL((k_cgs_fused<S>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, h, (C*)w, part);
+  kprof_begin(KP_CGS, st);
+  cgs_launch<S, 4>(nb, n, (const C*)V, ldv, nv, h, (C*)w, part, st);
   // V once, w read and written
   kprof_end(KP_CGS, (double)n * 2 * sizeof(S) * (nv + 2), st);
 }

@@ -46,21 +46,21 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
     const double hn = sqrt(ns);
     gs->hn = hn;
     gs->inv_hn = hn != 0.0 ? 1.0 / hn : 0.0;
-    // previous rotations G_i = [[c, s], [-conj(s), c]] on rows (i, i+1)
+    // previous rotations G_i = [[c, s], [-conj(s), c]] on rows (i, i+1); the
+    // running entry t (row i after rotations 0..i-1) stays in registers, so
+    // the dependent chain never waits on LDS
+    double2 t = make_double2(col[0], col[1]);
     for (int i = 0; i < j; ++i) {
-      const double2 a = make_double2(col[2 * i], col[2 * i + 1]);
       const double2 b = make_double2(col[2 * i + 2], col[2 * i + 3]);
       const double c = rc[i];
       const double2 s = make_double2(rs[2 * i], rs[2 * i + 1]);
       const double2 sconj = make_double2(s.x, -s.y);
-      const double2 na = cadd(cscale(a, c), cmul(s, b));
-      const double2 nb = csub(cscale(b, c), cmul(sconj, a));
+      const double2 na = cadd(cscale(t, c), cmul(s, b));
+      t = csub(cscale(b, c), cmul(sconj, t));
       col[2 * i] = na.x;
       col[2 * i + 1] = na.y;
-      col[2 * i + 2] = nb.x;
-      col[2 * i + 3] = nb.y;
     }
-    const double2 a = make_double2(col[2 * j], col[2 * j + 1]);
+    const double2 a = t;
     const double b = hn;
     double c;
     double2 s;

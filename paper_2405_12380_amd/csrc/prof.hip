@@ -1,7 +1,9 @@
-// Optional per-kernel timing: when enabled, the launchers of the hot kernels
-// bracket each launch with a pair of HIP events on the launch stream and
-// record the algorithmic bytes that launch must move.  Reading the totals
-// synchronizes on the recorded events.  Disabled by default (no events).
+// Optional per-kernel timing: when enabled for a kernel class, the launchers of
+// that class bracket each launch with a pair of HIP events on the launch stream
+// and record the algorithmic bytes that launch must move.  Reading the totals
+// synchronizes on the recorded events.  Disabled by default (no events).  Each
+// event pair adds a few microseconds between dependent launches, so a timing
+// run enables only the classes it reports.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -19,7 +21,7 @@ struct Rec {
   double bytes;
 };
 struct Prof {
-  bool on = false;
+  unsigned mask = 0;
   std::vector<Rec> recs[KP_COUNT];
   std::vector<hipEvent_t> pool;
   std::mutex mu;
@@ -47,17 +49,17 @@ Prof g_prof;
 thread_local hipEvent_t t_start = nullptr;
 }  // namespace
 
-bool kprof_on() { return g_prof.on; }
+bool kprof_on() { return g_prof.mask != 0; }
 
-void kprof_begin(hipStream_t st) {
-  if (!g_prof.on) return;
+void kprof_begin(int kind, hipStream_t st) {
+  if (!((g_prof.mask >> kind) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   t_start = g_prof.take();
   (void)hipEventRecord(t_start, st);
 }
 
 void kprof_end(int kind, double bytes, hipStream_t st) {
-  if (!g_prof.on || !t_start) return;
+  if (!((g_prof.mask >> kind) & 1u) || !t_start) return;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   hipEvent_t e = g_prof.take();
   (void)hipEventRecord(e, st);
@@ -71,11 +73,11 @@ using namespace helm;
 
 extern "C" {
 
-helm_status helm_kprof_enable(int on) {
+helm_status helm_kprof_enable(int mask) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   if (hipDeviceSynchronize() != hipSuccess) return fail(HELM_E_HIP, "helm_kprof_enable: device sync failed");
   g_prof.clear();
-  g_prof.on = on != 0;
+  g_prof.mask = (unsigned)mask & ((1u << KP_COUNT) - 1u);
   return HELM_OK;
 }
 

@@ -209,7 +209,7 @@ void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code
   using C = cplx_t<S>;
   const int nb = stencil_blocks(g);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
-  kprof_begin(st);
+  kprof_begin(KP_STENCIL, st);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_jacobi2z<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
                        omega);
@@ -294,7 +294,7 @@ static void launch_mode(const StencilGeom& g, const void* sc, const uint8_t* cod
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   // algorithmic bytes: x, s, the code byte, y (+ f); a red-black colour pass is half a sweep
   const double bytes = MODE == ST_APPLY ? n * (3 * esz + 1) : MODE == ST_RBGS ? n * (4 * esz + 1) / 2 : n * (4 * esz + 1);
-  kprof_begin(st);
+  kprof_begin(KP_STENCIL, st);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_stencil<S, 3, MODE>), dim3(nb), blk, 0, st, g, (const C*)sc, code, (const C*)x,
                        (const C*)f, (C*)y, omega, color, part);
@@ -328,7 +328,7 @@ void stencil_rbgs_fused(const StencilGeom& g0, const void* sc, const uint8_t* co
   g.ty = g.ny >= 8 ? 8 : g0.ty;
   const int nb = ((g.nx + 127) / 128) * ((g.ny + g.ty - 1) / g.ty) * ((g.nz + g.zb - 1) / g.zb);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
-  kprof_begin(st);
+  kprof_begin(KP_STENCIL, st);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_rbgs_fused<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)uin,
                        (const C*)f, (C*)uout, omega);

@@ -479,9 +479,18 @@ class Trainer:
         _check(_lib.don_train_export(self.h, net.h, None), "don_train_export")
 
 
-def kprof_enable(on: bool = True):
-    """Turn per-kernel event timing on (clearing earlier records) or off."""
-    _check(_lib.helm_kprof_enable(1 if on else 0), "helm_kprof_enable")
+def kprof_enable(on: bool = True, kinds=None):
+    """Turn per-kernel event timing on for the classes in `kinds` (all when
+    None), clearing earlier records, or off."""
+    if not on:
+        mask = 0
+    elif kinds is None:
+        mask = -1
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << int(k)
+    _check(_lib.helm_kprof_enable(mask), "helm_kprof_enable")
 
 
 def kprof_read(kind: int):
