@@ -176,53 +176,31 @@ void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef,
 }
 
 // ---- fused CGS pass: w' = w - V h and the partials of V^H w' --------------------
-// One element per thread.  The thread's values of every basis vector are
-// loaded once into registers (all loads independent), w' = w - sum_i V_i h_i is
-// formed and stored, and conj(V_i) w' is reduced over the wavefront (butterfly)
-// and then over the four wavefronts of the block in a fixed order: one pass over
-// V instead of two.  The kernel is instantiated for NB = 4, 8, ..., 52 register
-// slots and launched with the smallest NB >= nv, so registers, occupancy and the
-// butterfly's length follow the Arnoldi step instead of the longest one.
+// One pass over V: w' = w - sum_i V_i h_i is formed and stored, and the partials
+// of conj(V_i) w' are produced from the same loaded values.  Two kernels:
+//
+// k_cgs_fused (nv <= 8): one element per thread, every V_i in registers;
+//   conj(V_i) w' is reduced over the wavefront by a reduce-scatter butterfly
+//   and then over the four wavefronts of the block in a fixed order.
+//   Instantiated for NB = 4 and 8 register slots.
+// k_cgs_split (nv > 8): WAVES wavefronts share each 64-element chunk and
+//   wavefront q holds the vectors i = q, q + WAVES, ... (NW register slots), so
+//   registers per lane stay small while the chunk's loads of all vectors are in
+//   flight at once.  Per chunk: the wavefronts' partial sums of V h meet in LDS,
+//   w' is formed by every wavefront in the same order (only wavefront 0 reads
+//   and writes w; the others take w from LDS), then each wavefront adds
+//   conj(V_i) w' for its vectors; after CH chunks one butterfly per wavefront.
+//   Each vector belongs to one wavefront, so its partial needs no cross-wave sum.
+//   1.4-1.5x faster than the one-element-per-thread form for nv >= 26.
 constexpr int CG_MAX = 52;
 int cgs_fused_max_nv() { return CG_MAX; }
-int cgs_fused_nblocks(size_t n) { return (int)((n + 255) / 256); }
 
-template <typename S, int NB>
-__global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
-                                                   const double* __restrict__ h, cplx_t<S>* __restrict__ w,
-                                                   double* __restrict__ part) {
-  static_assert(NB % 4 == 0 && NB <= CG_MAX, "slot count: a multiple of 4, at most 52");
-  __shared__ double sh[4][2 * NB];
-  const size_t e = blockIdx.x * (size_t)256 + threadIdx.x;
-  const bool in = e < n;
-  double2 v[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) v[i] = (i < nv && in) ? ldc(V + (size_t)i * ldv, e) : czero();
-  double2 s = czero();
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-    if (i < nv) s = cadd(s, cmul(v[i], make_double2(h[2 * i], h[2 * i + 1])));
-  double2 wn = czero();
-  if (in) {
-    wn = csub(ldc(w, e), s);
-    stc(w, e, wn);
-    wn = ldc(w, e);  // the stored (possibly rounded) value enters the inner products
-  }
-  // d_i = conj(V_i) w' for all i, reduced over the wavefront by a
-  // reduce-scatter butterfly: three halving exchanges (xor 32, 16, 8) leave each
-  // lane NB/4 of the 2 NB real values summed over 8 lanes, three plain
-  // exchanges (xor 4, 2, 1) finish them; lane 8g then owns values
-  // [g NB/4, (g + 1) NB/4).
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double x[2 * NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const double2 d = cconjmul(v[i], wn);  // v[i] = 0 beyond nv
-    x[2 * i] = d.x;
-    x[2 * i + 1] = d.y;
-  }
+// reduce-scatter over a wavefront of the 2 NW values x[] (NW a multiple of 4):
+// afterwards lane 8g (g = 0..7) holds values [g NW/4, (g + 1) NW/4) in x[0..NW/4)
+template <int NW>
+__device__ __forceinline__ void wave_rs(double (&x)[2 * NW], int lane) {
   const bool b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
-  constexpr int H1 = NB, H2 = NB / 2, H3 = NB / 4;
+  constexpr int H1 = NW, H2 = NW / 2, H3 = NW / 4;
 #pragma unroll
   for (int q = 0; q < H1; ++q) {
     const double keep = b5 ? x[H1 + q] : x[q], send = b5 ? x[q] : x[H1 + q];
@@ -246,34 +224,143 @@ __global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __
     t += __shfl_xor(t, 1, 64);
     x[q] = t;
   }
-  if ((lane & 7) == 0) {
-    const int g = 4 * b5 + 2 * b4 + b3;
+}
+
+template <typename S, int NB>
+__global__ __launch_bounds__(256) void k_cgs_fused(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
+                                                   const double* __restrict__ h, cplx_t<S>* __restrict__ w,
+                                                   double* __restrict__ part) {
+  static_assert(NB % 4 == 0, "slot count: a multiple of 4");
+  __shared__ double sh[4][2 * NB];
+  const size_t e = blockIdx.x * (size_t)256 + threadIdx.x;
+  const bool in = e < n;
+  double2 v[NB];
 #pragma unroll
-    for (int q = 0; q < H3; ++q) sh[wave][H3 * g + q] = x[q];
+  for (int i = 0; i < NB; ++i) v[i] = (i < nv && in) ? ldc(V + (size_t)i * ldv, e) : czero();
+  double2 s = czero();
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i < nv) s = cadd(s, cmul(v[i], make_double2(h[2 * i], h[2 * i + 1])));
+  double2 wn = czero();
+  if (in) {
+    wn = csub(ldc(w, e), s);
+    stc(w, e, wn);
+    wn = ldc(w, e);  // the stored (possibly rounded) value enters the inner products
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double x[2 * NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const double2 d = cconjmul(v[i], wn);  // v[i] = 0 beyond nv
+    x[2 * i] = d.x;
+    x[2 * i + 1] = d.y;
+  }
+  wave_rs<NB>(x, lane);
+  if ((lane & 7) == 0) {
+    const int g = lane >> 3;
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) sh[wave][(NB / 4) * g + q] = x[q];
   }
   __syncthreads();
   for (int t = threadIdx.x; t < 2 * nv; t += 256)
     part[(size_t)blockIdx.x * 2 * nv + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
 }
 
-template <typename S, int NB>
-static void cgs_launch(int nb, size_t n, const cplx_t<S>* V, size_t ldv, int nv, const double* h, cplx_t<S>* w,
-                       double* part, hipStream_t st) {
-  if (nv > NB) {
-    if constexpr (NB < CG_MAX) cgs_launch<S, NB + 4>(nb, n, V, ldv, nv, h, w, part, st);
-    return;
+template <typename S>
+__device__ __forceinline__ double2 stored(double2 v) {
+  if (sizeof(S) == sizeof(float)) return make_double2((double)(float)v.x, (double)(float)v.y);
+  return v;
+}
+
+template <typename S, int NW, int WAVES, int CH>
+__global__ __launch_bounds__(64 * WAVES) void k_cgs_split(size_t n, const cplx_t<S>* __restrict__ V, size_t ldv,
+                                                        int nv, const double* __restrict__ h,
+                                                        cplx_t<S>* __restrict__ w, double* __restrict__ part) {
+  static_assert(NW % 4 == 0, "slot count: a multiple of 4");
+  __shared__ double2 ss[2][WAVES][64];
+  __shared__ double2 ws[2][64];
+  __shared__ double sh[WAVES][2 * NW];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: h goes to scalar registers
+  double x[2 * NW];
+#pragma unroll
+  for (int k = 0; k < 2 * NW; ++k) x[k] = 0.0;
+  double2 hk[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int i = wave + WAVES * k;
+    hk[k] = i < nv ? make_double2(h[2 * i], h[2 * i + 1]) : czero();
   }
-  hipLaunchKernelGGL((k_cgs_fused<S, NB>), dim3(nb), dim3(256), 0, st, n, V, ldv, nv, h, w, part);
+#pragma unroll 1
+  for (int c = 0; c < CH; ++c) {
+    const size_t e = ((size_t)blockIdx.x * CH + c) * 64 + lane;
+    const bool in = e < n;
+    double2 v[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int i = wave + WAVES * k;
+      v[k] = (i < nv && in) ? ldc(V + (size_t)i * ldv, e) : czero();
+    }
+    double2 s = czero();
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s = cadd(s, cmul(v[k], hk[k]));
+    ss[c & 1][wave][lane] = s;
+    if (wave == 0) ws[c & 1][lane] = in ? ldc(w, e) : czero();
+    __syncthreads();  // (the next write of this buffer comes after the next chunk's barrier)
+    double2 t = czero();
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) t = cadd(t, ss[c & 1][q][lane]);
+    double2 wn = czero();
+    if (in) {
+      wn = stored<S>(csub(ws[c & 1][lane], t));
+      if (wave == 0) stc(w, e, wn);
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const double2 d = cconjmul(v[k], wn);
+      x[2 * k] += d.x;
+      x[2 * k + 1] += d.y;
+    }
+  }
+  wave_rs<NW>(x, lane);
+  if ((lane & 7) == 0) {
+    const int g = lane >> 3;
+#pragma unroll
+    for (int q = 0; q < NW / 4; ++q) sh[wave][(NW / 4) * g + q] = x[q];
+  }
+  __syncthreads();
+  // value 2k + comp of wavefront q belongs to vector i = q + WAVES k
+  for (int t = threadIdx.x; t < 2 * nv; t += 64 * WAVES) {
+    const int i = t >> 1, q = i % WAVES, k = i / WAVES;
+    part[(size_t)blockIdx.x * 2 * nv + t] = sh[q][2 * k + (t & 1)];
+  }
+}
+
+int cgs_fused_nblocks(size_t n, int nv) {
+  const size_t per = nv <= 16 ? 256 : 512;  // elements per workgroup (see cgs_fused)
+  return (int)((n + per - 1) / per);
 }
 
 template <typename S>
-void cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st) {
+int cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st) {
   using C = cplx_t<S>;
-  const int nb = cgs_fused_nblocks(n);
+  const int nb = cgs_fused_nblocks(n, nv);
+  const C* Vc = (const C*)V;
+  C* wc = (C*)w;
   kprof_begin(KP_CGS, st);
-  cgs_launch<S, 4>(nb, n, (const C*)V, ldv, nv, h, (C*)w, part, st);
+  if (nv <= 4)
+    hipLaunchKernelGGL((k_cgs_fused<S, 4>), dim3(nb), dim3(256), 0, st, n, Vc, ldv, nv, h, wc, part);
+  else if (nv <= 8)
+    hipLaunchKernelGGL((k_cgs_fused<S, 8>), dim3(nb), dim3(256), 0, st, n, Vc, ldv, nv, h, wc, part);
+  else if (nv <= 16)  // 4 wavefronts x 4 slots, 4 chunks of 64: 256 elements per workgroup
+    hipLaunchKernelGGL((k_cgs_split<S, 4, 4, 4>), dim3(nb), dim3(256), 0, st, n, Vc, ldv, nv, h, wc, part);
+  else if (nv <= 32)  // 8 wavefronts x 4 slots, 8 chunks: 512 elements per workgroup
+    hipLaunchKernelGGL((k_cgs_split<S, 4, 8, 8>), dim3(nb), dim3(512), 0, st, n, Vc, ldv, nv, h, wc, part);
+  else                // 8 wavefronts x 8 slots (nv <= 64)
+    hipLaunchKernelGGL((k_cgs_split<S, 8, 8, 8>), dim3(nb), dim3(512), 0, st, n, Vc, ldv, nv, h, wc, part);
   // V once, w read and written
   kprof_end(KP_CGS, (double)n * 2 * sizeof(S) * (nv + 2), st);
+  return nb;
 }
 
 // ---- simple vector kernels ----------------------------------------------------
@@ -524,7 +611,7 @@ void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st) {
   template void multidot_part<S>(size_t, const void*, size_t, int, const void*, double*, hipStream_t);         \
   template void multi_axpy<S>(size_t, const void*, size_t, int, const double*, double, const void*, void*,     \
                               double*, hipStream_t);                                                           \
-  template void cgs_fused<S>(size_t, const void*, size_t, int, const double*, void*, double*, hipStream_t);    \
+  template int cgs_fused<S>(size_t, const void*, size_t, int, const double*, void*, double*, hipStream_t);     \
   template void scale_dev<S>(size_t, const void*, const double*, void*, hipStream_t);                          \
   template void scale_host<S>(size_t, const void*, double, void*, hipStream_t);                                \
   template void add_inplace<S>(size_t, const void*, void*, hipStream_t);                                       \

@@ -65,11 +65,12 @@ template <typename S>
 void multi_axpy(size_t n, const void* V, size_t ldv, int nv, const double* coef, double sgn, const void* base,
                 void* out, double* part, hipStream_t st);
 // Fused CGS pass for nv <= cgs_fused_max_nv(): w <- w - sum_i V_i h_i, and
-// part[b][2i..] = per-block partials of conj(V_i) w_new (cgs_fused_nblocks(n) blocks)
+// part[b][2i..] = per-block partials of conj(V_i) w_new over
+// cgs_fused_nblocks(n, nv) blocks (returned; at most (n + 255) / 256)
 int cgs_fused_max_nv();
-int cgs_fused_nblocks(size_t n);
+int cgs_fused_nblocks(size_t n, int nv);
 template <typename S>
-void cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st);
+int cgs_fused(size_t n, const void* V, size_t ldv, int nv, const double* h, void* w, double* part, hipStream_t st);
 // y = x * scal[0] (real scale on device)
 template <typename S>
 void scale_dev(size_t n, const void* x, const double* scal, void* y, hipStream_t st);

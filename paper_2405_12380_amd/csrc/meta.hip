@@ -141,7 +141,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   auto Vj = [&](int j) { return (void*)(V + (size_t)j * fld); };
 
   const int mdb = multidot_nblocks(n), rdb = red_nblocks(n), stb = stencil_nblocks(op->geom);
-  const int cfb = cgs_fused_nblocks(n);
+  const int cfb = cgs_fused_nblocks(n, 1);  // the largest block count of the fused CGS pass
   size_t pneed = (size_t)mdb * 2 * (m + 1);
   const size_t cneed = (size_t)cfb * 2 * (m + 1 < cgs_fused_max_nv() ? m + 1 : cgs_fused_max_nv());
   if (cneed > pneed) pneed = cneed;
@@ -197,8 +197,8 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
       reduce_cols(part, mdb, 2 * (j + 1), h1, st);
       if (j + 1 <= cgs_fused_max_nv()) {
         // first projection and second inner products in one pass over V
-        cgs_fused<S>(n, V, ldv, j + 1, h1, w, part, st);
-        reduce_cols(part, cfb, 2 * (j + 1), h2, st);
+        const int nb = cgs_fused<S>(n, V, ldv, j + 1, h1, w, part, st);
+        reduce_cols(part, nb, 2 * (j + 1), h2, st);
       } else {
         multi_axpy<S>(n, V, ldv, j + 1, h1, -1.0, w, w, nullptr, st);
         multidot_part<S>(n, V, ldv, j + 1, w, part, st);
