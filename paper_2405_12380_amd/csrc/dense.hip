@@ -276,10 +276,10 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
       for (int c = j + t; c < p; c += nt) G[j * p + c] = (c == j) ? piv : G[j * p + c] / piv;
       __syncthreads();
       // trailing update of the upper triangle: G[a][c] -= R[j][a] R[j][c], j < a <= c
-      const int m = p - j - 1;
-      for (int e = t; e < m * m; e += nt) {
-        const int a = j + 1 + e / m, c = j + 1 + e % m;
-        if (c >= a) G[a * p + c] -= G[j * p + a] * G[j * p + c];
+      // (a 32 x 32 thread grid: rows a = j + 1 + ty + 32 u, columns c = a + tx + 32 v)
+      for (int a = j + 1 + (t >> 5); a < p; a += nt >> 5) {
+        const double ra = G[j * p + a];
+        for (int c = a + (t & 31); c < p; c += 32) G[a * p + c] -= ra * G[j * p + c];
       }
     }
     __syncthreads();
@@ -287,19 +287,29 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
   const int r = s_nk;
   // X = R1^{-1}, R1[a][b] = G[kept[a]][kept[b]] (a <= b).  X[a][b] (a < b) is kept
   // at G[kept[b]][kept[a]] (strictly lower, unused by R), X[a][a] in xdiag.
-  for (int b = t; b < r; b += nt) {
-    for (int a = b; a >= 0; --a) {
-      double acc = (a == b) ? 1.0 : 0.0;
-      for (int c = a + 1; c <= b; ++c) {
-        const double xcb = (c == b) ? xdiag[b] : G[kept[b] * p + kept[c]];
-        acc -= G[kept[a] * p + kept[c]] * xcb;
+  // Rows a = r-1 .. 0 in turn; column b of row a is formed by the 8 threads
+  // 8b .. 8b+7, which split the sum over c and combine it with three shuffles.
+  {
+    const int b = t >> 3, sub = t & 7;
+    const bool colb = b < r && (t >> 3) < (nt >> 3);
+    for (int a = r - 1; a >= 0; --a) {
+      double acc = 0.0;
+      if (colb && b >= a)
+        for (int c = a + 1 + sub; c <= b; c += 8) {
+          const double xcb = (c == b) ? xdiag[b] : G[kept[b] * p + kept[c]];
+          acc += G[kept[a] * p + kept[c]] * xcb;
+        }
+      acc += __shfl_xor(acc, 4, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 1, 64);
+      if (colb && b >= a && sub == 0) {
+        const double v = ((a == b ? 1.0 : 0.0) - acc) / G[kept[a] * p + kept[a]];
+        if (a == b) xdiag[b] = v;
+        else G[kept[b] * p + kept[a]] = v;
       }
-      const double v = acc / G[kept[a] * p + kept[a]];
-      if (a == b) xdiag[b] = v;
-      else G[kept[b] * p + kept[a]] = v;
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int e = t; e < p * r; e += nt) S[e] = 0.0;
   __syncthreads();
   for (int e = t; e < r * r; e += nt) {
@@ -328,7 +338,8 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
                                                      int* __restrict__ info, double* __restrict__ cond) {
   __shared__ double2 pcol[128], prow[128], bufk[128], bufp[128];
   __shared__ double pabs[128], csum[128];
-  __shared__ int perm[128];
+  __shared__ double npart[8][128];
+  __shared__ int perm[128], dest[128];
   __shared__ int s_piv, s_bad;
   const int t = threadIdx.x;
   const int i = t >> 3, cb = t & 7, c0 = 16 * cb;
@@ -339,14 +350,22 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     const int c = c0 + q;
     a[q] = (row_in && c < r) ? make_double2(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]) : czero();
   }
-  // ||A||_1: column sums
-  if (t < 128) {
+  // ||A||_1: column sums, column t % 128 over rows t / 128 + 8 u (coalesced), the
+  // eight partials added in order
+  {
+    const int c = t & 127, r0 = t >> 7;
     double sm = 0.0;
-    if (t < r)
-      for (int ii = 0; ii < r; ++ii) sm += hypot(A[2 * ((size_t)ii * r + t)], A[2 * ((size_t)ii * r + t) + 1]);
-    csum[t] = sm;
+    if (c < r)
+      for (int ii = r0; ii < r; ii += 8) sm += hypot(A[2 * ((size_t)ii * r + c)], A[2 * ((size_t)ii * r + c) + 1]);
+    npart[r0][c] = sm;
   }
   if (t == 0) s_bad = 0;
+  __syncthreads();
+  if (t < 128) {
+    double sm = 0.0;
+    for (int q = 0; q < 8; ++q) sm += npart[q][t];
+    csum[t] = sm;
+  }
   __syncthreads();
   for (int k = 0; k < r; ++k) {
     const int kb = k >> 4, kq = k & 15;
@@ -405,13 +424,13 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
       }
       __syncthreads();
     }
-    // scale the pivot row: A[k][k] <- 1, row /= pivot; publish it
+    // scale the pivot row: A[k][k] <- 1, row *= 1 / pivot; publish it
     if (i == k) {
-      const double2 piv = pcol[k];
+      const double2 ipiv = cdiv(make_double2(1.0, 0.0), pcol[k]);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const double2 v = (c0 + q == k) ? make_double2(1.0, 0.0) : a[q];
-        a[q] = cdiv(v, piv);
+        a[q] = cmul(v, ipiv);
         prow[c0 + q] = a[q];
       }
     }
@@ -427,35 +446,44 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     }
     __syncthreads();
   }
+  // The row interchanges are undone as column interchanges in reverse order:
+  // column c of the result is column idx[c] of the eliminated matrix, so every
+  // entry is written once, straight to its final column.
+  if (t == 0) {
+    for (int c = 0; c < r; ++c) dest[c] = c;  // idx, built in place
+    for (int k = r - 1; k >= 0; --k) {
+      const int p = perm[k];
+      const int tmp = dest[k];
+      dest[k] = dest[p];
+      dest[p] = tmp;
+    }
+  }
+  __syncthreads();
+  if (t < r) pcol[dest[t]].x = (double)t;  // inverse map: column idx[c] goes to c
+  __syncthreads();
   if (row_in)
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int c = c0 + q;
       if (c < r) {
-        Ainv[2 * ((size_t)i * r + c)] = a[q].x;
-        Ainv[2 * ((size_t)i * r + c) + 1] = a[q].y;
+        const int to = (int)pcol[c].x;
+        Ainv[2 * ((size_t)i * r + to)] = a[q].x;
+        Ainv[2 * ((size_t)i * r + to) + 1] = a[q].y;
       }
     }
   __syncthreads();
-  // undo the row interchanges: column interchanges in reverse order, row by row
-  if (t < r) {
-    double* row = Ainv + 2 * (size_t)t * r;
-    for (int k = r - 1; k >= 0; --k) {
-      const int p = perm[k];
-      if (p != k) {
-        const double x0 = row[2 * k], x1 = row[2 * k + 1];
-        row[2 * k] = row[2 * p];
-        row[2 * k + 1] = row[2 * p + 1];
-        row[2 * p] = x0;
-        row[2 * p + 1] = x1;
-      }
-    }
+  {
+    const int c = t & 127, r0 = t >> 7;
+    double sm = 0.0;
+    if (c < r)
+      for (int ii = r0; ii < r; ii += 8)
+        sm += hypot(Ainv[2 * ((size_t)ii * r + c)], Ainv[2 * ((size_t)ii * r + c) + 1]);
+    npart[r0][c] = sm;
   }
   __syncthreads();
   if (t < 128) {
     double sm = 0.0;
-    if (t < r)
-      for (int ii = 0; ii < r; ++ii) sm += hypot(Ainv[2 * ((size_t)ii * r + t)], Ainv[2 * ((size_t)ii * r + t) + 1]);
+    for (int q = 0; q < 8; ++q) sm += npart[q][t];
     pabs[t] = sm;
   }
   __syncthreads();
