@@ -25,7 +25,17 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
   __shared__ double sh[16];
   const int w = blockIdx.x;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[(size_t)b * width + w];
+  // four loads per thread in flight at once, added in index order
+  for (int b0 = 0; b0 < nparts; b0 += 4 * 256) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + threadIdx.x + 256 * q;
+      v[q] = b < nparts ? part[(size_t)b * width + w] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc += v[q];
+  }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) out[w] = acc;
 }

@@ -127,9 +127,17 @@ __global__ __launch_bounds__(64) void k_ainv(int r, const double* __restrict__ A
                                              double* __restrict__ c) {
   const int j = blockIdx.x, l = threadIdx.x;
   double2 acc = czero();
-  for (int k = l; k < r; k += 64) {
-    const size_t o = 2 * ((size_t)j * r + k);
-    acc = cadd(acc, cmul(make_double2(Ainv[o], Ainv[o + 1]), make_double2(y[2 * k], y[2 * k + 1])));
+  for (int k0 = 0; k0 < r; k0 += 128) {  // both halves' loads in flight at once
+    double2 a[2], b[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = k0 + l + 64 * q;
+      const size_t o = 2 * ((size_t)j * r + k);
+      a[q] = k < r ? make_double2(Ainv[o], Ainv[o + 1]) : czero();
+      b[q] = k < r ? make_double2(y[2 * k], y[2 * k + 1]) : czero();
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc = cadd(acc, cmul(a[q], b[q]));
   }
   acc.x = wave_sum(acc.x);
   acc.y = wave_sum(acc.y);

@@ -336,7 +336,9 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
 // cond[0] = ||A||_1 ||A^{-1}||_1.
 __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __restrict__ A, double* __restrict__ Ainv,
                                                      int* __restrict__ info, double* __restrict__ cond) {
-  __shared__ double2 pcol[128], prow[128], bufk[128], bufp[128];
+  // prow holds the pivot row with one pad entry per 16 columns: the eight
+  // column blocks a wavefront reads at once then fall in different LDS banks
+  __shared__ double2 pcol[128], prow[128 + 8], bufk[128], bufp[128];
   __shared__ double pabs[128], csum[128];
   __shared__ double npart[8][128];
   __shared__ int perm[128], dest[128];
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
       for (int q = 0; q < 16; ++q) {
         const double2 v = (c0 + q == k) ? make_double2(1.0, 0.0) : a[q];
         a[q] = cmul(v, ipiv);
-        prow[c0 + q] = a[q];
+        prow[c0 + q + cb] = a[q];
       }
     }
     __syncthreads();
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const double2 v = (c0 + q == k) ? czero() : a[q];
-        a[q] = csub(v, cmul(f, prow[c0 + q]));
+        a[q] = csub(v, cmul(f, prow[c0 + q + cb]));
       }
     }
     __syncthreads();

@@ -19,9 +19,18 @@ __device__ static inline void H_set(double* H, int m, int i, int j, double2 v) {
 }
 __device__ static inline double cabs2(double2 a) { return hypot(a.x, a.y); }
 
+// Value held by lane `src` (uniform index) of the wavefront.
+__device__ static inline double lane_read(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // One wavefront: the new column (CGS2 coefficients h1 + h2) and the previous
-// rotations are staged in LDS, lane 0 applies the rotations (inherently
-// sequential, now on LDS), and the column is written back in parallel.
+// rotations are staged in LDS and, for the first 64 rows, in the lanes'
+// registers; lane 0 applies the rotations (inherently sequential), and the
+// column is written back in parallel.
 __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn,
                                                        const double* h1, const double* h2, const double* npart,
                                                        int nparts, GmState* gs, GmState* ghost) {
@@ -29,8 +38,18 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
   __shared__ double rc[1001], rs[2 * 1001];
   const int l = threadIdx.x;
   // ||w||^2 from the per-block partials of the last CGS update (fixed order)
+  // (sixteen loads per lane in flight at once, then added in index order)
   double ns = 0.0;
-  for (int b = l; b < nparts; b += 64) ns += npart[b];
+  for (int b0 = 0; b0 < nparts; b0 += 16 * 64) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int b = b0 + l + 64 * q;
+      v[q] = b < nparts ? npart[b] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ns += v[q];
+  }
   ns = wave_sum(ns);
   for (int i = l; i <= j; i += 64) {
     col[2 * i] = h1[2 * i] + h2[2 * i];
@@ -41,6 +60,12 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
     rs[2 * i] = sn[2 * i];
     rs[2 * i + 1] = sn[2 * i + 1];
   }
+  // lane q also keeps entry q + 1 of the column and rotation q in registers:
+  // the first 64 steps of the rotation chain read them with v_readlane
+  const double2 bq = l + 1 <= j ? make_double2(h1[2 * (l + 1)] + h2[2 * (l + 1)], h1[2 * (l + 1) + 1] + h2[2 * (l + 1) + 1])
+                                : czero();
+  const double cq = l < j ? cs[l] : 0.0;
+  const double2 sq = l < j ? make_double2(sn[2 * l], sn[2 * l + 1]) : czero();
   __syncthreads();
   if (l == 0) {
     const double hn = sqrt(ns);
@@ -51,9 +76,17 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
     // the dependent chain never waits on LDS
     double2 t = make_double2(col[0], col[1]);
     for (int i = 0; i < j; ++i) {
-      const double2 b = make_double2(col[2 * i + 2], col[2 * i + 3]);
-      const double c = rc[i];
-      const double2 s = make_double2(rs[2 * i], rs[2 * i + 1]);
+      double2 b, s;
+      double c;
+      if (i < 64) {
+        b = make_double2(lane_read(bq.x, i), lane_read(bq.y, i));
+        c = lane_read(cq, i);
+        s = make_double2(lane_read(sq.x, i), lane_read(sq.y, i));
+      } else {
+        b = make_double2(col[2 * i + 2], col[2 * i + 3]);
+        c = rc[i];
+        s = make_double2(rs[2 * i], rs[2 * i + 1]);
+      }
       const double2 sconj = make_double2(s.x, -s.y);
       const double2 na = cadd(cscale(t, c), cmul(s, b));
       t = csub(cscale(b, c), cmul(sconj, t));
