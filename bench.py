@@ -128,11 +128,11 @@ def main():
     solve_kw = dict(kind="gmres", restart=50, tol=1e-6, max_iters=5000, n_r=3, omega=0.5, p_used=128,
                     q_fp32=args.q_fp32)
 
-    def step(i):
+    def step(i, **over):
         d = insts[i % len(insts)]
         op = helm.Op(n, dt, d["ksq"], d["alpha"], d["mask"])
         u.zero_()
-        s, st = helm.meta_solve(op, net, d["f"], u, k=d["k"], **solve_kw)
+        s, st = helm.meta_solve(op, net, d["f"], u, k=d["k"], **dict(solve_kw, **over))
         op.close()
         if s != helm.OK:
             raise RuntimeError(f"meta_solve status {s}: {st}")
@@ -205,6 +205,23 @@ def main():
            "solve_ms_mean": round(float(np.mean([s["solve_ms"] for s in stats])), 3),
            "rel_res_max": float(max(s["rel_res"] for s in stats)),
            "roofline": roofline, "kernels": kernels}
+
+    if not args.q_fp32:
+        # the same steps with the trunk basis stored in fp32 (A_c built from the
+        # stored basis, every other quantity complex128): half the bytes of the
+        # two largest streams per iteration.  Not the headline.
+        log("fp32-basis variant")
+        for i in range(2):
+            step(i, q_fp32=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st32 = [step(i, q_fp32=True) for i in range(args.steps)]
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
+        out["fp32_basis"] = {"ms_per_step": round(ms32, 3), "iters": [s["iters"] for s in st32],
+                             "rel_res_max": float(max(s["rel_res"] for s in st32)),
+                             "speedup": round(ms_per_step / ms32, 3)}
+        log(f"fp32 basis: {ms32:.2f} ms/step, iters {out['fp32_basis']['iters']}")
 
     if not args.no_compare:
         log("standalone Krylov comparison")

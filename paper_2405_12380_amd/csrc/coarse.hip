@@ -16,6 +16,7 @@
 //               (re, im) in lane 16 rho.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -33,6 +34,16 @@ static constexpr int QT_MAXB = 512;
 int qt_nblocks(size_t n) {
   size_t nb = (n + 511) / 512;
   if (nb > QT_MAXB) nb = QT_MAXB;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+// the fp32-basis restriction reads half the bytes per row and runs twice the
+// workgroups to keep as many bytes in flight
+static constexpr int QT32_MAXB = 1024;
+int qt_nblocks32(size_t n) {
+  size_t nb = (n + 255) / 256;
+  if (nb > QT32_MAXB) nb = QT32_MAXB;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
@@ -80,46 +91,58 @@ __global__ __launch_bounds__(256) void k_qt_part(size_t n, int r, const T* __res
     part[(size_t)blockIdx.x * 2 * r + e] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
 }
 
-// fp32 basis: lane l owns columns 2l and 2l+1 (one 8-byte load per row, a
-// wavefront reads a 512 B row of 128 columns in one instruction); same sweep.
+// fp32 basis: each half-wavefront takes one row, lane m of it the four
+// columns 4m .. 4m + 3 (one 16-byte load; a wavefront reads two 512 B rows per
+// instruction); groups of four row pairs in the same grid sweep.  Rows whose
+// length r is not a multiple of 4 are read one float at a time.
 template <typename S>
 __global__ __launch_bounds__(256) void k_qt_part32(size_t n, int r, const float* __restrict__ Q,
                                                    const cplx_t<S>* __restrict__ x, double* __restrict__ part) {
-  __shared__ double sh[4][256];
+  constexpr int U = 4;
+  __shared__ double sh[4][2][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c0 = 2 * lane;
-  const bool pair = c0 + 1 < r, single = c0 < r;
-  const size_t W = ((size_t)gridDim.x * blockDim.x) >> 6, ng = (n + 3) / 4;
-  double a0r = 0, a0i = 0, a1r = 0, a1i = 0;
-  auto load2 = [&](size_t ii) -> float2 {
-    if (pair && ((r & 1) == 0)) return *reinterpret_cast<const float2*>(Q + ii * r + c0);
-    return make_float2(single ? Q[ii * r + c0] : 0.f, pair ? Q[ii * r + c0 + 1] : 0.f);
-  };
+  const int h = lane >> 5, m = lane & 31;
+  const bool v4 = (r & 3) == 0;
+  const size_t W = ((size_t)gridDim.x * blockDim.x) >> 6, ng = (n + 2 * U - 1) / (2 * U);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (size_t g = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6; g < ng; g += W) {
-    float2 q[4];
-    double2 xv[4];
+    float4 q[U];
+    double2 xv[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const size_t ii = 4 * g + u;
+    for (int u = 0; u < U; ++u) {
+      const size_t ii = 2 * U * g + 2 * u + h;
       const bool in = ii < n;
       xv[u] = in ? ldc(x, ii) : czero();
-      q[u] = in ? load2(ii) : make_float2(0.f, 0.f);
+      if (in && v4 && 4 * m < r) {
+        q[u] = *reinterpret_cast<const float4*>(Q + ii * r + 4 * m);
+      } else {
+        const float* row = Q + ii * r;
+        const int c = 4 * m;
+        q[u] = make_float4(in && c < r ? row[c] : 0.f, in && c + 1 < r ? row[c + 1] : 0.f,
+                           in && c + 2 < r ? row[c + 2] : 0.f, in && c + 3 < r ? row[c + 3] : 0.f);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a0r += (double)q[u].x * xv[u].x;
-      a0i += (double)q[u].x * xv[u].y;
-      a1r += (double)q[u].y * xv[u].x;
-      a1i += (double)q[u].y * xv[u].y;
+    for (int u = 0; u < U; ++u) {
+      acc[0] += (double)q[u].x * xv[u].x;
+      acc[1] += (double)q[u].x * xv[u].y;
+      acc[2] += (double)q[u].y * xv[u].x;
+      acc[3] += (double)q[u].y * xv[u].y;
+      acc[4] += (double)q[u].z * xv[u].x;
+      acc[5] += (double)q[u].z * xv[u].y;
+      acc[6] += (double)q[u].w * xv[u].x;
+      acc[7] += (double)q[u].w * xv[u].y;
     }
   }
-  sh[wave][2 * c0] = a0r;
-  sh[wave][2 * c0 + 1] = a0i;
-  sh[wave][2 * c0 + 2] = a1r;
-  sh[wave][2 * c0 + 3] = a1i;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[wave][h][8 * m + k] = acc[k];  // = 2 column + (re, im)
   __syncthreads();
-  for (int e = threadIdx.x; e < 2 * r; e += blockDim.x)
-    part[(size_t)blockIdx.x * 2 * r + e] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
+  for (int e = threadIdx.x; e < 2 * r; e += blockDim.x) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) v += sh[w][0][e] + sh[w][1][e];
+    part[(size_t)blockIdx.x * 2 * r + e] = v;
+  }
 }
 
 // c = Ainv y: block j computes row j (r x r complex, row-major)
@@ -155,64 +178,55 @@ __global__ __launch_bounds__(256) void k_skinny(size_t n, int r, const T* __rest
                           ((size_t)gridDim.x * blockDim.x) >> 6);
 }
 
-// fp32 basis version of k_skinny: lane l owns columns 2l, 2l+1 (one 8-byte
-// load per row); same butterfly over four rows.
+// fp32 basis version of k_skinny: one row per thread, the row read in 16-byte
+// pieces (one float at a time when r is not a multiple of 4), c staged in LDS;
+// no cross-lane reduction, so the half-size rows do not leave the shuffles
+// dominant.  Same two modes as k_skinny.
 template <typename S, int MODE>
 __global__ __launch_bounds__(256) void k_skinny32(size_t n, int r, const float* __restrict__ Q,
                                                   const double* __restrict__ c, cplx_t<S>* __restrict__ z,
                                                   const uint8_t* __restrict__ mask, const double* __restrict__ scal) {
-  const int lane = threadIdx.x & 63;
-  const size_t wave_g = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6;
-  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
-  const int c0 = 2 * lane;
-  const bool pair = c0 + 1 < r, single = c0 < r;
-  const double2 cc0 = single ? make_double2(c[2 * c0], c[2 * c0 + 1]) : czero();
-  const double2 cc1 = pair ? make_double2(c[2 * c0 + 2], c[2 * c0 + 3]) : czero();
+  __shared__ double2 cs[128];
+  const int t = threadIdx.x;
+  if (t < 128) cs[t] = t < r ? make_double2(c[2 * t], c[2 * t + 1]) : czero();
+  __syncthreads();
   double sc = 1.0;
   if (MODE == SK_SYNTH) sc = scal[0];
-  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
-  for (size_t i = wave_g * 4; i < n; i += nwaves * 4) {
-    double v[8];
+  const bool v4 = (r & 3) == 0;
+  const int nq = (r + 3) / 4;  // 16-byte pieces per row (at most 32)
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + t; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float* row = Q + i * r;
+    double yr = 0.0, yi = 0.0;
+#pragma unroll 1
+    for (int j0 = 0; j0 < nq; j0 += 8) {
+      float4 q[8];
 #pragma unroll
-    for (int rho = 0; rho < 4; ++rho) {
-      const size_t ii = i + rho;
-      float2 q = make_float2(0.f, 0.f);
-      if (ii < n) {
-        if (pair && ((r & 1) == 0)) q = *reinterpret_cast<const float2*>(Q + ii * r + c0);
-        else q = make_float2(single ? Q[ii * r + c0] : 0.f, pair ? Q[ii * r + c0 + 1] : 0.f);
+      for (int u = 0; u < 8; ++u) {
+        const int cq = 4 * (j0 + u);
+        if (j0 + u < nq && v4) {
+          q[u] = *reinterpret_cast<const float4*>(row + cq);
+        } else {
+          q[u] = make_float4(cq < r ? row[cq] : 0.f, cq + 1 < r ? row[cq + 1] : 0.f, cq + 2 < r ? row[cq + 2] : 0.f,
+                             cq + 3 < r ? row[cq + 3] : 0.f);
+        }
       }
-      v[2 * rho] = (double)q.x * cc0.x + (double)q.y * cc1.x;
-      v[2 * rho + 1] = (double)q.x * cc0.y + (double)q.y * cc1.y;
-    }
-    double w4[4];
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const double send = v[4 * (1 - b5) + qq];
-      w4[qq] = v[4 * b5 + qq] + __shfl_xor(send, 32, 64);
-    }
-    double w2[2];
-#pragma unroll
-    for (int qq = 0; qq < 2; ++qq) {
-      const double send = w4[2 * (1 - b4) + qq];
-      w2[qq] = w4[2 * b4 + qq] + __shfl_xor(send, 16, 64);
-    }
-    double w1;
-    {
-      const double send = w2[1 - b3];
-      w1 = w2[b3] + __shfl_xor(send, 8, 64);
-    }
-    w1 += __shfl_xor(w1, 4, 64);
-    w1 += __shfl_xor(w1, 2, 64);
-    w1 += __shfl_xor(w1, 1, 64);
-    const double other = __shfl_xor(w1, 8, 64);
-    if ((lane & 15) == 0) {
-      const size_t ii = i + 2 * b5 + b4;
-      if (ii < n) {
-        const double2 y = make_double2(w1, other);
-        if (MODE == SK_ADD) stc(z, ii, cadd(ldc(z, ii), y));
-        else stc(z, ii, mask[ii] ? czero() : cscale(y, sc));
+      for (int u = 0; u < 8; ++u) {
+        const int cq = 4 * (j0 + u);  // <= 124: cs[] beyond r holds zeros
+        const double2 c0 = cs[cq], c1 = cs[cq + 1], c2 = cs[cq + 2], c3 = cs[cq + 3];
+        yr += (double)q[u].x * c0.x;
+        yi += (double)q[u].x * c0.y;
+        yr += (double)q[u].y * c1.x;
+        yi += (double)q[u].y * c1.y;
+        yr += (double)q[u].z * c2.x;
+        yi += (double)q[u].z * c2.y;
+        yr += (double)q[u].w * c3.x;
+        yi += (double)q[u].w * c3.y;
       }
     }
+    const double2 y = make_double2(yr, yi);
+    if (MODE == SK_ADD) stc(z, i, cadd(ldc(z, i), y));
+    else stc(z, i, mask[i] ? czero() : cscale(y, sc));
   }
 }
 
@@ -294,15 +308,17 @@ static unsigned ew_grid(size_t total) {
 }
 
 // ---- launchers used by other units ------------------------------------------------
+// returns the number of partial rows written
 template <typename T, typename S>
-void qt_partials(size_t n, int r, const T* Q, const void* x, double* part, hipStream_t st) {
-  const int nb = qt_nblocks(n);
+int qt_partials(size_t n, int r, const T* Q, const void* x, double* part, hipStream_t st) {
+  const int nb = sizeof(T) == sizeof(float) ? qt_nblocks32(n) : qt_nblocks(n);
   kprof_begin(KP_QT, st);
   if (sizeof(T) == sizeof(float))
     hipLaunchKernelGGL((k_qt_part32<S>), dim3(nb), dim3(256), 0, st, n, r, (const float*)Q, (const cplx_t<S>*)x, part);
   else
     hipLaunchKernelGGL((k_qt_part<T, S>), dim3(nb), dim3(256), 0, st, n, r, Q, (const cplx_t<S>*)x, part);
   kprof_end(KP_QT, (double)n * (sizeof(T) * r + 2 * sizeof(S)), st);
+  return nb;
 }
 
 template <typename T, typename S>
@@ -315,6 +331,8 @@ void skinny_apply(size_t n, int r, const T* Q, const double* c, void* z, const u
   kprof_begin(KP_SKINNY, st);
   if (sizeof(T) == sizeof(float)) {
     const float* Qf = (const float*)Q;
+    nb = (n + 255) / 256;  // one row per thread, grid-strided
+    if (nb > 1024) nb = 1024;
     if (synth)
       hipLaunchKernelGGL((k_skinny32<S, SK_SYNTH>), dim3((unsigned)nb), dim3(256), 0, st, n, r, Qf, c, (cplx_t<S>*)z,
                          mask, scal);
@@ -443,7 +461,7 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   hipLaunchKernelGGL((k_im_s<S>), dim3(ew_grid(n)), dim3(256), 0, st, n, (const cplx_t<S>*)op->sc, wim);
   gram(n, r, Q, r, Q, r, wim, part, aim, st);
   if ((s = c.Ac.ensure(2 * sizeof(double) * r * r)) || (s = c.Ainv.ensure(2 * sizeof(double) * r * r)) ||
-      (s = c.qpart.ensure(sizeof(double) * 2 * (size_t)r * qt_nblocks(n))))
+      (s = c.qpart.ensure(sizeof(double) * 2 * (size_t)r * std::max(qt_nblocks(n), qt_nblocks32(n)))))
     return s;
   hipLaunchKernelGGL(k_combine_ac, dim3((r * r + 255) / 256), dim3(256), 0, st, r * r, are, aim, (double*)c.Ac.ptr);
   gj_inverse(r, (const double*)c.Ac.ptr, gjw, (double*)c.Ainv.ptr, info, cond, st);
@@ -483,12 +501,11 @@ helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t s
   const int r = c.rank;
   if (r == 0) return HELM_OK;
   const size_t n = op->nn;
-  const int nb = qt_nblocks(n);
   double* part = (double*)c.qpart.ptr;
   double* y = op->red + 1024;
   double* cc = op->red + 2048;
-  if (c.q_f32) qt_partials<float, S>(n, r, (const float*)c.Q.ptr, r1, part, st);
-  else qt_partials<double, S>(n, r, (const double*)c.Q.ptr, r1, part, st);
+  const int nb = c.q_f32 ? qt_partials<float, S>(n, r, (const float*)c.Q.ptr, r1, part, st)
+                         : qt_partials<double, S>(n, r, (const double*)c.Q.ptr, r1, part, st);
   reduce_cols(part, nb, 2 * r, y, st);
   hipLaunchKernelGGL(k_ainv, dim3(r), dim3(64), 0, st, r, (const double*)c.Ainv.ptr, y, cc);
   if (c.q_f32) skinny_apply<float, S>(n, r, (const float*)c.Q.ptr, cc, z, op->mask, nullptr, 0, st);

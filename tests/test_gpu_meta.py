@@ -107,18 +107,21 @@ def test_full_basis_one_iteration():
         assert st == helm.OK and stats["iters"] == 1, stats
 
 
-@pytest.mark.parametrize("kind,iters", [("gmres", 12), ("bicgstab", 6)])
-def test_meta_krylov_fp32_basis(kind, iters):
+@pytest.mark.parametrize("kind,iters,n,p_used", [("gmres", 12, 16, 64), ("bicgstab", 6, 16, 64),
+                                                 ("gmres", 10, 15, 30)])
+def test_meta_krylov_fp32_basis(kind, iters, n, p_used):
     """Basis stored in fp32 (A_c from the stored basis) against the oracle with
-    the same rounding of Q, complex128 elsewhere."""
-    C, s, op, net, cs = _setup(16, 64, q_round="f32")
-    r, Ac, Q = helm.coarse_info(op, net, p_used=64, want_q=True, q_fp32=True)
+    the same rounding of Q, complex128 elsewhere.  15^3 with 30 columns: a row
+    count that is not a multiple of the kernels' row groups and a row length
+    that is not a multiple of four floats."""
+    C, s, op, net, cs = _setup(n, p_used, q_round="f32")
+    r, Ac, Q = helm.coarse_info(op, net, p_used=p_used, want_q=True, q_fp32=True)
     assert Q.dtype == torch.float32 and r == cs.rank
     assert rel_err(Ac, cs.Ac) <= 1e-10
     M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
     u_or, info = meta_or.krylov_meta(kind, C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 0.0, iters, precond=M)
     u = op.field()
     st, stats = helm.meta_solve(op, net, op.field(C["f"]), u, kind=kind, restart=50, tol=0.0, max_iters=iters, n_r=3,
-                                omega=0.5, p_used=64, q_fp32=True)
+                                omega=0.5, p_used=p_used, q_fp32=True)
     assert stats["iters"] == iters
     assert rel_err(to_np(u), u_or) <= 1e-10
