@@ -153,13 +153,26 @@ __global__ __launch_bounds__(64) void k_backsolve(int k, int m, const double* H,
   const int l = threadIdx.x;
   const bool staged = k <= BS_LDS_MAX;
   if (staged)
-    for (int i = 0; i < k; ++i)
-      for (int c = i + l; c < k; c += 64) {
-        const double2 v = H_at(H, m, i, c);
-        const int o = tri(k, i, c);
-        hl[2 * o] = v.x;
-        hl[2 * o + 1] = v.y;
+    // the k x k square in batches of 8 entries per lane: the loads of a batch are
+    // in flight together before any of them is stored (entries below the
+    // diagonal are skipped)
+    for (int e0 = 0; e0 < k * k; e0 += 8 * 64) {
+      double2 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + l + 64 * q, i = e / k, c = e % k;
+        v[q] = (e < k * k && c >= i) ? H_at(H, m, i, c) : czero();
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + l + 64 * q, i = e / k, c = e % k;
+        if (e < k * k && c >= i) {
+          const int o = tri(k, i, c);
+          hl[2 * o] = v[q].x;
+          hl[2 * o + 1] = v[q].y;
+        }
+      }
+    }
   __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
     double2 acc = czero();
