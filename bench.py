@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=64, help="grid nodes per axis of the solve workload")
     ap.add_argument("--stencil-n", type=int, default=256, help="grid nodes per axis of the bandwidth runs")
+    ap.add_argument("--stencil-n2", type=int, default=384, help="a second, larger bandwidth grid (0 skips it)")
     ap.add_argument("--no-compare", action="store_true", help="skip the standalone Krylov comparison runs")
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -265,6 +266,9 @@ def main():
     if not args.no_stencil:
         log(f"stencil bandwidth at {args.stencil_n}^3")
         out["stencil"] = stencil_bandwidth(helm, I, torch, dev, args.stencil_n)
+        if args.stencil_n2 > 0:
+            log(f"stencil bandwidth at {args.stencil_n2}^3")
+            out["stencil_large"] = stencil_bandwidth(helm, I, torch, dev, args.stencil_n2, reps=10)
 
     if not args.no_batch:
         log(f"batched workload: {args.batch_count} problems")
