@@ -40,10 +40,12 @@ void stencil_rbgs_fused(const StencilGeom& g, const void* sc, const uint8_t* cod
 template <typename S>
 void jacobi_from_zero(size_t n, double dsum, const void* sc, const uint8_t* mask, const void* f, void* z,
                       double omega, hipStream_t st);
-// two Jacobi sweeps on A z = f from z = 0 in one pass (z must not alias f)
+// two Jacobi sweeps on A z = f from z = 0 in one pass (z must not alias f).
+// With fscale (device scalar) the right-hand side is fscale[0] * f, and fout
+// (optional, must alias neither f nor z) receives it.
 template <typename S>
 void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* z, double omega,
-                       hipStream_t st);
+                       hipStream_t st, const double* fscale = nullptr, void* fout = nullptr);
 template <typename S>
 void build_s(size_t n, const double* ksq, const double* alpha, void* sc, hipStream_t st);
 

@@ -55,11 +55,21 @@ struct MetaCtx {
 
 // z = M(v): n_r smoother sweeps on A z = v from z = 0, then the coarse
 // correction z += Q A_c^{-1} Q^T (v - A z).
+// With vscale (device scalar) the input is vscale[0] * v, and that scaled
+// vector is also written to vout (the GMRES basis vector, normalized on the
+// way in): the two-sweep Jacobi kernel scales as it loads, other paths scale
+// in a separate pass first.
 template <typename S>
-helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* z, hipStream_t st) {
+helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* z, hipStream_t st,
+                          const double* vscale = nullptr, void* vout = nullptr) {
   const meta_opts* o = c.o;
-  if (o->mg_levels > 0) return mg_apply<S>(op, c.net, o, v, z, st);
   const size_t n = op->nn;
+  if (vscale && !(o->mg_levels == 0 && o->n_r >= 2 && o->smoother == HELM_JACOBI)) {
+    scale_dev<S>(n, v, vscale, vout, st);
+    v = vout;
+    vscale = nullptr;
+  }
+  if (o->mg_levels > 0) return mg_apply<S>(op, c.net, o, v, z, st);
   helm_status s;
   if (o->n_r > 0) {
     if (o->smoother == HELM_JACOBI) {
@@ -72,7 +82,8 @@ helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* 
         const int rest = o->n_r - 2;
         void* a = (rest & 1) ? op->tmp.ptr : z;
         void* b = (rest & 1) ? z : op->tmp.ptr;
-        jacobi2_from_zero<S>(op->geom, op->sc, op->code, v, a, o->omega, st);
+        jacobi2_from_zero<S>(op->geom, op->sc, op->code, v, a, o->omega, st, vscale, vout);
+        if (vscale) v = vout;  // the later sweeps and the residual read the scaled vector
         for (int k = 0; k < rest; ++k) {
           stencil_jacobi<S>(op->geom, op->sc, op->code, v, a, b, o->omega, st);
           void* t = a;
@@ -121,10 +132,11 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   const size_t n = op->nn, esz = op_esz(op);
   const size_t fld = Carve::need(n * esz);
   const size_t dsm = Carve::need(sizeof(double) * (2 * (size_t)(m + 1) * m + 8 * (size_t)(m + 1) + 64));
-  helm_status s = op->ws.ensure(fld * (size_t)(m + 1 + 3) + dsm + Carve::need(sizeof(GmState)));
+  helm_status s = op->ws.ensure(fld * (size_t)(m + 1 + 4) + dsm + Carve::need(sizeof(GmState)));
   if (s) return s;
   Carve cv(op->ws.ptr);
   char* V = (char*)cv.take(fld * (m + 1));
+  void* W = cv.take(n * esz);  // the new Arnoldi vector before normalization
   void* z = cv.take(n * esz);
   void* t = cv.take(n * esz);
   c.r1 = cv.take(n * esz);
@@ -182,16 +194,21 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
     if (count >= o->max_iters) break;
     scale_host<S>(n, Vj(0), 1.0 / beta, Vj(0), st);
     gmres_init(beta, g, m, st);
-    // One Arnoldi step: z = M v_j, w = A z into V_{j+1}, CGS2, Givens, scale.
+    // One Arnoldi step: z = M v_j, w = A z into W, CGS2, Givens.  W stays
+    // unnormalized; the next step forms v_{j+1} = W / ||W|| as its first kernel
+    // reads it (inside the two-sweep Jacobi kernel, or a scaling pass).
     // Its status record is copied to pinned slot j & 1 and an event marks it.
     auto enqueue_step = [&](int j) -> helm_status {
       const void* zj = Vj(j);
+      const double* vsc = j > 0 ? &gs->inv_hn : nullptr;
       if (c.use_M) {
-        helm_status e2 = precond_apply<S>(op, c, Vj(j), z, st);
+        helm_status e2 = j > 0 ? precond_apply<S>(op, c, W, z, st, vsc, Vj(j)) : precond_apply<S>(op, c, Vj(j), z, st);
         if (e2) return e2;
         zj = z;
+      } else if (j > 0) {
+        scale_dev<S>(n, W, vsc, Vj(j), st);
       }
-      void* w = Vj(j + 1);
+      void* w = W;
       stencil_apply<S>(op->geom, op->sc, op->code, zj, w, st);
       multidot_part<S>(n, V, ldv, j + 1, w, part, st);
       reduce_cols(part, mdb, 2 * (j + 1), h1, st);
@@ -208,15 +225,15 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
       arnoldi_finish(j, m, H, g, cs, sn, h1, h2, part, rdb, gs, slot_dev[j & 1], st);
       hipError_t e1 = hipEventRecord(ev[j & 1], st);
       if (e1 != hipSuccess) return hip_fail(e1, "gmres: status event");
-      scale_dev<S>(n, w, &gs->inv_hn, w, st);
       return launch_check("gmres: arnoldi step");
     };
     int k = 0;
     if ((s = enqueue_step(0))) return s;
     for (int j = 0; j < m; ++j) {
       // look ahead: queue step j+1 before waiting for step j's status; if step j
-      // ends the cycle the queued step is discarded (it only touches V_{j+2},
-      // column j+1 of H and g[j+1..j+2], none of which the back-solve reads)
+      // ends the cycle the queued step is discarded (it only touches V_{j+1}, W,
+      // column j+1 of H and g[j+1..j+2], none of which the back-solve and the
+      // update u += M(V_{0..j} y) read)
       if (j + 1 < m && count + 1 < o->max_iters)
         if ((s = enqueue_step(j + 1))) return s;
       hipError_t e1 = hipEventSynchronize(ev[j & 1]);

@@ -57,8 +57,9 @@ __global__ __launch_bounds__(512) void k_stencil(StencilGeom g, const cplx_t<S>*
 template <typename S, int DIM>
 __global__ __launch_bounds__(512) void k_jacobi2z(StencilGeom g, const cplx_t<S>* __restrict__ sc,
                                                   const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ f,
-                                                  cplx_t<S>* __restrict__ y, double omega) {
-  jacobi2z_tile<S, DIM>(g, xcd_remap(blockIdx.x, gridDim.x), sc, code, f, y, omega);
+                                                  cplx_t<S>* __restrict__ y, double omega,
+                                                  const double* __restrict__ fscale, cplx_t<S>* __restrict__ fout) {
+  jacobi2z_tile<S, DIM>(g, xcd_remap(blockIdx.x, gridDim.x), sc, code, f, y, omega, fscale, fout);
 }
 
 // One red-black Gauss-Seidel sweep in a single pass, out of place (uin -> uout):
@@ -205,18 +206,18 @@ __global__ __launch_bounds__(512) void k_rbgs_fused(StencilGeom g, const cplx_t<
 
 template <typename S>
 void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* z, double omega,
-                       hipStream_t st) {
+                       hipStream_t st, const double* fscale, void* fout) {
   using C = cplx_t<S>;
   const int nb = stencil_blocks(g);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   kprof_begin(KP_STENCIL, st);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_jacobi2z<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
-                       omega);
+                       omega, fscale, (C*)fout);
   else
     hipLaunchKernelGGL((k_jacobi2z<S, 2>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)f, (C*)z,
-                       omega);
-  kprof_end(KP_STENCIL, n * (3 * esz + 1), st);
+                       omega, fscale, (C*)fout);
+  kprof_end(KP_STENCIL, n * ((fout ? 4 : 3) * esz + 1), st);
 }
 
 // z = omega D^{-1} f: a Jacobi sweep started from z = 0 (no stencil needed).
@@ -365,7 +366,7 @@ void build_s(size_t n, const double* ksq, const double* alpha, void* sc, hipStre
   template void jacobi_from_zero<S>(size_t, double, const void*, const uint8_t*, const void*, void*, double,  \
                                     hipStream_t);                                                           \
   template void jacobi2_from_zero<S>(const StencilGeom&, const void*, const uint8_t*, const void*, void*,     \
-                                     double, hipStream_t);                                                  \
+                                     double, hipStream_t, const double*, void*);                            \
   template void build_s<S>(size_t, const double*, const double*, void*, hipStream_t);
 HELM_INST(double)
 HELM_INST(float)

@@ -131,10 +131,30 @@ __device__ __forceinline__ double2 jac0(double2 f, double2 s, double dsum, bool 
   return make_double2(omega * q.x, omega * q.y);
 }
 
+// Right-hand side value at node q, optionally scaled on load by fs (the
+// scaled value rounded to the storage precision, exactly what a separate
+// scaling pass would have stored).
+template <typename S>
+__device__ __forceinline__ double2 ldf(const cplx_t<S>* __restrict__ f, size_t q, double fs, bool scaled) {
+  double2 v = ldc(f, q);
+  if (scaled) {
+    v = make_double2(v.x * fs, v.y * fs);
+    if (sizeof(S) == sizeof(float)) v = make_double2((double)(float)v.x, (double)(float)v.y);
+  }
+  return v;
+}
+
+// fscale (optional): the right-hand side is fscale[0] * f; fout (optional,
+// requires fscale) receives that scaled right-hand side, each node written once
+// by the thread that owns it.
 template <typename S, int DIM>
 __device__ __forceinline__ void jacobi2z_tile(const StencilGeom& g, unsigned lb, const cplx_t<S>* __restrict__ sc,
                                               const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ f,
-                                              cplx_t<S>* __restrict__ y, double omega) {
+                                              cplx_t<S>* __restrict__ y, double omega,
+                                              const double* __restrict__ fscale = nullptr,
+                                              cplx_t<S>* __restrict__ fout = nullptr) {
+  const bool scaled = fscale != nullptr;
+  const double fs = scaled ? fscale[0] : 1.0;
   const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
   const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
   const int i = bx * 64 + threadIdx.x;
@@ -147,22 +167,23 @@ __device__ __forceinline__ void jacobi2z_tile(const StencilGeom& g, unsigned lb,
   const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
   size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
   // z1 of the column at z-1, z (the z-1 value only matters when present)
-  double2 zc = jac0(ldc(f, p), ldc(sc, p), g.dsum, code[p] & NB_SELF, omega);
+  double2 zc = jac0(ldf<S>(f, p, fs, scaled), ldc(sc, p), g.dsum, code[p] & NB_SELF, omega);
   double2 zmv = czero();
-  if (DIM == 3 && z0 > 0) zmv = jac0(ldc(f, p - plane), ldc(sc, p - plane), g.dsum, false, omega);
+  if (DIM == 3 && z0 > 0) zmv = jac0(ldf<S>(f, p - plane, fs, scaled), ldc(sc, p - plane), g.dsum, false, omega);
   for (int z = z0; z < z1e; ++z, p += plane) {
     double2 znv = czero();
-    if (DIM == 3 && z + 1 < g.nz) znv = jac0(ldc(f, p + plane), ldc(sc, p + plane), g.dsum, false, omega);
+    if (DIM == 3 && z + 1 < g.nz) znv = jac0(ldf<S>(f, p + plane, fs, scaled), ldc(sc, p + plane), g.dsum, false, omega);
     const unsigned cd = code[p];
-    const double2 fp = ldc(f, p), sp = ldc(sc, p);
+    const double2 fp = ldf<S>(f, p, fs, scaled), sp = ldc(sc, p);
+    if (fout) stc(fout, p, fp);
     double2 ax;
     if (cd & NB_SELF) {
       ax = zc;
     } else {
-      const double2 a = (cd & NB_XM) ? czero() : jac0(ldc(f, p + oxm), ldc(sc, p + oxm), g.dsum, false, omega);
-      const double2 b = (cd & NB_XP) ? czero() : jac0(ldc(f, p + oxp), ldc(sc, p + oxp), g.dsum, false, omega);
-      const double2 e = (cd & NB_YM) ? czero() : jac0(ldc(f, p + oym), ldc(sc, p + oym), g.dsum, false, omega);
-      const double2 h = (cd & NB_YP) ? czero() : jac0(ldc(f, p + oyp), ldc(sc, p + oyp), g.dsum, false, omega);
+      const double2 a = (cd & NB_XM) ? czero() : jac0(ldf<S>(f, p + oxm, fs, scaled), ldc(sc, p + oxm), g.dsum, false, omega);
+      const double2 b = (cd & NB_XP) ? czero() : jac0(ldf<S>(f, p + oxp, fs, scaled), ldc(sc, p + oxp), g.dsum, false, omega);
+      const double2 e = (cd & NB_YM) ? czero() : jac0(ldf<S>(f, p + oym, fs, scaled), ldc(sc, p + oym), g.dsum, false, omega);
+      const double2 h = (cd & NB_YP) ? czero() : jac0(ldf<S>(f, p + oyp, fs, scaled), ldc(sc, p + oyp), g.dsum, false, omega);
       double2 acc;
       acc.x = ((zc.x - a.x) + (zc.x - b.x)) * g.ih2[0];
       acc.y = ((zc.y - a.y) + (zc.y - b.y)) * g.ih2[0];
@@ -184,7 +205,7 @@ __device__ __forceinline__ void jacobi2z_tile(const StencilGeom& g, unsigned lb,
       zc = znv;
       // the next node's own z1 needs its own mask bit; recompute if it is masked
       if (z + 1 < z1e && (code[p + plane] & NB_SELF))
-        zc = jac0(ldc(f, p + plane), ldc(sc, p + plane), g.dsum, true, omega);
+        zc = jac0(ldf<S>(f, p + plane, fs, scaled), ldc(sc, p + plane), g.dsum, true, omega);
     }
   }
 }
