@@ -262,7 +262,16 @@ __global__ __launch_bounds__(256) void kb_update(const BProb* __restrict__ P, co
 // in a fixed order (thread t takes blocks t, t + 256, ..., then a fixed tree).
 __device__ double seg_sum(const double* part, int width, int k, int b0, int nb, double* sh) {
   double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) a += part[(size_t)(b0 + b) * width + k];
+  for (int bb = 0; bb < nb; bb += 4 * 256) {  // four loads in flight, added in index order
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = bb + threadIdx.x + 256 * q;
+      v[q] = b < nb ? part[(size_t)(b0 + b) * width + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a += v[q];
+  }
   return block_sum(a, sh);
 }
 
@@ -384,7 +393,13 @@ __global__ __launch_bounds__(256) void kb_qreduce(const BProb* __restrict__ P, c
   const int e = threadIdx.x;
   if (e >= 2 * q.rank) return;
   double a = 0.0;
-  for (int b = 0; b < q.qbn; ++b) a += part[(size_t)(q.qb0 + b) * 256 + e];
+  for (int bb = 0; bb < q.qbn; bb += 8) {  // eight loads in flight, added in index order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = bb + u < q.qbn ? part[(size_t)(q.qb0 + bb + u) * 256 + e] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += v[u];
+  }
   y[(size_t)p * 256 + e] = a;
 }
 

@@ -26,6 +26,7 @@
 #include "lib.h"
 #include "prof.h"
 #include "coarse_dev.h"
+#include "stencil_dev.h"
 
 namespace helm {
 
@@ -231,34 +232,39 @@ __global__ __launch_bounds__(256) void k_skinny32(size_t n, int r, const float* 
 }
 
 // B = (L - diag(Re s)) Q on real columns (n x r, row-major); masked rows -> 0.
+// A row of 4 nodes per workgroup step (threadIdx.y), the 64 lanes across the
+// node's columns; absent neighbours (ghost or masked) come from the node's
+// neighbour code, so no coordinates are formed.
 template <typename S>
 __global__ __launch_bounds__(256) void k_batched_lap(StencilGeom g, int r, const double* __restrict__ Q,
-                                                     const cplx_t<S>* __restrict__ sc, const uint8_t* __restrict__ mask,
+                                                     const cplx_t<S>* __restrict__ sc, const uint8_t* __restrict__ code,
                                                      double* __restrict__ B) {
   const size_t n = (size_t)g.nx * g.ny * g.nz;
-  const size_t total = n * r;
-  const size_t plane = (size_t)g.nx * g.ny;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t p = e / r;
-    const int j = (int)(e % r);
-    if (mask[p]) {
-      B[e] = 0.0;
-      continue;
+  const size_t ry = (size_t)g.nx * r, rz = (size_t)g.nx * g.ny * r;
+  for (size_t p = blockIdx.x * (size_t)blockDim.y + threadIdx.y; p < n; p += (size_t)gridDim.x * blockDim.y) {
+    const unsigned cd = code[p];
+    const size_t row = p * r;
+    const double sre = ldc(sc, p).x;
+    for (int j = threadIdx.x; j < r; j += 64) {
+      const size_t e = row + j;
+      if (cd & NB_SELF) {
+        B[e] = 0.0;
+        continue;
+      }
+      const double c = Q[e];
+      const double xm = (cd & NB_XM) ? 0.0 : Q[e - r];
+      const double xp = (cd & NB_XP) ? 0.0 : Q[e + r];
+      const double ym = (cd & NB_YM) ? 0.0 : Q[e - ry];
+      const double yp = (cd & NB_YP) ? 0.0 : Q[e + ry];
+      double acc = ((c - xm) + (c - xp)) * g.ih2[0];
+      acc = acc + ((c - ym) + (c - yp)) * g.ih2[1];
+      if (g.dim == 3) {
+        const double zm = (cd & NB_ZM) ? 0.0 : Q[e - rz];
+        const double zp = (cd & NB_ZP) ? 0.0 : Q[e + rz];
+        acc = acc + ((c - zm) + (c - zp)) * g.ih2[2];
+      }
+      B[e] = acc - sre * c;
     }
-    const int i = (int)(p % g.nx), jj = (int)((p / g.nx) % g.ny), l = (int)(p / plane);
-    const double c = Q[e];
-    const double xm = (i > 0 && !mask[p - 1]) ? Q[e - r] : 0.0;
-    const double xp = (i + 1 < g.nx && !mask[p + 1]) ? Q[e + r] : 0.0;
-    const double ym = (jj > 0 && !mask[p - g.nx]) ? Q[e - (size_t)g.nx * r] : 0.0;
-    const double yp = (jj + 1 < g.ny && !mask[p + g.nx]) ? Q[e + (size_t)g.nx * r] : 0.0;
-    double acc = ((c - xm) + (c - xp)) * g.ih2[0];
-    acc = acc + ((c - ym) + (c - yp)) * g.ih2[1];
-    if (g.dim == 3) {
-      const double zm = (l > 0 && !mask[p - plane]) ? Q[e - plane * r] : 0.0;
-      const double zp = (l + 1 < g.nz && !mask[p + plane]) ? Q[e + plane * r] : 0.0;
-      acc = acc + ((c - zm) + (c - zp)) * g.ih2[2];
-    }
-    B[e] = acc - ldc(sc, p).x * c;
   }
 }
 
@@ -454,8 +460,12 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
                        (double*)c.Q.ptr);
   // B = (L - diag(Re s)) Q into W2; A_c = Q^T B - i Q^T diag(Im s) Q
   double* Bm = Q1;
-  hipLaunchKernelGGL((k_batched_lap<S>), dim3(ew_grid(n * r)), dim3(256), 0, st, op->geom, r, Q,
-                     (const cplx_t<S>*)op->sc, op->mask, Bm);
+  {
+    size_t nbl = (n + 3) / 4;
+    if (nbl > 16384) nbl = 16384;
+    hipLaunchKernelGGL((k_batched_lap<S>), dim3((unsigned)nbl), dim3(64, 4), 0, st, op->geom, r, Q,
+                       (const cplx_t<S>*)op->sc, op->code, Bm);
+  }
   gram(n, r, Q, r, Bm, r, nullptr, part, are, st);
   double* wim = Bm;  // B no longer needed: reuse for Im s
   hipLaunchKernelGGL((k_im_s<S>), dim3(ew_grid(n)), dim3(256), 0, st, n, (const cplx_t<S>*)op->sc, wim);

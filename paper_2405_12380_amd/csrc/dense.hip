@@ -32,9 +32,18 @@ template <typename T> __device__ __forceinline__ int acc_row(int lane, int i);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int i) { return (lane >> 4) + 4 * i; }
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int i) { return 4 * (lane >> 4) + i; }
 
+// tanh for the fp64 layers from expm1: t = e^{2|x|} - 1, tanh|x| = t / (t + 2),
+// sign restored (no cancellation near 0; within 5e-16 of the library tanh and
+// about 3x cheaper per element, which matters in the trunk GEMM epilogue)
+__device__ __forceinline__ double tanh_fast(double x) {
+  const double t = expm1(2.0 * fabs(x));
+  return copysign(t / (t + 2.0), x);
+}
+__device__ __forceinline__ float tanh_fast(float x) { return tanhf(x); }
+
 template <typename T>
 __device__ __forceinline__ T activate(T x, int act) {
-  if (act == ACT_TANH) return tanh(x);
+  if (act == ACT_TANH) return tanh_fast(x);
   if (act == ACT_RELU) return x > T(0) ? x : T(0);
   if (act == ACT_LEAKY) return x > T(0) ? x : T(0.01) * x;
   return x;
@@ -63,9 +72,9 @@ __global__ __launch_bounds__(256) void k_coord_layer(int dim, int nx, int ny, in
 // ---- MFMA GEMM: C = act(A W + b) ---------------------------------------------
 // A: M x K (lda), W: K x N (ldw), C: M x N (ldc), all row-major.  64x64 tile
 // per workgroup of four wavefronts (32x32 each, 2x2 MFMA tiles), K staged in
-// chunks of 16 through LDS (A stored k-major so MFMA operand reads are
+// chunks of 32 through LDS (A stored k-major so MFMA operand reads are
 // conflict-free).
-constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T* __restrict__ A, size_t lda,
@@ -83,22 +92,36 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T* __re
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
   for (int k0 = 0; k0 < K; k0 += GB_K) {
-    // A tile: 64 rows x 16 k, 4 elements per thread
+    // A tile: 64 rows x 32 k (consecutive threads take consecutive k of a row,
+    // 128 contiguous bytes per 16 threads), 8 elements per thread; all loads
+    // of a thread are issued before the tile is stored
     {
-      const int r = t >> 2, kq = (t & 3) * 4;
-      const int gr = bm + r;
-      for (int q = 0; q < 4; ++q) {
-        const int gk = k0 + kq + q;
-        As[kq + q][r] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : T(0);
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = t + 256 * q, r = e >> 5, kk = e & 31;
+        const int gr = bm + r, gk = k0 + kk;
+        v[q] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = t + 256 * q;
+        As[e & 31][e >> 5] = v[q];
       }
     }
-    // W tile: 16 k x 64 n
+    // W tile: 32 k x 64 n
     {
-      const int kk = t >> 4, nq = (t & 15) * 4;
-      const int gk = k0 + kk;
-      for (int q = 0; q < 4; ++q) {
-        const int gn = bn + nq + q;
-        Ws[kk][nq + q] = (gk < K && gn < N) ? W[(size_t)gk * ldw + gn] : T(0);
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = t + 256 * q, kk = e >> 6, c = e & 63;
+        const int gk = k0 + kk, gn = bn + c;
+        v[q] = (gk < K && gn < N) ? W[(size_t)gk * ldw + gn] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = t + 256 * q;
+        Ws[e >> 6][e & 63] = v[q];
       }
     }
     __syncthreads();
@@ -184,17 +207,23 @@ __global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __r
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
   for (size_t ib = i0; ib < i1; ib += GR_ROWS) {
-    for (int e = t; e < GR_ROWS * 128; e += 256) {
-      const int rr = e >> 7, cc = e & 127;
+    // 16 rows x 128 columns of X and Y: every load of a thread in flight before
+    // the first store to LDS
+    double xv[GR_ROWS * 128 / 256], yv[GR_ROWS * 128 / 256];
+#pragma unroll
+    for (int q = 0; q < GR_ROWS * 128 / 256; ++q) {
+      const int e = t + 256 * q, rr = e >> 7, cc = e & 127;
       const size_t gi = ib + rr;
-      double xv = 0.0, yv = 0.0;
-      if (gi < i1 && cc < r) {
-        xv = X[gi * ldx + cc];
-        yv = Y[gi * ldy + cc];
-        if (w) yv *= w[gi];
-      }
-      Xs[rr][cc] = xv;
-      Ys[rr][cc] = yv;
+      const bool in = gi < i1 && cc < r;
+      xv[q] = in ? X[gi * ldx + cc] : 0.0;
+      yv[q] = in ? Y[gi * ldy + cc] : 0.0;
+      if (in && w) yv[q] *= w[gi];
+    }
+#pragma unroll
+    for (int q = 0; q < GR_ROWS * 128 / 256; ++q) {
+      const int e = t + 256 * q, rr = e >> 7, cc = e & 127;
+      Xs[rr][cc] = xv[q];
+      Ys[rr][cc] = yv[q];
     }
     __syncthreads();
 #pragma unroll
