@@ -104,7 +104,7 @@ __device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, 
 // B[l % 16][8 (l / 16) .. +7] (B stored n-major) and C[4 (l / 16) + i][l % 16].
 constexpr int CTW = TN + 8;  // LDS row stride of the staged output tile (bf16)
 
-__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_nt(GemmArgs g) {
   // operand tiles during the k loop; the output tile (then its transpose) afterwards
   __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSW];
   __bf16* As = smem;
@@ -171,11 +171,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
       }
     return;
   }
-  // bf16 results: epilogue math in registers, then the tile goes through LDS
-  // twice, row-major (C) and column-major (C^T; a lane's four rows of one column
-  // are 8 contiguous bytes there), each written out as 16-byte row chunks
+  // bf16 results: the epilogue math goes straight from the accumulators into a
+  // row-major LDS copy of the tile (the accumulators are read once, so they
+  // never need a second set of registers); C is written from it as 16-byte row
+  // chunks, and C^T from the same copy, each 16-byte column chunk gathered from
+  // eight LDS rows
   __bf16* Cs = smem;  // TM x CTW, reuses the operand tiles (the k loop ended with a barrier)
-  typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int col = n0 + wn * 64 + j * 16 + (l & 15);
@@ -192,17 +193,10 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
           const float h = bf2f(g.aux[(long)(row0 + q) * g.ldc + col]);
           v *= 1.0f - h * h;
         }
-        acc[i][j][q] = v;
+        Cs[(wm * 64 + i * 16 + 4 * (l >> 4) + q) * CTW + wn * 64 + j * 16 + (l & 15)] = (__bf16)v;
       }
     }
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        Cs[(wm * 64 + i * 16 + 4 * (l >> 4) + q) * CTW + wn * 64 + j * 16 + (l & 15)] = (__bf16)acc[i][j][q];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -212,20 +206,14 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
       *(bf8*)((__bf16*)g.C + (long)row * g.ldc + col) = *(const bf8*)(Cs + rl * CTW + cq);
   }
   if (!g.CT) return;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      bf4 r4 = {(__bf16)acc[i][j][0], (__bf16)acc[i][j][1], (__bf16)acc[i][j][2], (__bf16)acc[i][j][3]};
-      *(bf4*)(Cs + (wn * 64 + j * 16 + (l & 15)) * CTW + wm * 64 + i * 16 + 4 * (l >> 4)) = r4;
-    }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int c = t + 256 * k, cl = c >> 4, rq = (c & 15) * 8;
     const int col = n0 + cl, row = m0 + rq;
-    if (col < g.N && row + 8 <= g.M) *(bf8*)(g.CT + (long)col * g.ldct + row) = *(const bf8*)(Cs + cl * CTW + rq);
+    bf8 v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = Cs[(rq + u) * CTW + cl];
+    if (col < g.N && row + 8 <= g.M) *(bf8*)(g.CT + (long)col * g.ldct + row) = v;
   }
 }
 
@@ -234,7 +222,13 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g, const float* 
   const long MN = (long)g.M * g.N;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < MN; e += (long)gridDim.x * 256) {
     float v = 0.f;
-    for (int z = 0; z < splits; ++z) v += part[z * MN + e];
+    for (int z0 = 0; z0 < splits; z0 += 8) {  // eight slices' loads in flight, added in slice order
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = z0 + u < splits ? part[(z0 + u) * MN + e] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += x[u];
+    }
     const int row = (int)(e / g.N), col = (int)(e % g.N);
     const __bf16 r = ep_store(g, row, col, v);
     if (g.CT) g.CT[(long)col * g.ldct + row] = r;
@@ -246,10 +240,18 @@ __global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ D, lo
   __shared__ double sh[16];
   const __bf16* row = D + (long)blockIdx.x * M;
   double a = 0.0;
-  for (long c = threadIdx.x * 8L; c < M; c += 256 * 8L) {
-    const bf8 v = *(const bf8*)(row + c);
+  for (long c0 = threadIdx.x * 8L; c0 < M; c0 += 4 * 256 * 8L) {  // four 16-byte loads in flight, same order
+    bf8 v[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) a += (double)bf2f(v[j]);
+    for (int u = 0; u < 4; ++u) {
+      const long c = c0 + u * 256 * 8L;
+      if (c < M) v[u] = *(const bf8*)(row + c);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (c0 + u * 256 * 8L < M)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a += (double)bf2f(v[u][j]);
   }
   a = block_sum(a, sh);
   if (threadIdx.x == 0) out[blockIdx.x] = (float)a;
