@@ -252,7 +252,13 @@ __global__ void k_reduce_rows(const double* __restrict__ part, int nparts, size_
   const size_t w = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (w >= width) return;
   double acc = 0.0;
-  for (int b = 0; b < nparts; ++b) acc += part[(size_t)b * width + w];
+  for (int b0 = 0; b0 < nparts; b0 += 8) {  // eight partials' loads in flight, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = b0 + u < nparts ? part[(size_t)(b0 + u) * width + w] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
   out[w] = scale * acc;
 }
 
@@ -276,7 +282,14 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
   __shared__ int s_nk, s_fail;
   __shared__ double s_piv, s_thr2;
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < p * p; e += nt) G[e] = Gin[e];
+  for (int e0 = 0; e0 < p * p; e0 += 4 * nt) {  // four loads in flight per thread
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = e0 + t + u * nt < p * p ? Gin[e0 + t + u * nt] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + t + u * nt < p * p) G[e0 + t + u * nt] = v[u];
+  }
   __syncthreads();
   if (t == 0) {
     s_nk = 0;
@@ -367,12 +380,12 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
                                                      int* __restrict__ info, double* __restrict__ cond) {
   // prow holds the pivot row with one pad entry per 16 columns: the eight
   // column blocks a wavefront reads at once then fall in different LDS banks
-  __shared__ double2 pcol[128], prow[128 + 8], bufk[128], bufp[128];
-  __shared__ double pabs[128], csum[128];
+  __shared__ double2 pcol[2][128], prow[128 + 8], bufk[128], bufp[128];
+  __shared__ double pabs[2][128], csum[128];
   __shared__ double npart[8][128];
   __shared__ int perm[128], dest[128];
-  __shared__ int s_piv, s_bad;
-  const int t = threadIdx.x;
+  __shared__ int s_bad;
+  const int t = threadIdx.x, lane = t & 63;
   const int i = t >> 3, cb = t & 7, c0 = 16 * cb;
   const bool row_in = i < r;
   double2 a[16];
@@ -381,6 +394,18 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     const int c = c0 + q;
     a[q] = (row_in && c < r) ? make_double2(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]) : czero();
   }
+  // pivot column k (its entries and moduli, rows below k only) into buffer k & 1
+  auto publish = [&](int k) {
+    if (cb == (k >> 4) && row_in) {
+      double2 v = czero();
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q == (k & 15)) v = a[q];
+      pcol[k & 1][i] = v;
+      pabs[k & 1][i] = i >= k ? hypot(v.x, v.y) : -1.0;
+    }
+  };
+  publish(0);
   // ||A||_1: column sums, column t % 128 over rows t / 128 + 8 u (coalesced), the
   // eight partials added in order
   {
@@ -397,43 +422,33 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     for (int q = 0; q < 8; ++q) sm += npart[q][t];
     csum[t] = sm;
   }
-  __syncthreads();
+  // Per pivot: two barriers (four with a row interchange).  Every wavefront
+  // finds the pivot itself from the published moduli (same data, same order,
+  // same result), and the elimination of column k publishes column k + 1 into
+  // the other buffer.
   for (int k = 0; k < r; ++k) {
-    const int kb = k >> 4, kq = k & 15;
-    if (cb == kb && row_in) {
-      double2 v = czero();
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q == kq) v = a[q];
-      pcol[i] = v;
-      pabs[i] = i >= k ? hypot(v.x, v.y) : -1.0;
-    }
-    __syncthreads();
-    if (t < 64) {
-      double best = -2.0;
-      int bi = 0;
-      for (int ii = t; ii < r; ii += 64)
-        if (pabs[ii] > best) {
-          best = pabs[ii];
-          bi = ii;
-        }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
+    const int buf = k & 1;
+    double best = -2.0;
+    int bi = 0;
+    for (int ii = lane; ii < r; ii += 64)
+      if (pabs[buf][ii] > best) {
+        best = pabs[buf][ii];
+        bi = ii;
       }
-      if (t == 0) {
-        s_piv = bi;
-        perm[k] = bi;
-        if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
       }
     }
-    __syncthreads();
-    const int p = s_piv;
+    const int p = bi;
+    if (t == 0) {
+      perm[k] = p;
+      if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
+    }
     if (p != k) {
       if (i == k)
 #pragma unroll
@@ -449,15 +464,15 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
 #pragma unroll
         for (int q = 0; q < 16; ++q) a[q] = bufk[c0 + q];
       if (t == 0) {
-        const double2 tmp = pcol[k];
-        pcol[k] = pcol[p];
-        pcol[p] = tmp;
+        const double2 tmp = pcol[buf][k];
+        pcol[buf][k] = pcol[buf][p];
+        pcol[buf][p] = tmp;
       }
       __syncthreads();
     }
     // scale the pivot row: A[k][k] <- 1, row *= 1 / pivot; publish it
     if (i == k) {
-      const double2 ipiv = cdiv(make_double2(1.0, 0.0), pcol[k]);
+      const double2 ipiv = cdiv(make_double2(1.0, 0.0), pcol[buf][k]);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const double2 v = (c0 + q == k) ? make_double2(1.0, 0.0) : a[q];
@@ -468,13 +483,14 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     __syncthreads();
     // eliminate column k from every other row: A[i][:] <- (A[i][:] with A[i][k] = 0) - f A[k][:]
     if (i != k && row_in) {
-      const double2 f = pcol[i];
+      const double2 f = pcol[buf][i];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const double2 v = (c0 + q == k) ? czero() : a[q];
         a[q] = csub(v, cmul(f, prow[c0 + q + cb]));
       }
     }
+    if (k + 1 < r) publish(k + 1);
     __syncthreads();
   }
   // The row interchanges are undone as column interchanges in reverse order:
@@ -490,14 +506,14 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     }
   }
   __syncthreads();
-  if (t < r) pcol[dest[t]].x = (double)t;  // inverse map: column idx[c] goes to c
+  if (t < r) pcol[0][dest[t]].x = (double)t;  // inverse map: column idx[c] goes to c
   __syncthreads();
   if (row_in)
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int c = c0 + q;
       if (c < r) {
-        const int to = (int)pcol[c].x;
+        const int to = (int)pcol[0][c].x;
         Ainv[2 * ((size_t)i * r + to)] = a[q].x;
         Ainv[2 * ((size_t)i * r + to) + 1] = a[q].y;
       }
@@ -515,14 +531,14 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
   if (t < 128) {
     double sm = 0.0;
     for (int q = 0; q < 8; ++q) sm += npart[q][t];
-    pabs[t] = sm;
+    pabs[0][t] = sm;
   }
   __syncthreads();
   if (t == 0) {
     double na = 0.0, ni = 0.0;
     for (int c = 0; c < r; ++c) {
       na = fmax(na, csum[c]);
-      ni = fmax(ni, pabs[c]);
+      ni = fmax(ni, pabs[0][c]);
     }
     cond[0] = na * ni;
     info[0] = s_bad;

@@ -61,14 +61,26 @@ def test_precond_parity(smoother, n_r):
 @pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
 @pytest.mark.parametrize("kind,iters", [("gmres", 12), ("bicgstab", 8)])
 def test_meta_krylov_forced_count(kind, iters, dtype):
+    _forced_count(kind, iters, dtype, 50)
+
+
+@pytest.mark.parametrize("restart,iters", [(60, 54), (4, 11)])
+def test_meta_gmres_forced_count_restarts(restart, iters):
+    """Restart lengths beyond the fused CGS pass (the two-pass path for
+    j + 1 > 52) and short cycles (each cycle's first vector is normalized on
+    the host, the others inside the next step's first kernel)."""
+    _forced_count("gmres", iters, helm.C128, restart)
+
+
+def _forced_count(kind, iters, dtype, restart):
     C, s, op, net, cs = _setup(16, 64, dtype)
     f = C["f"]
     if dtype == helm.C64:
         f = f.astype(np.complex64).astype(np.complex128)
     M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
-    u_or, info = meta_or.krylov_meta(kind, f, np.zeros_like(f), s, C["mask"], 50, 0.0, iters, precond=M)
+    u_or, info = meta_or.krylov_meta(kind, f, np.zeros_like(f), s, C["mask"], restart, 0.0, iters, precond=M)
     u = op.field()
-    st, stats = helm.meta_solve(op, net, op.field(f), u, kind=kind, restart=50, tol=0.0, max_iters=iters, n_r=3,
+    st, stats = helm.meta_solve(op, net, op.field(f), u, kind=kind, restart=restart, tol=0.0, max_iters=iters, n_r=3,
                                 omega=0.5, p_used=64)
     assert stats["iters"] == iters
     assert stats["rank_used"] == cs.rank
