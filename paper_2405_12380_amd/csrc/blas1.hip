@@ -8,6 +8,7 @@
 #include "common.h"
 #include "internal.h"
 #include "prof.h"
+#include "stencil_dev.h"
 
 namespace helm {
 
@@ -136,6 +137,93 @@ void multidot_part(size_t n, const void* V, size_t ldv, int nv, const void* w, d
   else
     hipLaunchKernelGGL((k_multidot<S, 2048>), dim3(nb), dim3(256), 0, st, n, (const C*)V, ldv, nv, (const C*)w, part);
   kprof_end(KP_MULTIDOT, (double)n * 2 * sizeof(S) * (nv + 1), st);
+}
+
+// ---- matvec fused with the multi-dot -----------------------------------------
+// w = A z for the workgroup's chunk (the per-node arithmetic of the apply
+// stencil, neighbours through the node's code byte), stored and staged in LDS,
+// then the same partials of V^H w as k_multidot: one launch and one pass over
+// w fewer per Arnoldi step.
+template <typename S, int CH>
+__global__ __launch_bounds__(256) void k_multidot_apply(StencilGeom g, const cplx_t<S>* __restrict__ sc,
+                                                        const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ z,
+                                                        const cplx_t<S>* __restrict__ V, size_t ldv, int nv,
+                                                        cplx_t<S>* __restrict__ w, double* __restrict__ part) {
+  __shared__ double2 ws[CH];
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const ptrdiff_t sy = g.nx, sz = (ptrdiff_t)g.nx * g.ny;
+  const size_t c0 = (size_t)blockIdx.x * CH;
+  for (int t = threadIdx.x; t < CH; t += 256) {
+    const size_t e = c0 + t;
+    double2 ax = czero();
+    if (e < n) {
+      const unsigned cd = code[e];
+      const double2 c = ldc(z, e);
+      if (cd & NB_SELF) {
+        ax = c;
+      } else {
+        const double2 a = sel0(cd & NB_XM, ldc(z, e - ((cd & NB_XM) ? 0 : 1)));
+        const double2 b = sel0(cd & NB_XP, ldc(z, e + ((cd & NB_XP) ? 0 : 1)));
+        const double2 ee = sel0(cd & NB_YM, ldc(z, e - ((cd & NB_YM) ? 0 : sy)));
+        const double2 h = sel0(cd & NB_YP, ldc(z, e + ((cd & NB_YP) ? 0 : sy)));
+        const double2 sp = ldc(sc, e);
+        double2 acc;
+        acc.x = ((c.x - a.x) + (c.x - b.x)) * g.ih2[0];
+        acc.y = ((c.y - a.y) + (c.y - b.y)) * g.ih2[0];
+        acc.x = acc.x + ((c.x - ee.x) + (c.x - h.x)) * g.ih2[1];
+        acc.y = acc.y + ((c.y - ee.y) + (c.y - h.y)) * g.ih2[1];
+        if (g.dim == 3) {
+          const double2 q = sel0(cd & NB_ZM, ldc(z, e - ((cd & NB_ZM) ? 0 : sz)));
+          const double2 u = sel0(cd & NB_ZP, ldc(z, e + ((cd & NB_ZP) ? 0 : sz)));
+          acc.x = acc.x + ((c.x - q.x) + (c.x - u.x)) * g.ih2[2];
+          acc.y = acc.y + ((c.y - q.y) + (c.y - u.y)) * g.ih2[2];
+        }
+        ax = csub(acc, cmul(sp, c));
+      }
+      stc(w, e, ax);
+      if (sizeof(S) == sizeof(float)) ax = make_double2((double)(float)ax.x, (double)(float)ax.y);
+    }
+    ws[t] = ax;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool full = c0 + CH <= n;
+  for (int i = wave; i < nv; i += 4) {
+    const cplx_t<S>* Vi = V + (size_t)i * ldv + c0;
+    double2 acc = czero();
+    if (full) {
+#pragma unroll
+      for (int t = 0; t < CH / 64; ++t) acc = cadd(acc, cconjmul(ldc(Vi, lane + 64 * t), ws[lane + 64 * t]));
+    } else {
+      for (int t = 0; t < CH / 64; ++t) {
+        const int el = lane + 64 * t;
+        if (c0 + el < n) acc = cadd(acc, cconjmul(ldc(Vi, el), ws[el]));
+      }
+    }
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (lane == 0) {
+      part[(size_t)blockIdx.x * 2 * nv + 2 * i] = acc.x;
+      part[(size_t)blockIdx.x * 2 * nv + 2 * i + 1] = acc.y;
+    }
+  }
+}
+
+template <typename S>
+void multidot_apply(const StencilGeom& g, const void* sc, const uint8_t* code, const void* z, const void* V,
+                    size_t ldv, int nv, void* w, double* part, hipStream_t st) {
+  using C = cplx_t<S>;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  const int nb = multidot_nblocks(n);
+  kprof_begin(KP_MULTIDOT, st);
+  if (md_chunk(n) == 512)
+    hipLaunchKernelGGL((k_multidot_apply<S, 512>), dim3(nb), dim3(256), 0, st, g, (const C*)sc, code, (const C*)z,
+                       (const C*)V, ldv, nv, (C*)w, part);
+  else
+    hipLaunchKernelGGL((k_multidot_apply<S, 2048>), dim3(nb), dim3(256), 0, st, g, (const C*)sc, code, (const C*)z,
+                       (const C*)V, ldv, nv, (C*)w, part);
+  // V once; z, s and the code byte once (z's neighbours from cache); w written
+  kprof_end(KP_MULTIDOT, (double)n * (2 * sizeof(S) * (nv + 3) + 1), st);
 }
 
 // ---- multi-axpy -------------------------------------------------------------
@@ -622,6 +710,8 @@ void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st) {
   template void multi_axpy<S>(size_t, const void*, size_t, int, const double*, double, const void*, void*,     \
                               double*, hipStream_t);                                                           \
   template int cgs_fused<S>(size_t, const void*, size_t, int, const double*, void*, double*, hipStream_t);     \
+  template void multidot_apply<S>(const StencilGeom&, const void*, const uint8_t*, const void*, const void*,   \
+                                  size_t, int, void*, double*, hipStream_t);                                   \
   template void scale_dev<S>(size_t, const void*, const double*, void*, hipStream_t);                          \
   template void scale_host<S>(size_t, const void*, double, void*, hipStream_t);                                \
   template void add_inplace<S>(size_t, const void*, void*, hipStream_t);                                       \

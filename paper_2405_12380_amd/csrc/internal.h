@@ -61,6 +61,10 @@ void nrm2_part(size_t n, const void* x, double* part, hipStream_t st);  // 1 per
 int multidot_nblocks(size_t n);
 template <typename S>
 void multidot_part(size_t n, const void* V, size_t ldv, int nv, const void* w, double* part, hipStream_t st);
+// w = A z (the apply stencil) and the multidot_part partials of V^H w in one launch
+template <typename S>
+void multidot_apply(const StencilGeom& g, const void* sc, const uint8_t* code, const void* z, const void* V,
+                    size_t ldv, int nv, void* w, double* part, hipStream_t st);
 // out = base + sgn * sum_i V_i coef_i   (coef: nv complex doubles on device; base may be NULL)
 // if part != NULL, per-block partials of ||out||^2 are written (red_nblocks(n) of them)
 template <typename S>

@@ -209,8 +209,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
         scale_dev<S>(n, W, vsc, Vj(j), st);
       }
       void* w = W;
-      stencil_apply<S>(op->geom, op->sc, op->code, zj, w, st);
-      multidot_part<S>(n, V, ldv, j + 1, w, part, st);
+      multidot_apply<S>(op->geom, op->sc, op->code, zj, V, ldv, j + 1, w, part, st);  // w = A z_j and V^H w
       reduce_cols(part, mdb, 2 * (j + 1), h1, st);
       if (j + 1 <= cgs_fused_max_nv()) {
         // first projection and second inner products in one pass over V
