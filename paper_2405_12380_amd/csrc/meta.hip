@@ -298,6 +298,8 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
   BiState* bs = (BiState*)cv.take(sizeof(BiState));
   double* red = (double*)cv.take(64 * sizeof(double));
   const int rdb = red_nblocks(n), stb = stencil_nblocks(op->geom);
+  EventPair ev;
+  if (!ev.ok()) return fail(HELM_E_HIP, "bicgstab: event creation failed");
   double* part;
   if ((s = op_part(op, (size_t)(3 * rdb > stb ? 3 * rdb : stb), &part))) return s;
   if (!c.use_M) {
@@ -326,26 +328,45 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
     // rho for the first iteration of this sweep
     dot_part<S>(n, rh, r, part, st);
     reduce_cols(part, rdb, 2, red + 8, st);
-    bool first = true, stopped = false;
-    while (count < o->max_iters) {
+    // One iteration = half 1 (rho, p, M p, v = A M p, alpha, s, ||s||) and
+    // half 2 (M s, t = A M s, omega, the updates of u and r, ||r||).  Each half
+    // ends by copying the state record to pinned memory behind an event.  Half 1
+    // of the next iteration is queued before the host looks at ||r||: if ||r||
+    // ends the sweep, that half is discarded (it writes only p, v, s, their
+    // preconditioned copies and the scalar record, which a new sweep resets).
+    BiState* hS = (BiState*)(op->host + 256);
+    BiState* hR = (BiState*)(op->host + 320);
+    auto half1 = [&](bool first_) -> helm_status {
       bicg_scalar(BI_RHO, bs, red + 8, st);
-      bicg_p<S>(n, r, v, p, bs, first ? 1 : 0, st);
-      first = false;
+      bicg_p<S>(n, r, v, p, bs, first_ ? 1 : 0, st);
       if (c.use_M) {
-        if ((s = precond_apply<S>(op, c, p, ph, st))) return s;
-        papps++;
+        helm_status e2 = precond_apply<S>(op, c, p, ph, st);
+        if (e2) return e2;
       }
       stencil_apply<S>(op->geom, op->sc, op->code, ph, v, st);
-      matvecs++;
       dot_part<S>(n, rh, v, part, st);
       reduce_cols(part, rdb, 2, red, st);
       bicg_scalar(BI_ALPHA, bs, red, st);
       bicg_s<S>(n, r, v, sv, bs, part, st);
       reduce_cols(part, rdb, 1, red + 2, st);
       bicg_scalar(BI_SS, bs, red + 2, st);
+      hipError_t e1 = hipMemcpyAsync(hS, bs, sizeof(BiState), hipMemcpyDeviceToHost, st);
+      if (e1 == hipSuccess) e1 = hipEventRecord(ev[0], st);
+      return e1 == hipSuccess ? launch_check("bicgstab: half 1") : hip_fail(e1, "bicgstab: half 1 record");
+    };
+    bool stopped = false, pending = false;
+    if (count < o->max_iters) {
+      if ((s = half1(true))) return s;
+      pending = true;
+    }
+    while (pending) {
+      pending = false;
+      hipError_t e1 = hipEventSynchronize(ev[0]);
+      if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: s");
+      BiState hb = *hS;
+      matvecs++;
+      if (c.use_M) papps++;
       count++;
-      if ((s = read_host(op, bs, sizeof(BiState), st, "bicgstab: s"))) return s;
-      BiState hb = *(const BiState*)op->host;
       if (hb.flag) {
         status = hb.flag == -4 ? HELM_E_BREAKDOWN : HELM_E_NONFINITE;
         stopped = true;
@@ -373,8 +394,16 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       bicg_update<S>(n, ph, sh, sv, t, rh, u, r, bs, part, st);
       reduce_cols(part, rdb, 3, red + 8 - 1, st);  // red[7] = ||r||^2, red[8..9] = r_hat^H r (next rho)
       bicg_scalar(BI_RR, bs, red + 7, st);
-      if ((s = read_host(op, bs, sizeof(BiState), st, "bicgstab: r"))) return s;
-      hb = *(const BiState*)op->host;
+      e1 = hipMemcpyAsync(hR, bs, sizeof(BiState), hipMemcpyDeviceToHost, st);
+      if (e1 == hipSuccess) e1 = hipEventRecord(ev[1], st);
+      if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: half 2 record");
+      if (count < o->max_iters) {  // look ahead: the next half 1
+        if ((s = half1(false))) return s;
+        pending = true;
+      }
+      e1 = hipEventSynchronize(ev[1]);
+      if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: r");
+      hb = *hR;
       if (hb.flag) {
         status = hb.flag == -4 ? HELM_E_BREAKDOWN : HELM_E_NONFINITE;
         stopped = true;
