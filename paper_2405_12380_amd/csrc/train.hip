@@ -60,8 +60,12 @@ struct GemmArgs {
 
 __device__ __forceinline__ float bf2f(__bf16 v) { return (float)v; }
 
-// tanh x = 1 - 2 / (1 + e^{2x}) with the hardware exponential (saturates to +-1)
-__device__ __forceinline__ float fast_tanh(float x) { return 1.0f - __fdividef(2.0f, 1.0f + __expf(2.0f * x)); }
+// tanh x = 1 - 2 / (1 + e^{2x}) with the hardware exponential and reciprocal
+// (each within an ulp or so of fp32, far below the bf16 rounding that follows;
+// saturates to +-1: e^{2x} = inf gives 1, e^{2x} = 0 gives -1)
+__device__ __forceinline__ float fast_tanh(float x) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
+}
 
 // Epilogue of one value of C(row, col); returns the stored bf16 value for the transposed copy.
 __device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, float v) {
@@ -177,6 +181,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   // chunks, and C^T from the same copy, each 16-byte column chunk gathered from
   // eight LDS rows
   __bf16* Cs = smem;  // TM x CTW, reuses the operand tiles (the k loop ended with a barrier)
+  if (g.ep == EP_DTANH_BF16) {
+    // the activation tile h goes into Cs first, read with 16-byte row loads all
+    // in flight at once; each value of C then reads its h from LDS and
+    // overwrites it (every position belongs to one thread, so no barrier
+    // separates the read from the write)
+    bf8 hv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = t + 256 * k, rl = c >> 4, cq = (c & 15) * 8;
+      const int row = m0 + rl, col = n0 + cq;
+      hv[k] = (row < g.M && col + 8 <= g.N) ? *(const bf8*)(g.aux + (long)row * g.ldc + col) : zero;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int c = t + 256 * k, rl = c >> 4, cq = (c & 15) * 8;
+      *(bf8*)(Cs + rl * CTW + cq) = hv[k];
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int col = n0 + wn * 64 + j * 16 + (l & 15);
@@ -184,16 +207,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float bias = (cin && (g.ep == EP_BIAS_BF16 || g.ep == EP_BIAS_TANH_BF16)) ? g.bias[col] : 0.0f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row0 = m0 + wm * 64 + i * 16 + 4 * (l >> 4);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         float v = acc[i][j][q] + bias;
+        __bf16* cp = Cs + (wm * 64 + i * 16 + 4 * (l >> 4) + q) * CTW + wn * 64 + j * 16 + (l & 15);
         if (g.ep == EP_BIAS_TANH_BF16) v = fast_tanh(v);
-        else if (g.ep == EP_DTANH_BF16 && cin && row0 + q < g.M) {
-          const float h = bf2f(g.aux[(long)(row0 + q) * g.ldc + col]);
+        else if (g.ep == EP_DTANH_BF16) {
+          const float h = bf2f(*cp);  // zero outside the M x N result, which is never stored
           v *= 1.0f - h * h;
         }
-        Cs[(wm * 64 + i * 16 + 4 * (l >> 4) + q) * CTW + wn * 64 + j * 16 + (l & 15)] = (__bf16)v;
+        *cp = (__bf16)v;
       }
     }
   }
