@@ -505,13 +505,20 @@ struct don_trainer_s {
   int ndata = 0;
   size_t part_floats = 0;
   hipStream_t st = nullptr;
+  // the branch MLP runs on st2, beside the trunk on st (forked and joined by events)
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  Buffer bpart;  // split-k partials of the branch products (the trunk's use part)
   hipGraphExec_t step_exec = nullptr;
   ~don_trainer_s() {
     if (step_exec) (void)hipGraphExecDestroy(step_exec);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (st2) (void)hipStreamDestroy(st2);
     if (st) (void)hipStreamDestroy(st);
     for (Buffer* b : {&master, &grad, &mom, &var, &wbf, &wtb, &X, &XT, &Fb, &FbT, &ba.h, &ba.hT, &ta.h, &ta.hT, &dz[0],
                       &dz[1], &dzT[0], &dzT[1], &bdz[0], &bdz[1], &bdzT[0], &bdzT[1], &Bc, &BcT, &Ut, &dUt, &dUtT,
-                      &dBc, &part, &lpart, &wv, &ctr, &losses, &idx, &Fdata})
+                      &dBc, &part, &bpart, &lpart, &wv, &ctr, &losses, &idx, &Fdata})
       b->release();
   }
 };
@@ -552,7 +559,7 @@ int splits_for(int M, int N, int K, int target) {
 }
 
 // forward through one MLP from H0 (M x Kp0) and its transpose
-void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, Acts& a) {
+void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, Acts& a, hipStream_t st, float* part) {
   const __bf16* wt = (const __bf16*)t->wtb.ptr;
   const float* mw = (const float*)t->master.ptr;
   __bf16* h = (__bf16*)a.h.ptr;
@@ -561,14 +568,15 @@ void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, A
   for (size_t li = 0; li < L.size(); ++li) {
     const Layer& y = L[li];
     const bool last = li + 1 == L.size();
-    gemm(t->st, in, y.Kp, wt + y.offW, y.Kp, M, y.N, y.Kp, h + a.off[li], y.N, last ? EP_BIAS_BF16 : EP_BIAS_TANH_BF16,
-         mw + y.offb, nullptr, hT + a.off[li], M, splits_for(M, y.N, y.Kp, 256), (float*)t->part.ptr);
+    gemm(st, in, y.Kp, wt + y.offW, y.Kp, M, y.N, y.Kp, h + a.off[li], y.N, last ? EP_BIAS_BF16 : EP_BIAS_TANH_BF16,
+         mw + y.offb, nullptr, hT + a.off[li], M, splits_for(M, y.N, y.Kp, 256), part);
     in = h + a.off[li];
   }
 }
 
 // backward through one MLP given dZ of its last layer (row-major dz[0], transposed dzT[0])
-void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, Acts& a, Buffer* dz, Buffer* dzT) {
+void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, Acts& a, Buffer* dz, Buffer* dzT,
+             hipStream_t st, float* part) {
   const __bf16* wb = (const __bf16*)t->wbf.ptr;
   float* g = (float*)t->grad.ptr;
   const __bf16* h = (const __bf16*)a.h.ptr;
@@ -582,19 +590,28 @@ void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, 
     // dW = H^T dZ (Kp x N): A = H^T (Kp x M), B = dZ^T (N x M), reduction over the M rows
     int sp = splits_for(y.Kp, y.N, M, 512);
     while ((size_t)sp * y.Kp * y.N > t->part_floats && sp > 1) --sp;
-    gemm(t->st, inT, M, dT, M, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, nullptr, 0, sp,
-         (float*)t->part.ptr);
+    gemm(st, inT, M, dT, M, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, nullptr, 0, sp, part);
     // db = row sums of dZ^T
-    hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, t->st, (const __bf16*)dT, (long)M, g + y.offb);
+    hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, st, (const __bf16*)dT, (long)M, g + y.offb);
     if (li > 0) {
       // dZ_below = (dZ W^T) * (1 - H_below^2): A = dZ (M x N), B = W (Kp x N, n-major = k-contiguous)
       const Layer& z = L[li - 1];
       __bf16* dn = (__bf16*)dz[1 - cur].ptr;
       __bf16* dnT = (__bf16*)dzT[1 - cur].ptr;
-      gemm(t->st, d, y.N, wb + y.offW, y.N, M, z.N, y.N, dn, z.N, EP_DTANH_BF16, nullptr, h + a.off[li - 1], dnT, M);
+      gemm(st, d, y.N, wb + y.offW, y.N, M, z.N, y.N, dn, z.N, EP_DTANH_BF16, nullptr, h + a.off[li - 1], dnT, M);
       cur = 1 - cur;
     }
   }
+}
+
+// st2 starts after the work queued so far on st; st continues after st2's work
+void fork(don_trainer_s* t) {
+  (void)hipEventRecord(t->ev_fork, t->st);
+  (void)hipStreamWaitEvent(t->st2, t->ev_fork, 0);
+}
+void join(don_trainer_s* t) {
+  (void)hipEventRecord(t->ev_join, t->st2);
+  (void)hipStreamWaitEvent(t->st, t->ev_join, 0);
 }
 
 void train_step(don_trainer_s* t, bool update) {
@@ -604,10 +621,13 @@ void train_step(don_trainer_s* t, bool update) {
   const Layer& b0 = t->bl[0];
   __bf16* Fb = (__bf16*)t->Fb.ptr;
   __bf16* FbT = (__bf16*)t->FbT.ptr;
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(b0.Kp) < 64 ? grid_for(b0.Kp) : 64, S), dim3(256), 0, t->st,
+  // the two MLPs are independent until the output product: branch on st2, trunk on st
+  fork(t);
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(b0.Kp) < 64 ? grid_for(b0.Kp) : 64, S), dim3(256), 0, t->st2,
                      (const __bf16*)t->Fdata.ptr, (long)b0.Kp, idx, ctr, S, Fb, FbT);
-  mlp_fwd(t, t->bl, Fb, S, t->ba);
-  mlp_fwd(t, t->tl, (const __bf16*)t->X.ptr, P, t->ta);
+  mlp_fwd(t, t->bl, Fb, S, t->ba, t->st2, (float*)t->bpart.ptr);
+  mlp_fwd(t, t->tl, (const __bf16*)t->X.ptr, P, t->ta, t->st, (float*)t->part.ptr);
+  join(t);
   const size_t lb = t->bl.size() - 1, lt = t->tl.size() - 1;
   const __bf16* Bout = (const __bf16*)t->ba.h.ptr + t->ba.off[lb];
   const __bf16* T = (const __bf16*)t->ta.h.ptr + t->ta.off[lt];
@@ -637,8 +657,10 @@ void train_step(don_trainer_s* t, bool update) {
        (float*)t->part.ptr);
   hipLaunchKernelGGL(k_from_dbc, dim3((2 * S * p + 255) / 256), dim3(256), 0, t->st, (const float*)dBc, S, p,
                      (__bf16*)t->bdz[0].ptr, (__bf16*)t->bdzT[0].ptr);
-  mlp_bwd(t, t->tl, (const __bf16*)t->XT.ptr, P, t->ta, t->dz, t->dzT);
-  mlp_bwd(t, t->bl, FbT, S, t->ba, t->bdz, t->bdzT);
+  fork(t);
+  mlp_bwd(t, t->bl, FbT, S, t->ba, t->bdz, t->bdzT, t->st2, (float*)t->bpart.ptr);
+  mlp_bwd(t, t->tl, (const __bf16*)t->XT.ptr, P, t->ta, t->dz, t->dzT, t->st, (float*)t->part.ptr);
+  join(t);
   if (update) {
     hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
                        (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
@@ -706,8 +728,11 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
     if (e) delete t;
     return e;
   };
-  if (hipStreamCreateWithFlags(&t->st, hipStreamNonBlocking) != hipSuccess)
-    return fin(fail(HELM_E_HIP, "don_train_create: stream"));
+  if (hipStreamCreateWithFlags(&t->st, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&t->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming) != hipSuccess)
+    return fin(fail(HELM_E_HIP, "don_train_create: streams and events"));
   const size_t S = t->S, P = t->P;
   auto acts = [&](Acts& a, std::vector<Layer>& L, size_t M) -> helm_status {
     size_t sum = 0;
@@ -741,7 +766,7 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
       return fin(s);
   if ((s = t->Bc.ensure(2 * 2 * S * t->p)) || (s = t->BcT.ensure(2 * 2 * S * t->p)) || (s = t->Ut.ensure(4 * 2 * S * P)) ||
       (s = t->dUt.ensure(2 * 2 * S * P)) || (s = t->dUtT.ensure(2 * 2 * S * P)) || (s = t->dBc.ensure(4 * 2 * S * t->p)) ||
-      (s = t->part.ensure(4 * t->part_floats)) || (s = t->lpart.ensure(8 * 2 * S * nch)) || (s = t->wv.ensure(4 * S)) ||
+      (s = t->part.ensure(4 * t->part_floats)) || (s = t->bpart.ensure(4 * t->part_floats)) || (s = t->lpart.ensure(8 * 2 * S * nch)) || (s = t->wv.ensure(4 * S)) ||
       (s = t->ctr.ensure(64)) || (s = t->losses.ensure(4 * (size_t)o->max_steps)) ||
       (s = t->idx.ensure(4 * (size_t)o->max_steps * S)))
     return fin(s);
