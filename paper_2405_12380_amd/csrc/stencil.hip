@@ -204,6 +204,187 @@ __global__ __launch_bounds__(512) void k_rbgs_fused(StencilGeom g, const cplx_t<
   }
 }
 
+// ---- red-black sweep through an LDS ring of planes (3D) -------------------------
+// A workgroup owns a 64 x 8 column tile and marches over zb planes.  Each plane
+// of uin is staged once in LDS with a two-node rim (68 x 12 values); a ring of
+// six staged planes is kept.  In step z the red half-sweep of plane z + 1 runs
+// on the tile and a one-node rim (the rim's red values are the neighbouring
+// tile's, recomputed here from uin, so no other workgroup's output is read) and
+// overwrites the red positions of the staged plane; then the black half-sweep
+// of plane z reads its six red neighbours (planes z - 1, z, z + 1) and its own
+// old value from LDS.  Black positions in LDS always keep their uin values, which
+// is what the red updates read.  Plane z + 4 is loaded into registers one step
+// ahead and the node data (code byte, s, f) of the next step's updates as well;
+// one barrier per step.  Every global access is a buffer load or store whose
+// offset is pushed past the end of the buffer where the node is absent (loads
+// give 0, stores are dropped), so a step issues the same memory operations on
+// every path and waiting for the prefetched data never waits for the step's
+// stores.  Red values are rounded to the storage precision before the black
+// updates read them, as if the two colours were separate passes through
+// memory; the per-node arithmetic is relax_upd's.  Buffers must be under 2 GiB.
+constexpr int RB_TX = 64, RB_TY = 8, RB_LX = RB_TX + 4, RB_LY = RB_TY + 4, RB_PL = RB_LX * RB_LY, RB_NS = 6;
+constexpr int RB_RROW = (RB_TX + 2) / 2, RB_NRED = RB_RROW * (RB_TY + 2);  // red nodes of the tile and its rim (330)
+constexpr unsigned RB_OOB = 0x80000000u;  // byte offset past the end of every buffer the kernel is given
+static_assert(RB_PL <= 4 * 256 && RB_NRED <= 2 * 256 && RB_TX * RB_TY == 2 * 256, "ring tile sizes");
+
+typedef unsigned int rb_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int rb_u2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rb_rsrc(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double2 rb_ld(__amdgpu_buffer_rsrc_t r, unsigned off, const double2*) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 rb_ld(__amdgpu_buffer_rsrc_t r, unsigned off, const float2*) {
+  const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  return make_double2((double)v.x, (double)v.y);
+}
+template <bool NT>
+__device__ __forceinline__ void rb_st(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v, double2*) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(rb_u4, v), r, off, 0, NT ? 2 : 0);
+}
+template <bool NT>
+__device__ __forceinline__ void rb_st(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v, float2*) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rb_u2, make_float2((float)v.x, (float)v.y)), r, off, 0,
+                                        NT ? 2 : 0);
+}
+
+template <typename S>
+__device__ __forceinline__ double2 rnd_store(double2 v) {
+  if (sizeof(S) == sizeof(float)) return make_double2((double)(float)v.x, (double)(float)v.y);
+  return v;
+}
+
+struct NodeIn {
+  unsigned cd;
+  double2 s, f;
+};
+
+template <typename S, bool NT>
+__global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const cplx_t<S>* __restrict__ sc,
+                                                   const uint8_t* __restrict__ code,
+                                                   const cplx_t<S>* __restrict__ uin, const cplx_t<S>* __restrict__ f,
+                                                   cplx_t<S>* __restrict__ uout, double omega) {
+  using C = cplx_t<S>;
+  __shared__ double2 ring[RB_NS][RB_PL];
+  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned nbx = (g.nx + RB_TX - 1) / RB_TX, nby = (g.ny + RB_TY - 1) / RB_TY;
+  const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+  const int gx0 = bx * RB_TX - 2, gy0 = by * RB_TY - 2;  // global (x, y) of LDS position (0, 0)
+  const int z0 = bz * zb, z1 = min(g.nz, z0 + zb);
+  const int t = threadIdx.x;
+  const size_t nxy = (size_t)g.nx * g.ny, nn = nxy * g.nz;
+  const __amdgpu_buffer_rsrc_t r_u = rb_rsrc(uin, nn * sizeof(C)), r_f = rb_rsrc(f, nn * sizeof(C)),
+                               r_s = rb_rsrc(sc, nn * sizeof(C)), r_c = rb_rsrc(code, nn),
+                               r_o = rb_rsrc(uout, nn * sizeof(C));
+  auto slot = [](int k) { return (k + RB_NS) % RB_NS; };  // k >= -RB_NS
+  // node index of LDS position e in plane k, or -1 where there is no node
+  auto node = [&](int e, int k) -> long {
+    const int gx = gx0 + e % RB_LX, gy = gy0 + e / RB_LX;
+    return (k >= 0 && k < g.nz && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny)
+               ? (long)((size_t)gx + (size_t)g.nx * gy + nxy * k)
+               : -1L;
+  };
+  auto boff = [](long p, unsigned esz) { return p >= 0 ? (unsigned)p * esz : RB_OOB; };
+  // staged plane k: thread t holds LDS positions t + 256 q (zero where there is no node)
+  double2 pre[4];
+  auto load_plane = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      pre[q] = rb_ld(r_u, boff(e < RB_PL ? node(e, k) : -1L, sizeof(C)), (const C*)nullptr);
+    }
+  };
+  auto store_plane = [&](int k) {
+    double2* P = ring[slot(k)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (t + 256 * q < RB_PL) P[t + 256 * q] = pre[q];
+  };
+  // red node r (< RB_NRED) of plane k: LDS position on the tile or its one-node rim
+  auto red_pos = [&](int r, int k) {
+    const int ly = 1 + r / RB_RROW, c = r % RB_RROW;
+    const int lx = 1 + ((gx0 + 1 + gy0 + ly + k) & 1) + 2 * c;
+    return ly * RB_LX + lx;
+  };
+  // black node of plane k owned by thread t (32 per row, 8 rows)
+  auto black_pos = [&](int k) {
+    const int ly = 2 + t / (RB_TX / 2), c = t % (RB_TX / 2);
+    const int lx = 3 - ((gx0 + gy0 + ly + k) & 1) + 2 * c;
+    return ly * RB_LX + lx;
+  };
+  auto load_node = [&](long p, NodeIn& in) {
+    in.cd = __builtin_amdgcn_raw_buffer_load_b8(r_c, boff(p, 1), 0, 0);
+    in.s = rb_ld(r_s, boff(p, sizeof(C)), (const C*)nullptr);
+    in.f = rb_ld(r_f, boff(p, sizeof(C)), (const C*)nullptr);
+  };
+  // this thread's u-th red node of plane k: LDS position, node index (-1: none)
+  auto red_node = [&](int u, int k, int& e) -> long {
+    const int r = t + 256 * u;
+    e = red_pos(r < RB_NRED ? r : RB_NRED - 1, k);
+    return r < RB_NRED ? node(e, k) : -1L;
+  };
+  NodeIn rn[2], bn;  // node data of the next step's red updates and black update
+  auto load_next = [&](int kr, int kb) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int e;
+      load_node(red_node(u, kr, e), rn[u]);
+    }
+    load_node(node(black_pos(kb), kb), bn);
+  };
+  // red half-sweep of plane k; the tile's values go to uout when `own`
+  auto red = [&](int k, const NodeIn* in, bool own) {
+    double2* P = ring[slot(k)];
+    const double2* Pm = ring[slot(k - 1)];
+    const double2* Pp = ring[slot(k + 1)];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int e;
+      const long p = red_node(u, k, e);
+      const double2 v = rnd_store<S>(relax_upd<S>(g, in[u].cd, P[e], P[e - 1], P[e + 1], P[e - RB_LX], P[e + RB_LX],
+                                                  Pm[e], Pp[e], in[u].s, in[u].f, omega, true));
+      if (p >= 0) P[e] = v;
+      const int lx = e % RB_LX, ly = e / RB_LX;
+      const bool tile = lx >= 2 && lx < RB_TX + 2 && ly >= 2 && ly < RB_TY + 2;
+      rb_st<NT>(r_o, boff(own && tile ? p : -1L, sizeof(C)), v, (C*)nullptr);
+    }
+  };
+  // prologue: planes z0 - 2 .. z0 + 2 staged, plane z0 + 3 in flight, red of z0 - 1 and z0
+  NodeIn r0[2], r1[2];
+  for (int k = z0 - 2; k <= z0 + 2; ++k) {
+    load_plane(k);
+    store_plane(k);
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    int e;
+    load_node(red_node(u, z0 - 1, e), r0[u]);
+    load_node(red_node(u, z0, e), r1[u]);
+  }
+  load_plane(z0 + 3);
+  __syncthreads();
+  red(z0 - 1, r0, false);
+  red(z0, r1, true);
+  load_next(z0 + 1, z0);
+  for (int z = z0; z < z1; ++z) {
+    const NodeIn rc[2] = {rn[0], rn[1]};
+    const NodeIn bc = bn;
+    store_plane(z + 3);  // loaded one step ago; its slot last held plane z - 3
+    load_plane(z + 4);
+    load_next(z + 2, z + 1);
+    red(z + 1, rc, z + 1 < z1);
+    __syncthreads();
+    // black half-sweep of plane z on the tile
+    const int e = black_pos(z);
+    const double2* P = ring[slot(z)];
+    const double2 v = relax_upd<S>(g, bc.cd, P[e], P[e - 1], P[e + 1], P[e - RB_LX], P[e + RB_LX],
+                                   ring[slot(z - 1)][e], ring[slot(z + 1)][e], bc.s, bc.f, omega, true);
+    rb_st<NT>(r_o, boff(node(e, z), sizeof(C)), v, (C*)nullptr);
+  }
+}
+
 template <typename S>
 void jacobi2_from_zero(const StencilGeom& g, const void* sc, const uint8_t* code, const void* f, void* z, double omega,
                        hipStream_t st, const double* fscale, void* fout) {
@@ -330,7 +511,19 @@ void stencil_rbgs_fused(const StencilGeom& g0, const void* sc, const uint8_t* co
   const int nb = ((g.nx + 127) / 128) * ((g.ny + g.ty - 1) / g.ty) * ((g.nz + g.zb - 1) / g.zb);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   kprof_begin(KP_STENCIL, st);
-  if (g.dim == 3)
+  if (g.dim == 3 && n * esz < 2147483648.0) {
+    // planes per workgroup: about 1024 workgroups, marches of 2 .. 32 planes
+    const long tiles = (long)((g.nx + RB_TX - 1) / RB_TX) * ((g.ny + RB_TY - 1) / RB_TY);
+    int zb = (int)(tiles * g.nz / 1024);
+    zb = zb < 2 ? 2 : zb > 32 ? 32 : zb;
+    const long nbr = tiles * ((g.nz + zb - 1) / zb);
+    if (g.nt)
+      hipLaunchKernelGGL((k_rbgs_ring<S, true>), dim3((unsigned)nbr), dim3(256), 0, st, g, zb, (const C*)sc, code,
+                         (const C*)uin, (const C*)f, (C*)uout, omega);
+    else
+      hipLaunchKernelGGL((k_rbgs_ring<S, false>), dim3((unsigned)nbr), dim3(256), 0, st, g, zb, (const C*)sc, code,
+                         (const C*)uin, (const C*)f, (C*)uout, omega);
+  } else if (g.dim == 3)
     hipLaunchKernelGGL((k_rbgs_fused<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)uin,
                        (const C*)f, (C*)uout, omega);
   else
