@@ -394,10 +394,20 @@ __global__ __launch_bounds__(256) void k_dU(const float* __restrict__ Ut, const 
   }
 }
 
-// Adam on the flat parameters (fp32), step t = tstep[0] + 1; refreshes the bf16 copies
+// weight matrices inside the flat parameter array (Kp x N row-major at off)
+constexpr int WT_MAX = 16;
+struct WTab {
+  int n;
+  long off[WT_MAX];
+  int Kp[WT_MAX], N[WT_MAX];
+};
+
+// Adam on the flat parameters (fp32), step t = tstep[0] + 1; refreshes the bf16
+// copies: W as stored, and W^T (N x Kp) of every matrix listed in tab
 __global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ w, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, __bf16* __restrict__ wb,
-                                              float lr, float b1, float b2, float eps, const int* __restrict__ tstep) {
+                                              __bf16* __restrict__ wt, WTab tab, float lr, float b1, float b2,
+                                              float eps, const int* __restrict__ tstep) {
   const int t = tstep[0] + 1;
   // bias corrections in fp64: 1 - b2^t in fp32 cancels about 10 bits at b2 = 0.999
   const float c1 = (float)(1.0 - pow((double)b1, (double)t)), c2 = (float)(1.0 - pow((double)b2, (double)t));
@@ -409,7 +419,15 @@ __global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ w, con
     v[e] = ve;
     const float we = w[e] - lr * (me / c1) / (sqrtf(ve / c2) + eps);
     w[e] = we;
-    wb[e] = (__bf16)we;
+    const __bf16 wh = (__bf16)we;
+    wb[e] = wh;
+    for (int L = 0; L < tab.n; ++L) {
+      const long o = e - tab.off[L];
+      if (o >= 0 && o < (long)tab.Kp[L] * tab.N[L]) {
+        const int oi = (int)o;
+        wt[tab.off[L] + (long)(oi % tab.N[L]) * tab.Kp[L] + oi / tab.N[L]] = wh;
+      }
+    }
   }
 }
 
@@ -508,13 +526,19 @@ struct don_trainer_s {
   // the branch MLP runs on st2, beside the trunk on st (forked and joined by events)
   hipStream_t st2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the trunk's bias gradients (row sums of dZ^T) run on st3 beside its weight products
+  hipStream_t st3 = nullptr;
+  hipEvent_t ev_rs = nullptr, ev_rsj = nullptr;
   Buffer bpart;  // split-k partials of the branch products (the trunk's use part)
   hipGraphExec_t step_exec = nullptr;
   ~don_trainer_s() {
     if (step_exec) (void)hipGraphExecDestroy(step_exec);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_rs) (void)hipEventDestroy(ev_rs);
+    if (ev_rsj) (void)hipEventDestroy(ev_rsj);
     if (st2) (void)hipStreamDestroy(st2);
+    if (st3) (void)hipStreamDestroy(st3);
     if (st) (void)hipStreamDestroy(st);
     for (Buffer* b : {&master, &grad, &mom, &var, &wbf, &wtb, &X, &XT, &Fb, &FbT, &ba.h, &ba.hT, &ta.h, &ta.hT, &dz[0],
                       &dz[1], &dzT[0], &dzT[1], &bdz[0], &bdz[1], &bdzT[0], &bdzT[1], &Bc, &BcT, &Ut, &dUt, &dUtT,
@@ -575,8 +599,10 @@ void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, A
 }
 
 // backward through one MLP given dZ of its last layer (row-major dz[0], transposed dzT[0])
+// side (optional): stream for the bias gradients, forked from st per layer and
+// joined before the dZ buffer it reads is overwritten (two layers on) and at the end
 void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, Acts& a, Buffer* dz, Buffer* dzT,
-             hipStream_t st, float* part) {
+             hipStream_t st, float* part, hipStream_t side = nullptr) {
   const __bf16* wb = (const __bf16*)t->wbf.ptr;
   float* g = (float*)t->grad.ptr;
   const __bf16* h = (const __bf16*)a.h.ptr;
@@ -587,21 +613,46 @@ void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, 
     const __bf16* inT = li == 0 ? H0T : hT + a.off[li - 1];
     __bf16* d = (__bf16*)dz[cur].ptr;
     __bf16* dT = (__bf16*)dzT[cur].ptr;
+    // db = row sums of dZ^T
+    if (side) {
+      (void)hipEventRecord(t->ev_rs, st);
+      (void)hipStreamWaitEvent(side, t->ev_rs, 0);
+      hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, side, (const __bf16*)dT, (long)M, g + y.offb);
+      (void)hipEventRecord(t->ev_rsj, side);
+    } else {
+      hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, st, (const __bf16*)dT, (long)M, g + y.offb);
+    }
     // dW = H^T dZ (Kp x N): A = H^T (Kp x M), B = dZ^T (N x M), reduction over the M rows
     int sp = splits_for(y.Kp, y.N, M, 512);
     while ((size_t)sp * y.Kp * y.N > t->part_floats && sp > 1) --sp;
     gemm(st, inT, M, dT, M, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, nullptr, 0, sp, part);
-    // db = row sums of dZ^T
-    hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, st, (const __bf16*)dT, (long)M, g + y.offb);
     if (li > 0) {
       // dZ_below = (dZ W^T) * (1 - H_below^2): A = dZ (M x N), B = W (Kp x N, n-major = k-contiguous)
       const Layer& z = L[li - 1];
       __bf16* dn = (__bf16*)dz[1 - cur].ptr;
       __bf16* dnT = (__bf16*)dzT[1 - cur].ptr;
+      // dnT held the previous layer's dZ^T, read by its row sums on the side stream
+      if (side) (void)hipStreamWaitEvent(st, t->ev_rsj, 0);
       gemm(st, d, y.N, wb + y.offW, y.N, M, z.N, y.N, dn, z.N, EP_DTANH_BF16, nullptr, h + a.off[li - 1], dnT, M);
       cur = 1 - cur;
     }
   }
+  if (side) (void)hipStreamWaitEvent(st, t->ev_rsj, 0);
+}
+
+// Adam step on st (parameters, moments, both bf16 copies)
+void adam(don_trainer_s* t, const int* tstep) {
+  WTab tab{};
+  for (auto* L : {&t->bl, &t->tl})
+    for (const Layer& y : *L) {
+      tab.off[tab.n] = (long)y.offW;
+      tab.Kp[tab.n] = y.Kp;
+      tab.N[tab.n] = y.N;
+      ++tab.n;
+    }
+  hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
+                     (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
+                     (__bf16*)t->wbf.ptr, (__bf16*)t->wtb.ptr, tab, t->lr, t->b1, t->b2, t->eps, tstep);
 }
 
 // st2 starts after the work queued so far on st; st continues after st2's work
@@ -659,16 +710,10 @@ void train_step(don_trainer_s* t, bool update) {
                      (__bf16*)t->bdz[0].ptr, (__bf16*)t->bdzT[0].ptr);
   fork(t);
   mlp_bwd(t, t->bl, FbT, S, t->ba, t->bdz, t->bdzT, t->st2, (float*)t->bpart.ptr);
-  mlp_bwd(t, t->tl, (const __bf16*)t->XT.ptr, P, t->ta, t->dz, t->dzT, t->st, (float*)t->part.ptr);
+  mlp_bwd(t, t->tl, (const __bf16*)t->XT.ptr, P, t->ta, t->dz, t->dzT, t->st, (float*)t->part.ptr, t->st3);
   join(t);
   if (update) {
-    hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
-                       (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
-                       (__bf16*)t->wbf.ptr, t->lr, t->b1, t->b2, t->eps, ctr + 1);
-    for (auto* L : {&t->bl, &t->tl})
-      for (const Layer& y : *L)
-        hipLaunchKernelGGL(k_transpose, dim3(grid_for((long)y.Kp * y.N)), dim3(256), 0, t->st, y.Kp, y.N,
-                           (const __bf16*)t->wbf.ptr + y.offW, (__bf16*)t->wtb.ptr + y.offW);
+    adam(t, ctr + 1);
   }
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, t->st, (int*)t->ctr.ptr, (int*)t->ctr.ptr + 1, update ? 1 : 0);
 }
@@ -696,6 +741,8 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   for (size_t i = 1; i < net->tw.size(); ++i)
     if (net->tw[i] > 256 || net->tw[i] % 64)
       return fail(HELM_E_INVAL, "don_train_create: trunk widths after the input must be multiples of 64, <= 256");
+  if (net->bw.size() + net->tw.size() - 2 > (size_t)WT_MAX)
+    return fail(HELM_E_INVAL, "don_train_create: more than %d layers", WT_MAX);
   don_trainer_s* t = new don_trainer_s();
   t->S = o->batch;
   t->P = o->n_points;
@@ -730,6 +777,9 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   };
   if (hipStreamCreateWithFlags(&t->st, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&t->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&t->st3, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_rs, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&t->ev_rsj, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming) != hipSuccess)
     return fin(fail(HELM_E_HIP, "don_train_create: streams and events"));
@@ -896,13 +946,7 @@ helm_status don_train_apply(don_trainer t, const float* grads, void* stream) {
   hipError_t e = hipMemcpyAsync(t->grad.ptr, grads, 4 * t->nparam, hipMemcpyDeviceToDevice, t->st);
   if (e != hipSuccess) return hip_fail(e, "don_train_apply: copy");
   int* ctr = (int*)t->ctr.ptr;
-  hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
-                     (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
-                     (__bf16*)t->wbf.ptr, t->lr, t->b1, t->b2, t->eps, (const int*)(ctr + 1));
-  for (auto* L : {&t->bl, &t->tl})
-    for (const Layer& y : *L)
-      hipLaunchKernelGGL(k_transpose, dim3(grid_for((long)y.Kp * y.N)), dim3(256), 0, t->st, y.Kp, y.N,
-                         (const __bf16*)t->wbf.ptr + y.offW, (__bf16*)t->wtb.ptr + y.offW);
+  adam(t, ctr + 1);
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, t->st, ctr, ctr + 1, 1);
   return sync(t, "don_train_apply");
 }
