@@ -530,9 +530,11 @@ struct don_trainer_s {
   hipStream_t st3 = nullptr;
   hipEvent_t ev_rs = nullptr, ev_rsj = nullptr;
   Buffer bpart;  // split-k partials of the branch products (the trunk's use part)
-  hipGraphExec_t step_exec = nullptr;
+  hipGraphExec_t step_exec = nullptr;   // one step
+  hipGraphExec_t multi_exec = nullptr;  // GRAPH_STEPS steps (fewer gaps between graph launches)
   ~don_trainer_s() {
     if (step_exec) (void)hipGraphExecDestroy(step_exec);
+    if (multi_exec) (void)hipGraphExecDestroy(multi_exec);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_rs) (void)hipEventDestroy(ev_rs);
@@ -885,6 +887,8 @@ helm_status don_train_data(don_trainer t, int n, const float* F, const void* Y) 
   return sync(t, "don_train_data");
 }
 
+static constexpr int GRAPH_STEPS = 8;
+
 static helm_status run_steps(don_trainer t, int count, const int* idx, bool update, float* loss_out) {
   if (!t || !idx || count < 1) return fail(HELM_E_INVAL, "don_train: bad argument");
   if (!t->Y) return fail(HELM_E_INVAL, "don_train: no data (don_train_data)");
@@ -899,19 +903,29 @@ static helm_status run_steps(don_trainer t, int count, const int* idx, bool upda
   if (e != hipSuccess) return hip_fail(e, "don_train: setup");
   helm_status s;
   if (update) {
-    if (!t->step_exec) {
+    // steps are captured once as graphs of one and of GRAPH_STEPS steps; the
+    // sample indices and the step counter live on the device
+    auto capture = [&](int steps, hipGraphExec_t* out) -> helm_status {
       hipGraph_t g;
-      if ((s = sync(t, "don_train: capture"))) return s;
+      helm_status s2 = sync(t, "don_train: capture");
+      if (s2) return s2;
       if (hipStreamBeginCapture(t->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(HELM_E_HIP, "don_train: begin capture");
-      train_step(t, true);
-      e = hipStreamEndCapture(t->st, &g);
-      if (e != hipSuccess) return hip_fail(e, "don_train: end capture");
-      e = hipGraphInstantiate(&t->step_exec, g, nullptr, nullptr, 0);
+      for (int k = 0; k < steps; ++k) train_step(t, true);
+      hipError_t e2 = hipStreamEndCapture(t->st, &g);
+      if (e2 != hipSuccess) return hip_fail(e2, "don_train: end capture");
+      e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return hip_fail(e, "don_train: instantiate");
+      return e2 == hipSuccess ? HELM_OK : hip_fail(e2, "don_train: instantiate");
+    };
+    if (!t->step_exec && (s = capture(1, &t->step_exec))) return s;
+    if (count >= GRAPH_STEPS && !t->multi_exec && (s = capture(GRAPH_STEPS, &t->multi_exec))) return s;
+    int k = 0;
+    for (; k + GRAPH_STEPS <= count; k += GRAPH_STEPS) {
+      e = hipGraphLaunch(t->multi_exec, t->st);
+      if (e != hipSuccess) return hip_fail(e, "don_train: replay");
     }
-    for (int k = 0; k < count; ++k) {
+    for (; k < count; ++k) {
       e = hipGraphLaunch(t->step_exec, t->st);
       if (e != hipSuccess) return hip_fail(e, "don_train: replay");
     }
