@@ -31,8 +31,11 @@ struct Prof {
       pool.pop_back();
       return e;
     }
+    // timing-only events: no system-scope cache writeback and invalidation at
+    // each record, which would otherwise sit inside the measured interval and
+    // slow the kernel that follows
     hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
+    (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
   }
   void clear() {
