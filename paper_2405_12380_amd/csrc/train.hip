@@ -17,8 +17,11 @@
 // every product is of that form, the epilogues also write a transposed copy of
 // each activation and each gradient (the backward products reduce over the
 // points, which must then be contiguous), and Adam refreshes both W and W^T in
-// bf16.  A step is captured once as a HIP graph and replayed; the
-// sample indices and the step counter live on the device.
+// bf16.  The branch MLP (forward and backward) runs on a second stream beside
+// the trunk, and the trunk's bias row sums on a third beside its weight
+// products.  Steps are captured as HIP graphs (one step, and eight steps per
+// launch) and replayed; the sample indices and the step counter live on the
+// device.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
