@@ -243,6 +243,105 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+// Whole-MLP forward for a 128-row block (the trunk, whose M is the number of
+// points): the block's activation stays in LDS from layer to layer, so only
+// the first layer's input is read from HBM; each layer writes its output (h,
+// row-major) and its transpose (h^T) for the backward pass.  Four wavefronts,
+// wavefront w owning output columns 64 w .. 64 w + 63 of all 128 rows (8 x 4
+// tiles of v_mfma_f32_16x16x32_bf16); A fragments come from the LDS
+// activation, B fragments straight from W^T (a few hundred KB, resident in L2)
+// one 32-deep k step ahead, so the k loop has no barrier.  The k order of the
+// accumulation and the epilogue are those of k_gemm_nt, so the values equal
+// the layer-by-layer products bit for bit.
+constexpr int FW_MAXL = 8, FW_ACT = 256 + 8;  // layers; LDS activation row stride (bf16)
+struct FwdArgs {
+  int L, M;
+  int Kp[FW_MAXL], N[FW_MAXL];  // Kp[0] = padded input width; Kp[l + 1] = N[l]; all multiples of 64, <= 256
+  const __bf16* X;              // M x Kp[0] input rows
+  const __bf16* wt[FW_MAXL];    // W^T, N x Kp, k-contiguous
+  const float* bias[FW_MAXL];
+  __bf16* h[FW_MAXL];   // M x N
+  __bf16* hT[FW_MAXL];  // N x M
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_fwd(FwdArgs a) {
+  __shared__ __attribute__((aligned(16))) __bf16 act[TM * FW_ACT];
+  const int m0 = blockIdx.x * TM;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  bf8 zero;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
+  {
+    const int cpr = a.Kp[0] / 8;  // 16-byte pieces per input row
+    for (int c = t; c < TM * cpr; c += 256) {
+      const int r = c / cpr, kq = (c % cpr) * 8;
+      *(bf8*)(act + r * FW_ACT + kq) = m0 + r < a.M ? *(const bf8*)(a.X + (long)(m0 + r) * a.Kp[0] + kq) : zero;
+    }
+  }
+  __syncthreads();
+  for (int li = 0; li < a.L; ++li) {
+    const int Kp = a.Kp[li], N = a.N[li];
+    const bool last = li + 1 == a.L, on = 64 * w < N;
+    f4 acc[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    if (on) {
+      // lane l's B fragment rows: W^T rows 64 w + 16 j + (l % 16), k offset 8 (l / 16)
+      const __bf16* Wl = a.wt[li] + (long)(64 * w + (l & 15)) * Kp + 8 * (l >> 4);
+      bf8 bv[4], bn[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = *(const bf8*)(Wl + (long)j * 16 * Kp);
+      for (int k = 0; k < Kp; k += 32) {
+        if (k + 32 < Kp) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bn[j] = *(const bf8*)(Wl + (long)j * 16 * Kp + k + 32);
+        }
+        bf8 av[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) av[i] = *(const bf8*)(act + (i * 16 + (l & 15)) * FW_ACT + k + 8 * (l >> 4));
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+      }
+    }
+    __syncthreads();  // every wavefront has finished reading this layer's input
+    if (on) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = 64 * w + j * 16 + (l & 15);
+        const float bias = a.bias[li][col];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float v = acc[i][j][q] + bias;
+            if (!last) v = fast_tanh(v);
+            act[(i * 16 + 4 * (l >> 4) + q) * FW_ACT + col] = (__bf16)v;
+          }
+      }
+    }
+    __syncthreads();
+    // h as 16-byte row pieces, h^T as 16-byte column pieces gathered from eight rows
+    const int cpr = N / 8;
+    for (int c = t; c < TM * cpr; c += 256) {
+      const int r = c / cpr, cq = (c % cpr) * 8;
+      if (m0 + r < a.M) *(bf8*)(a.h[li] + (long)(m0 + r) * N + cq) = *(const bf8*)(act + r * FW_ACT + cq);
+    }
+    for (int c = t; c < N * (TM / 8); c += 256) {
+      const int col = c / (TM / 8), rq = (c % (TM / 8)) * 8;
+      bf8 v;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = act[(rq + u) * FW_ACT + col];
+      if (m0 + rq + 8 <= a.M) *(bf8*)(a.hT[li] + (long)col * a.M + m0 + rq) = v;
+    }
+  }
+}
+
 // sum of split-k slices in a fixed order, then the epilogue (and the transposed copy)
 __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g, const float* __restrict__ part, int splits) {
   const long MN = (long)g.M * g.N;
@@ -588,19 +687,41 @@ int splits_for(int M, int N, int K, int target) {
 }
 
 // forward through one MLP from H0 (M x Kp0) and its transpose
-void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, Acts& a, hipStream_t st, float* part) {
+// forward through layers 0 .. count - 1 of one MLP, one product per layer
+void mlp_fwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, Acts& a, hipStream_t st, float* part,
+             size_t count) {
   const __bf16* wt = (const __bf16*)t->wtb.ptr;
   const float* mw = (const float*)t->master.ptr;
   __bf16* h = (__bf16*)a.h.ptr;
   __bf16* hT = (__bf16*)a.hT.ptr;
   const __bf16* in = H0;
-  for (size_t li = 0; li < L.size(); ++li) {
+  for (size_t li = 0; li < count; ++li) {
     const Layer& y = L[li];
     const bool last = li + 1 == L.size();
     gemm(st, in, y.Kp, wt + y.offW, y.Kp, M, y.N, y.Kp, h + a.off[li], y.N, last ? EP_BIAS_BF16 : EP_BIAS_TANH_BF16,
          mw + y.offb, nullptr, hT + a.off[li], M, splits_for(M, y.N, y.Kp, 256), part);
     in = h + a.off[li];
   }
+}
+
+// forward through layers first .. of one MLP in one launch (k_mlp_fwd); the
+// input is H0 for first = 0, else the output of layer first - 1
+void mlp_fwd_fused(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, int M, Acts& a, hipStream_t st,
+                   int first = 0) {
+  FwdArgs f{};
+  f.L = (int)L.size() - first;
+  f.M = M;
+  f.X = first == 0 ? H0 : (const __bf16*)a.h.ptr + a.off[first - 1];
+  for (int q = 0; q < f.L; ++q) {
+    const Layer& y = L[first + q];
+    f.Kp[q] = y.Kp;
+    f.N[q] = y.N;
+    f.wt[q] = (const __bf16*)t->wtb.ptr + y.offW;
+    f.bias[q] = (const float*)t->master.ptr + y.offb;
+    f.h[q] = (__bf16*)a.h.ptr + a.off[first + q];
+    f.hT[q] = (__bf16*)a.hT.ptr + a.off[first + q];
+  }
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((M + TM - 1) / TM), dim3(256), 0, st, f);
 }
 
 // backward through one MLP given dZ of its last layer (row-major dz[0], transposed dzT[0])
@@ -681,8 +802,10 @@ void train_step(don_trainer_s* t, bool update) {
   fork(t);
   hipLaunchKernelGGL(k_gather, dim3(grid_for(b0.Kp) < 64 ? grid_for(b0.Kp) : 64, S), dim3(256), 0, t->st2,
                      (const __bf16*)t->Fdata.ptr, (long)b0.Kp, idx, ctr, S, Fb, FbT);
-  mlp_fwd(t, t->bl, Fb, S, t->ba, t->st2, (float*)t->bpart.ptr);
-  mlp_fwd(t, t->tl, (const __bf16*)t->X.ptr, P, t->ta, t->st, (float*)t->part.ptr);
+  // branch: the wide input layer as a split-k product, the rest in one launch
+  mlp_fwd(t, t->bl, Fb, S, t->ba, t->st2, (float*)t->bpart.ptr, 1);
+  if (t->bl.size() > 1) mlp_fwd_fused(t, t->bl, Fb, S, t->ba, t->st2, 1);
+  mlp_fwd_fused(t, t->tl, (const __bf16*)t->X.ptr, P, t->ta, t->st);
   join(t);
   const size_t lb = t->bl.size() - 1, lt = t->tl.size() - 1;
   const __bf16* Bout = (const __bf16*)t->ba.h.ptr + t->ba.off[lb];
@@ -746,8 +869,8 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   for (size_t i = 1; i < net->tw.size(); ++i)
     if (net->tw[i] > 256 || net->tw[i] % 64)
       return fail(HELM_E_INVAL, "don_train_create: trunk widths after the input must be multiples of 64, <= 256");
-  if (net->bw.size() + net->tw.size() - 2 > (size_t)WT_MAX)
-    return fail(HELM_E_INVAL, "don_train_create: more than %d layers", WT_MAX);
+  if (net->bw.size() + net->tw.size() - 2 > (size_t)WT_MAX || net->tw.size() - 1 > (size_t)FW_MAXL)
+    return fail(HELM_E_INVAL, "don_train_create: too many layers (%d in all, %d in the trunk at most)", WT_MAX, FW_MAXL);
   don_trainer_s* t = new don_trainer_s();
   t->S = o->batch;
   t->P = o->n_points;
