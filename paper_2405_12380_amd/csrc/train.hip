@@ -71,7 +71,7 @@ __device__ __forceinline__ float fast_tanh(float x) {
 }
 
 // Epilogue of one value of C(row, col); returns the stored bf16 value for the transposed copy.
-__device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, float v) {
+__device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, float v, int slice = 0) {
   const long o = (long)row * g.ldc + col;
   __bf16 r = (__bf16)0.0f;
   switch (g.ep) {
@@ -96,8 +96,8 @@ __device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, 
       ((__bf16*)g.C)[o] = r;
       break;
     }
-    default:  // EP_PART: split-k slice blockIdx.z of an M x N fp32 array
-      ((float*)g.C)[(long)blockIdx.z * g.M * g.N + (long)row * g.N + col] = v;
+    default:  // EP_PART: split-k slice `slice` of an M x N fp32 array
+      ((float*)g.C)[(long)slice * g.M * g.N + (long)row * g.N + col] = v;
   }
   return r;
 }
@@ -116,8 +116,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSW];
   __bf16* As = smem;
   __bf16* Bs = smem + TM * LDSW;
-  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
-  const int kb = blockIdx.z * g.kchunk;
+  // logical tile (y fastest, then x, then the k slice): consecutive logical
+  // blocks run on one XCD, so the column tiles of a row block, and the tiles of
+  // a k slice, read their shared operand rows through that XCD's L2
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned lb = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+  const int byl = lb % gy, bxl = (lb / gy) % gx, bzl = lb / (gx * gy);
+  const int m0 = bxl * TM, n0 = byl * TN;
+  const int kb = bzl * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int wm = w >> 1, wn = w & 1;
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (col >= g.N) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (row0 + q < g.M) ep_store(g, row0 + q, col, acc[i][j][q]);
+          if (row0 + q < g.M) ep_store(g, row0 + q, col, acc[i][j][q], bzl);
       }
     return;
   }
@@ -288,25 +294,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     if (on) {
-      // lane l's B fragment rows: W^T rows 64 w + 16 j + (l % 16), k offset 8 (l / 16)
+      // lane l's B fragment rows: W^T rows 64 w + 16 j + (l % 16), k offset 8 (l / 16);
+      // two register sets, each loaded one 32-deep step before it is used
       const __bf16* Wl = a.wt[li] + (long)(64 * w + (l & 15)) * Kp + 8 * (l >> 4);
-      bf8 bv[4], bn[4];
+      bf8 b0[4], b1[4];
+      auto loadb = [&](bf8* b, int k) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = *(const bf8*)(Wl + (long)j * 16 * Kp);
-      for (int k = 0; k < Kp; k += 32) {
-        if (k + 32 < Kp) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) bn[j] = *(const bf8*)(Wl + (long)j * 16 * Kp + k + 32);
-        }
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf8*)(Wl + (long)j * 16 * Kp + k);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads here, a whole step ahead of their use
+      };
+      auto step = [&](const bf8* b, int k) {
         bf8 av[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) av[i] = *(const bf8*)(act + (i * 16 + (l & 15)) * FW_ACT + k + 8 * (l >> 4));
 #pragma unroll
         for (int i = 0; i < 8; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], b[j], acc[i][j], 0, 0, 0);
+      };
+      loadb(b0, 0);
+      for (int k = 0; k < Kp; k += 64) {  // Kp is a multiple of 64
+        loadb(b1, k + 32);
+        step(b0, k);
+        loadb(b0, k + 64 < Kp ? k + 64 : k);  // the last step reloads (unconditional, so waits stay exact)
+        step(b1, k + 32);
       }
     }
     __syncthreads();  // every wavefront has finished reading this layer's input
