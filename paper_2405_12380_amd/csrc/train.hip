@@ -111,6 +111,12 @@ __device__ __forceinline__ __bf16 ep_store(const GemmArgs& g, int row, int col, 
 // B[l % 16][8 (l / 16) .. +7] (B stored n-major) and C[4 (l / 16) + i][l % 16].
 constexpr int CTW = TN + 8;  // LDS row stride of the staged output tile (bf16)
 
+// Position of element (r, c) of the staged output tile: the 16-byte pieces of
+// row r are permuted by (r / 8) mod 8, so the column gathers of the transposed
+// copy (sixteen lanes reading rows 8 apart) fall in distinct LDS banks; row
+// pieces stay contiguous and aligned.
+__device__ __forceinline__ int csw(int r, int c) { return r * CTW + ((((c >> 3) ^ ((r >> 3) & 7)) << 3) | (c & 7)); }
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_nt(GemmArgs g) {
   // operand tiles during the k loop; the output tile (then its transpose) afterwards
   __shared__ __attribute__((aligned(16))) __bf16 smem[(TM + TN) * LDSW];
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int c = t + 256 * k, rl = c >> 4, cq = (c & 15) * 8;
-      *(bf8*)(Cs + rl * CTW + cq) = hv[k];
+      *(bf8*)(Cs + csw(rl, cq)) = hv[k];
     }
     __syncthreads();
   }
@@ -219,7 +225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         float v = acc[i][j][q] + bias;
-        __bf16* cp = Cs + (wm * 64 + i * 16 + 4 * (l >> 4) + q) * CTW + wn * 64 + j * 16 + (l & 15);
+        __bf16* cp = Cs + csw(wm * 64 + i * 16 + 4 * (l >> 4) + q, wn * 64 + j * 16 + (l & 15));
         if (g.ep == EP_BIAS_TANH_BF16) v = fast_tanh(v);
         else if (g.ep == EP_DTANH_BF16) {
           const float h = bf2f(*cp);  // zero outside the M x N result, which is never stored
@@ -235,7 +241,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int c = t + 256 * k, rl = c >> 4, cq = (c & 15) * 8;
     const int row = m0 + rl, col = n0 + cq;
     if (row < g.M && col + 8 <= g.N)
-      *(bf8*)((__bf16*)g.C + (long)row * g.ldc + col) = *(const bf8*)(Cs + rl * CTW + cq);
+      *(bf8*)((__bf16*)g.C + (long)row * g.ldc + col) = *(const bf8*)(Cs + csw(rl, cq));
   }
   if (!g.CT) return;
 #pragma unroll
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int col = n0 + cl, row = m0 + rq;
     bf8 v;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = Cs[(rq + u) * CTW + cl];
+    for (int u = 0; u < 8; ++u) v[u] = Cs[csw(rq + u, cl)];
     if (col < g.N && row + 8 <= g.M) *(bf8*)(g.CT + (long)col * g.ldct + row) = v;
   }
 }

@@ -25,11 +25,11 @@ helm = pytest.importorskip("paper_2405_12380_amd.helm")
 NPTS = (16, 16, 16)
 
 
-def _net_and_data(seed=0, n=128, P=None):
+def _net_and_data(seed=0, n=128, P=None, npts=NPTS, trunk_w=(64, 64, 64)):
     g = np.random.default_rng([77, seed])
     branch = I.glorot_mlp([129, 64, 64, 128], g)
-    trunk = I.glorot_mlp([3, 64, 64, 64], g, first_gain=4.0)
-    X = I.node_points(NPTS)
+    trunk = I.glorot_mlp([3, *trunk_w], g, first_gain=4.0)
+    X = I.node_points(npts)
     F = g.standard_normal((n, 129)).astype(np.float32)
     Y = (g.standard_normal((n, X.shape[0])) + 1j * g.standard_normal((n, X.shape[0]))).astype(np.complex64)
     return branch, trunk, X, F, Y
@@ -44,8 +44,12 @@ def _f32(layers):
     return [(W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for W, b in layers]
 
 
-def test_grad_parity_with_bf16_oracle():
-    branch, trunk, X, F, Y = _net_and_data()
+@pytest.mark.parametrize("npts,trunk_w", [(NPTS, (64, 64, 64)), ((12, 12, 12), (128, 192, 64))])
+def test_grad_parity_with_bf16_oracle(npts, trunk_w):
+    """Loss and every gradient against the oracle with the same bf16 roundings;
+    the second case has a point count that leaves the last 128-row block half
+    full and trunk layers of 128 and 192 outputs."""
+    branch, trunk, X, F, Y = _net_and_data(npts=npts, trunk_w=trunk_w)
     net = _load(branch, trunk)
     tr = helm.Trainer(net, X, batch=64, max_steps=4)
     tr.data(torch.as_tensor(F).cuda(), torch.as_tensor(Y).cuda())
