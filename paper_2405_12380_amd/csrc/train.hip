@@ -266,6 +266,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // accumulation and the epilogue are those of k_gemm_nt, so the values equal
 // the layer-by-layer products bit for bit.
 constexpr int FW_MAXL = 8, FW_ACT = 256 + 8;  // layers; LDS activation row stride (bf16)
+// element (r, c) of the LDS activation, 16-byte pieces permuted per row as in csw
+__device__ __forceinline__ int asw(int r, int c) { return r * FW_ACT + ((((c >> 3) ^ ((r >> 3) & 7)) << 3) | (c & 7)); }
 struct FwdArgs {
   int L, M;
   int Kp[FW_MAXL], N[FW_MAXL];  // Kp[0] = padded input width; Kp[l + 1] = N[l]; all multiples of 64, <= 256
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int cpr = a.Kp[0] / 8;  // 16-byte pieces per input row
     for (int c = t; c < TM * cpr; c += 256) {
       const int r = c / cpr, kq = (c % cpr) * 8;
-      *(bf8*)(act + r * FW_ACT + kq) = m0 + r < a.M ? *(const bf8*)(a.X + (long)(m0 + r) * a.Kp[0] + kq) : zero;
+      *(bf8*)(act + asw(r, kq)) = m0 + r < a.M ? *(const bf8*)(a.X + (long)(m0 + r) * a.Kp[0] + kq) : zero;
     }
   }
   __syncthreads();
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       auto step = [&](const bf8* b, int k) {
         bf8 av[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) av[i] = *(const bf8*)(act + (i * 16 + (l & 15)) * FW_ACT + k + 8 * (l >> 4));
+        for (int i = 0; i < 8; ++i) av[i] = *(const bf8*)(act + asw(i * 16 + (l & 15), k + 8 * (l >> 4)));
 #pragma unroll
         for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -338,7 +340,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           for (int q = 0; q < 4; ++q) {
             float v = acc[i][j][q] + bias;
             if (!last) v = fast_tanh(v);
-            act[(i * 16 + 4 * (l >> 4) + q) * FW_ACT + col] = (__bf16)v;
+            act[asw(i * 16 + 4 * (l >> 4) + q, col)] = (__bf16)v;
           }
       }
     }
@@ -347,13 +349,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int cpr = N / 8;
     for (int c = t; c < TM * cpr; c += 256) {
       const int r = c / cpr, cq = (c % cpr) * 8;
-      if (m0 + r < a.M) *(bf8*)(a.h[li] + (long)(m0 + r) * N + cq) = *(const bf8*)(act + r * FW_ACT + cq);
+      if (m0 + r < a.M) *(bf8*)(a.h[li] + (long)(m0 + r) * N + cq) = *(const bf8*)(act + asw(r, cq));
     }
     for (int c = t; c < N * (TM / 8); c += 256) {
       const int col = c / (TM / 8), rq = (c % (TM / 8)) * 8;
       bf8 v;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = act[(rq + u) * FW_ACT + col];
+      for (int u = 0; u < 8; ++u) v[u] = act[asw(rq + u, col)];
       if (m0 + rq + 8 <= a.M) *(bf8*)(a.hT[li] + (long)col * a.M + m0 + rq) = v;
     }
   }
