@@ -855,9 +855,10 @@ void train_step(don_trainer_s* t, bool update) {
        (float*)t->part.ptr);
   hipLaunchKernelGGL(k_from_dbc, dim3((2 * S * p + 255) / 256), dim3(256), 0, t->st, (const float*)dBc, S, p,
                      (__bf16*)t->bdz[0].ptr, (__bf16*)t->bdzT[0].ptr);
+  // trunk backward captured first (the long chain), the branch's beside it
   fork(t);
-  mlp_bwd(t, t->bl, FbT, S, t->ba, t->bdz, t->bdzT, t->st2, (float*)t->bpart.ptr);
   mlp_bwd(t, t->tl, (const __bf16*)t->XT.ptr, P, t->ta, t->dz, t->dzT, t->st, (float*)t->part.ptr, t->st3);
+  mlp_bwd(t, t->bl, FbT, S, t->ba, t->bdz, t->bdzT, t->st2, (float*)t->bpart.ptr);
   join(t);
   if (update) {
     adam(t, ctr + 1);
