@@ -515,24 +515,31 @@ __global__ __launch_bounds__(256) void k_dU(const float* __restrict__ Ut, const 
   }
 }
 
-// weight matrices inside the flat parameter array (Kp x N row-major at off)
+// weight matrices inside the flat parameter array (Kp x N row-major at off,
+// the N biases at offb); tile0[L] = index of layer L's first 64 x 64 tile
 constexpr int WT_MAX = 16;
 struct WTab {
   int n;
-  long off[WT_MAX];
+  long off[WT_MAX], offb[WT_MAX];
   int Kp[WT_MAX], N[WT_MAX];
+  int tile0[WT_MAX + 1];
 };
 
 // Adam on the flat parameters (fp32), step t = tstep[0] + 1; refreshes the bf16
-// copies: W as stored, and W^T (N x Kp) of every matrix listed in tab
-__global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ w, const float* __restrict__ g,
+// copies W and W^T.  Workgroup b < tile0[n] takes one 64 x 64 tile of a weight
+// matrix (coalesced reads and writes along N; the bf16 tile goes through LDS
+// so W^T is written along Kp, coalesced too); the next n workgroups take one
+// layer's biases each.  The padding between layers in the flat arrays is not
+// touched (its gradient is zero and its values never read).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, __bf16* __restrict__ wb,
                                               __bf16* __restrict__ wt, WTab tab, float lr, float b1, float b2,
                                               float eps, const int* __restrict__ tstep) {
+  __shared__ __bf16 tile[64][66];
   const int t = tstep[0] + 1;
   // bias corrections in fp64: 1 - b2^t in fp32 cancels about 10 bits at b2 = 0.999
   const float c1 = (float)(1.0 - pow((double)b1, (double)t)), c2 = (float)(1.0 - pow((double)b2, (double)t));
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+  auto update = [&](long e) {
     const float ge = g[e];
     const float me = b1 * m[e] + (1.0f - b1) * ge;
     const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
@@ -542,13 +549,26 @@ __global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ w, con
     w[e] = we;
     const __bf16 wh = (__bf16)we;
     wb[e] = wh;
-    for (int L = 0; L < tab.n; ++L) {
-      const long o = e - tab.off[L];
-      if (o >= 0 && o < (long)tab.Kp[L] * tab.N[L]) {
-        const int oi = (int)o;
-        wt[tab.off[L] + (long)(oi % tab.N[L]) * tab.Kp[L] + oi / tab.N[L]] = wh;
-      }
+    return wh;
+  };
+  const int b = blockIdx.x;
+  if (b < tab.tile0[tab.n]) {
+    int L = 0;
+    while (b >= tab.tile0[L + 1]) ++L;
+    const int tl = b - tab.tile0[L], tcn = tab.N[L] / 64;
+    const int r0 = (tl / tcn) * 64, c0 = (tl % tcn) * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      tile[r][c] = update(tab.off[L] + (long)(r0 + r) * tab.N[L] + c0 + c);
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      wt[tab.off[L] + (long)(c0 + c) * tab.Kp[L] + r0 + r] = tile[r][c];
+    }
+  } else {
+    const int L = b - tab.tile0[tab.n];
+    for (int e = threadIdx.x; e < tab.N[L]; e += 256) (void)update(tab.offb[L] + e);
   }
 }
 
@@ -791,13 +811,15 @@ void adam(don_trainer_s* t, const int* tstep) {
   for (auto* L : {&t->bl, &t->tl})
     for (const Layer& y : *L) {
       tab.off[tab.n] = (long)y.offW;
+      tab.offb[tab.n] = (long)y.offb;
       tab.Kp[tab.n] = y.Kp;
       tab.N[tab.n] = y.N;
+      tab.tile0[tab.n + 1] = tab.tile0[tab.n] + (y.Kp / 64) * (y.N / 64);
       ++tab.n;
     }
-  hipLaunchKernelGGL(k_adam, dim3(grid_for((long)t->nparam)), dim3(256), 0, t->st, (long)t->nparam,
-                     (float*)t->master.ptr, (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr,
-                     (__bf16*)t->wbf.ptr, (__bf16*)t->wtb.ptr, tab, t->lr, t->b1, t->b2, t->eps, tstep);
+  hipLaunchKernelGGL(k_adam, dim3(tab.tile0[tab.n] + tab.n), dim3(256), 0, t->st, (float*)t->master.ptr,
+                     (const float*)t->grad.ptr, (float*)t->mom.ptr, (float*)t->var.ptr, (__bf16*)t->wbf.ptr,
+                     (__bf16*)t->wtb.ptr, tab, t->lr, t->b1, t->b2, t->eps, tstep);
 }
 
 // st2 starts after the work queued so far on st; st continues after st2's work
