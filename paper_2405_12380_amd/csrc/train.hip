@@ -764,45 +764,53 @@ void mlp_fwd_fused(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0, in
 }
 
 // backward through one MLP given dZ of its last layer (row-major dz[0], transposed dzT[0])
-// side (optional): stream for the bias gradients, forked from st per layer and
-// joined before the dZ buffer it reads is overwritten (two layers on) and at the end
+// side (optional): stream for each layer's weight and bias gradients, forked
+// from st once the layer's dZ is there, so they run beside the product that
+// forms the next dZ; st waits for a layer's side work before it overwrites the
+// dZ buffers that work reads (two layers on), and at the end
 void mlp_bwd(don_trainer_s* t, std::vector<Layer>& L, const __bf16* H0T, int M, Acts& a, Buffer* dz, Buffer* dzT,
              hipStream_t st, float* part, hipStream_t side = nullptr) {
   const __bf16* wb = (const __bf16*)t->wbf.ptr;
   float* g = (float*)t->grad.ptr;
   const __bf16* h = (const __bf16*)a.h.ptr;
   const __bf16* hT = (const __bf16*)a.hT.ptr;
+  hipStream_t gs = side ? side : st;  // stream of the gradient products
   int cur = 0;
+  bool pending = false;  // side work of the previous layer not yet waited for
   for (int li = (int)L.size() - 1; li >= 0; --li) {
     const Layer& y = L[li];
     const __bf16* inT = li == 0 ? H0T : hT + a.off[li - 1];
     __bf16* d = (__bf16*)dz[cur].ptr;
     __bf16* dT = (__bf16*)dzT[cur].ptr;
-    // db = row sums of dZ^T
     if (side) {
       (void)hipEventRecord(t->ev_rs, st);
       (void)hipStreamWaitEvent(side, t->ev_rs, 0);
-      hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, side, (const __bf16*)dT, (long)M, g + y.offb);
-      (void)hipEventRecord(t->ev_rsj, side);
-    } else {
-      hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, st, (const __bf16*)dT, (long)M, g + y.offb);
     }
+    // db = row sums of dZ^T
+    hipLaunchKernelGGL(k_rowsum, dim3(y.N), dim3(256), 0, gs, (const __bf16*)dT, (long)M, g + y.offb);
     // dW = H^T dZ (Kp x N): A = H^T (Kp x M), B = dZ^T (N x M), reduction over the M rows
     int sp = splits_for(y.Kp, y.N, M, 512);
     while ((size_t)sp * y.Kp * y.N > t->part_floats && sp > 1) --sp;
-    gemm(st, inT, M, dT, M, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, nullptr, 0, sp, part);
+    gemm(gs, inT, M, dT, M, y.Kp, y.N, M, g + y.offW, y.N, EP_F32, nullptr, nullptr, nullptr, 0, sp, part);
     if (li > 0) {
       // dZ_below = (dZ W^T) * (1 - H_below^2): A = dZ (M x N), B = W (Kp x N, n-major = k-contiguous)
       const Layer& z = L[li - 1];
       __bf16* dn = (__bf16*)dz[1 - cur].ptr;
       __bf16* dnT = (__bf16*)dzT[1 - cur].ptr;
-      // dnT held the previous layer's dZ^T, read by its row sums on the side stream
-      if (side) (void)hipStreamWaitEvent(st, t->ev_rsj, 0);
+      // dn / dnT held the previous layer's dZ, read by that layer's side work
+      if (pending) (void)hipStreamWaitEvent(st, t->ev_rsj, 0);
+      if (side) {
+        (void)hipEventRecord(t->ev_rsj, side);  // this layer's side work, waited for one layer on
+        pending = true;
+      }
       gemm(st, d, y.N, wb + y.offW, y.N, M, z.N, y.N, dn, z.N, EP_DTANH_BF16, nullptr, h + a.off[li - 1], dnT, M);
       cur = 1 - cur;
+    } else if (side) {
+      (void)hipEventRecord(t->ev_rsj, side);
+      pending = true;
     }
   }
-  if (side) (void)hipStreamWaitEvent(st, t->ev_rsj, 0);
+  if (pending) (void)hipStreamWaitEvent(st, t->ev_rsj, 0);
 }
 
 // Adam step on st (parameters, moments, both bf16 copies)
