@@ -919,8 +919,11 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
   for (size_t i = 1; i < net->tw.size(); ++i)
     if (net->tw[i] > 256 || net->tw[i] % 64)
       return fail(HELM_E_INVAL, "don_train_create: trunk widths after the input must be multiples of 64, <= 256");
-  if (net->bw.size() + net->tw.size() - 2 > (size_t)WT_MAX || net->tw.size() - 1 > (size_t)FW_MAXL)
-    return fail(HELM_E_INVAL, "don_train_create: too many layers (%d in all, %d in the trunk at most)", WT_MAX, FW_MAXL);
+  // the trunk runs in one fused launch, the branch's layers after its input layer in another
+  if (net->bw.size() + net->tw.size() - 2 > (size_t)WT_MAX || net->tw.size() - 1 > (size_t)FW_MAXL ||
+      net->bw.size() - 2 > (size_t)FW_MAXL)
+    return fail(HELM_E_INVAL, "don_train_create: too many layers (%d in all, %d in the trunk, %d in the branch at most)",
+                WT_MAX, FW_MAXL, FW_MAXL + 1);
   don_trainer_s* t = new don_trainer_s();
   t->S = o->batch;
   t->P = o->n_points;
