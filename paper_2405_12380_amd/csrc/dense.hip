@@ -70,73 +70,73 @@ __global__ __launch_bounds__(256) void k_coord_layer(int dim, int nx, int ny, in
 }
 
 // ---- MFMA GEMM: C = act(A W + b) ---------------------------------------------
-// A: M x K (lda), W: K x N (ldw), C: M x N (ldc), all row-major.  64x64 tile
-// per workgroup of four wavefronts (32x32 each, 2x2 MFMA tiles), K staged in
-// chunks of 32 through LDS (A stored k-major so MFMA operand reads are
-// conflict-free).
-constexpr int GB_M = 64, GB_N = 64, GB_K = 32;
+// A: M x K (lda), W: K x N (ldw), C: M x N (ldc), all row-major.  128 x 128 tile
+// per workgroup of four wavefronts, each 64 x 64 (4 x 4 MFMA tiles, so every
+// operand value read from LDS feeds four products); K staged 16 at a time
+// through LDS (A stored k-major) with the next chunk's loads in registers while
+// the current chunk is multiplied.  Products are accumulated in k order, four
+// at a time.
+constexpr int GB_M = 128, GB_N = 128, GB_K = 16, GB_PAD = 4;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const T* __restrict__ A, size_t lda,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm(int M, int N, int K, const T* __restrict__ A, size_t lda,
                                               const T* __restrict__ W, size_t ldw, const T* __restrict__ bias,
                                               int act, T* __restrict__ C, size_t ldc) {
   using AccT = typename Acc<T>::type;
-  __shared__ T As[GB_K][GB_M + 1];
-  __shared__ T Ws[GB_K][GB_N + 1];
+  __shared__ T As[GB_K][GB_M + GB_PAD];
+  __shared__ T Ws[GB_K][GB_N + GB_PAD];
   const int nbn = (N + GB_N - 1) / GB_N;
   const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
   const int bm = (int)(lb / nbn) * GB_M, bn = (int)(lb % nbn) * GB_N;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  AccT acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += GB_K) {
-    // A tile: 64 rows x 32 k (consecutive threads take consecutive k of a row,
-    // 128 contiguous bytes per 16 threads), 8 elements per thread; all loads
-    // of a thread are issued before the tile is stored
-    {
-      T v[8];
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  AccT acc[4][4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = t + 256 * q, r = e >> 5, kk = e & 31;
-        const int gr = bm + r, gk = k0 + kk;
-        v[q] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : T(0);
-      }
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = t + 256 * q;
-        As[e & 31][e >> 5] = v[q];
-      }
+    for (int b = 0; b < 4; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+  // A chunk: 128 rows x 16 k (16 consecutive threads read 16 consecutive k of a
+  // row); W chunk: 16 k x 128 n (consecutive threads read consecutive n)
+  T va[8], vw[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      const int r = e >> 4, kk = e & 15, gr = bm + r, gk = k0 + kk;
+      va[q] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : T(0);
+      const int wk = e >> 7, c = e & 127, gkw = k0 + wk, gn = bn + c;
+      vw[q] = (gkw < K && gn < N) ? W[(size_t)gkw * ldw + gn] : T(0);
     }
-    // W tile: 32 k x 64 n
-    {
-      T v[8];
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += GB_K) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = t + 256 * q, kk = e >> 6, c = e & 63;
-        const int gk = k0 + kk, gn = bn + c;
-        v[q] = (gk < K && gn < N) ? W[(size_t)gk * ldw + gn] : T(0);
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = t + 256 * q;
-        Ws[e >> 6][e & 63] = v[q];
-      }
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      As[e & 15][e >> 4] = va[q];
+      Ws[e >> 7][e & 127] = vw[q];
     }
     __syncthreads();
+    if (k0 + GB_K < K) load(k0 + GB_K);
 #pragma unroll
     for (int kk = 0; kk < GB_K; kk += 4) {
-      T av[2], bv[2];
-      for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wm + a * 16 + (lane & 15)];
-      for (int b = 0; b < 2; ++b) bv[b] = Ws[kk + (lane >> 4)][wn + b * 16 + (lane & 15)];
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk + (lane >> 4)][wm + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Ws[kk + (lane >> 4)][wn + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gr = bm + wm + a * 16 + acc_row<T>(lane, i);
         const int gc = bn + wn + b * 16 + (lane & 15);
