@@ -206,10 +206,10 @@ __global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __r
   d4 acc[4][4];
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  for (size_t ib = i0; ib < i1; ib += GR_ROWS) {
-    // 16 rows x 128 columns of X and Y: every load of a thread in flight before
-    // the first store to LDS
-    double xv[GR_ROWS * 128 / 256], yv[GR_ROWS * 128 / 256];
+  // 16 rows x 128 columns of X and Y per chunk; the next chunk's loads are in
+  // flight while the current one is multiplied
+  double xv[GR_ROWS * 128 / 256], yv[GR_ROWS * 128 / 256];
+  auto load = [&](size_t ib) {
 #pragma unroll
     for (int q = 0; q < GR_ROWS * 128 / 256; ++q) {
       const int e = t + 256 * q, rr = e >> 7, cc = e & 127;
@@ -219,6 +219,9 @@ __global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __r
       yv[q] = in ? Y[gi * ldy + cc] : 0.0;
       if (in && w) yv[q] *= w[gi];
     }
+  };
+  if (i0 < i1) load(i0);
+  for (size_t ib = i0; ib < i1; ib += GR_ROWS) {
 #pragma unroll
     for (int q = 0; q < GR_ROWS * 128 / 256; ++q) {
       const int e = t + 256 * q, rr = e >> 7, cc = e & 127;
@@ -226,6 +229,7 @@ __global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __r
       Ys[rr][cc] = yv[q];
     }
     __syncthreads();
+    if (ib + GR_ROWS < i1) load(ib + GR_ROWS);
 #pragma unroll
     for (int kk = 0; kk < GR_ROWS; kk += 4) {
       double av[4], bv[4];
