@@ -50,22 +50,39 @@ __device__ __forceinline__ T activate(T x, int act) {
 }
 
 // ---- trunk input layer: h = act(x W + b) at grid-node coordinates --------------
+// Workgroup b takes rows [b rpb, (b + 1) rpb) of the output, threads its
+// columns (W and b of a column loaded once); the node indices of the first
+// row come from one division, the next rows by stepping x, then y, then z.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coord_layer(int dim, int nx, int ny, int nz, size_t row0, size_t nrows,
-                                                     const T* __restrict__ W, const T* __restrict__ b, int N,
-                                                     int act, T* __restrict__ out) {
-  const size_t total = nrows * (size_t)N;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t r = e / N;
-    const int c = (int)(e % N);
-    const size_t p = row0 + r;
-    const int ix = (int)(p % nx);
-    const int iy = (int)((p / nx) % ny);
-    const int iz = (int)(p / ((size_t)nx * ny));
-    const T xc[3] = {T(ix + 1) / T(nx + 1), T(iy + 1) / T(ny + 1), T(iz + 1) / T(nz + 1)};
-    T acc = xc[0] * W[c];
-    for (int d = 1; d < dim; ++d) acc += xc[d] * W[(size_t)d * N + c];
-    out[e] = activate<T>(acc + b[c], act);
+                                                     size_t rpb, const T* __restrict__ W, const T* __restrict__ b,
+                                                     int N, int act, T* __restrict__ out) {
+  const size_t r0 = (size_t)blockIdx.x * rpb, r1 = min(nrows, r0 + rpb);
+  if (r0 >= r1) return;
+  const size_t p0 = row0 + r0;
+  int ix = (int)(p0 % nx), iy = (int)((p0 / nx) % ny), iz = (int)(p0 / ((size_t)nx * ny));
+  for (int c0 = 0; c0 < N; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    const bool on = c < N;
+    const T w0 = on ? W[c] : T(0), w1 = on && dim > 1 ? W[(size_t)N + c] : T(0),
+            w2 = on && dim > 2 ? W[2 * (size_t)N + c] : T(0), bc = on ? b[c] : T(0);
+    int jx = ix, jy = iy, jz = iz;
+    for (size_t r = r0; r < r1; ++r) {
+      if (on) {
+        const T xc[3] = {T(jx + 1) / T(nx + 1), T(jy + 1) / T(ny + 1), T(jz + 1) / T(nz + 1)};
+        T acc = xc[0] * w0;
+        if (dim > 1) acc += xc[1] * w1;
+        if (dim > 2) acc += xc[2] * w2;
+        out[r * (size_t)N + c] = activate<T>(acc + bc, act);
+      }
+      if (++jx == nx) {
+        jx = 0;
+        if (++jy == ny) {
+          jy = 0;
+          ++jz;
+        }
+      }
+    }
   }
 }
 
@@ -553,11 +570,13 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
 template <typename T>
 void coord_layer(int dim, const int n[3], size_t row0, size_t nrows, const T* W, const T* b, int N, int act, T* out,
                  hipStream_t st) {
-  size_t total = nrows * (size_t)N;
-  size_t nb = (total + 255) / 256;
-  if (nb > 16384) nb = 16384;
-  hipLaunchKernelGGL((k_coord_layer<T>), dim3((unsigned)nb), dim3(256), 0, st, dim, n[0], n[1], n[2], row0, nrows, W, b,
-                     N, act, out);
+  // about 4096 workgroups of at least 16 rows each
+  size_t rpb = (nrows + 4095) / 4096;
+  if (rpb < 16) rpb = 16;
+  const size_t nb = (nrows + rpb - 1) / rpb;
+  if (nb == 0) return;
+  hipLaunchKernelGGL((k_coord_layer<T>), dim3((unsigned)nb), dim3(256), 0, st, dim, n[0], n[1], n[2], row0, nrows, rpb,
+                     W, b, N, act, out);
 }
 
 template <typename T>
