@@ -178,16 +178,17 @@ helm_status deeponet_infer(don_net net, helm_op op, int mode, const void* r, dou
 typedef struct don_trainer_s* don_trainer;
 
 typedef struct {
-  int n_points;    /* P: trunk evaluation points per sample (multiple of 32)        */
-  int batch;       /* S: samples per step (32, 64, 96 or 128)                       */
+  int n_points;    /* P: trunk evaluation points per sample (positive multiple of 64) */
+  int batch;       /* S: samples per step (64 or 128)                               */
   int max_steps;   /* capacity: most steps of one don_train_steps / don_train_eval  */
   double lr, beta1, beta2, eps;  /* Adam                                            */
 } don_train_opts;
 
-/* Trainer for `net` (SPLIT_OUTPUT head, tanh; widths after each input multiples
- * of 32 and <= 256).  It keeps fp32 master copies of the net's weights (input
- * widths padded to multiples of 32 with zero rows), their bf16 copies, Adam's
- * moments, and every activation of a step.  X: device array of P x d fp64 trunk
+/* Trainer for `net` (SPLIT_OUTPUT head, tanh; p a multiple of 64; widths after
+ * each input multiples of 64 and <= 256; at most 8 trunk layers, 9 branch
+ * layers and 16 in all; otherwise HELM_E_INVAL).  It keeps fp32 master copies
+ * of the net's weights (input widths padded to multiples of 64 with zero rows),
+ * their bf16 copies (W and W^T), Adam's moments, and every activation of a step.  X: device array of P x d fp64 trunk
  * inputs (node coordinates), copied.  One step on samples idx[0..S):
  *   T = trunk(X), B = branch(F_idx), U_s = T B_s[:p] + i T B_s[p:],
  *   L = mean_s ||U_s - Y_s|| / ||Y_s||, gradients by backpropagation, Adam
