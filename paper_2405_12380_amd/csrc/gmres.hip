@@ -62,10 +62,14 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
   }
   // lane q also keeps entry q + 1 of the column and rotation q in registers:
   // the first 64 steps of the rotation chain read them with v_readlane
-  const double2 bq = l + 1 <= j ? make_double2(h1[2 * (l + 1)] + h2[2 * (l + 1)], h1[2 * (l + 1) + 1] + h2[2 * (l + 1) + 1])
-                                : czero();
-  const double cq = l < j ? cs[l] : 0.0;
-  const double2 sq = l < j ? make_double2(sn[2 * l], sn[2 * l + 1]) : czero();
+  double2 bq = l + 1 <= j ? make_double2(h1[2 * (l + 1)] + h2[2 * (l + 1)], h1[2 * (l + 1) + 1] + h2[2 * (l + 1) + 1])
+                          : czero();
+  double cq = l < j ? cs[l] : 0.0;
+  double2 sq = l < j ? make_double2(sn[2 * l], sn[2 * l + 1]) : czero();
+  // lane 0 alone reads these per-lane values (v_readlane) below: pin them in
+  // every lane's registers here, so that no part of their computation can be
+  // moved into the lane-0 branch
+  __asm__ volatile("" : "+v"(bq.x), "+v"(bq.y), "+v"(cq), "+v"(sq.x), "+v"(sq.y));
   __syncthreads();
   if (l == 0) {
     const double hn = sqrt(ns);
