@@ -11,7 +11,12 @@
 
 namespace helm {
 
-template <typename T> __device__ __forceinline__ double ldq(const T* q, size_t i) { return (double)q[i]; }
+// basis loads are streaming (each Q value is read once per pass and the basis
+// is larger than the caches): non-temporal, so they do not push the Krylov
+// vectors out of L2 and the memory-side cache
+template <typename T> __device__ __forceinline__ double ldq(const T* q, size_t i) {
+  return (double)__builtin_nontemporal_load(q + i);
+}
 
 // part[b][2j + {0,1}] = sum_{i in block b} Q_ij x_i  (complex x, real Q, j < r <= 128)
 // One 256-thread workgroup: rows [i0, i1); out[2j + {0,1}] for j < r.
