@@ -32,6 +32,27 @@ __device__ __forceinline__ void stc_out(float2* p, size_t i, double2 v, bool nt)
   else p[i] = make_float2((float)v.x, (float)v.y);
 }
 
+// Inputs read once per sweep (s, f and the code byte): on grids far larger than
+// the caches these are non-temporal loads, so the caches keep the field whose
+// neighbour rows are read again by the adjacent rows of the tile.
+__device__ __forceinline__ double2 ldc_once(const double2* p, size_t i, bool nt) {
+  if (nt) {
+    const dv2 v = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(p + i));
+    return make_double2(v.x, v.y);
+  }
+  return p[i];
+}
+__device__ __forceinline__ double2 ldc_once(const float2* p, size_t i, bool nt) {
+  if (nt) {
+    const fv2 v = __builtin_nontemporal_load(reinterpret_cast<const fv2*>(p + i));
+    return make_double2((double)v.x, (double)v.y);
+  }
+  return ldc(p, i);
+}
+__device__ __forceinline__ unsigned ldcode(const uint8_t* p, size_t i, bool nt) {
+  return nt ? (unsigned)__builtin_nontemporal_load(p + i) : (unsigned)p[i];
+}
+
 // One workgroup's tile: logical block lb of geometry g.  RESID writes the
 // block's partial of ||r||^2 to *partial.
 template <typename S, int DIM, int MODE>
@@ -62,12 +83,12 @@ __device__ __forceinline__ void stencil_tile(const StencilGeom& g, unsigned lb, 
       if (DIM == 3 && z + 1 < g.nz) znext = ldc(x, p + plane);
       const bool upd = (MODE != ST_RBGS) || (((i + j + z) & 1) == color);
       if (upd) {
-        const unsigned cd = code[p];
+        const unsigned cd = ldcode(code, p, g.nt);
         const double2 xm = ldc(x, p + oxm), xp = ldc(x, p + oxp);
         const double2 ym = ldc(x, p + oym), yp = ldc(x, p + oyp);
-        const double2 sp = ldc(sc, p);
+        const double2 sp = ldc_once(sc, p, g.nt);
         double2 fp = czero();
-        if (MODE != ST_APPLY) fp = ldc(f, p);
+        if (MODE != ST_APPLY) fp = ldc_once(f, p, g.nt);
         double2 ax;
         if (cd & NB_SELF) {
           ax = c;
