@@ -349,14 +349,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int cpr = N / 8;
     for (int c = t; c < TM * cpr; c += 256) {
       const int r = c / cpr, cq = (c % cpr) * 8;
-      if (m0 + r < a.M) *(bf8*)(a.h[li] + (long)(m0 + r) * N + cq) = *(const bf8*)(act + asw(r, cq));
+      if (m0 + r < a.M)  // read again only in the backward pass: streaming stores
+        __builtin_nontemporal_store(*(const bf8*)(act + asw(r, cq)), (bf8*)(a.h[li] + (long)(m0 + r) * N + cq));
     }
     for (int c = t; c < N * (TM / 8); c += 256) {
       const int col = c / (TM / 8), rq = (c % (TM / 8)) * 8;
       bf8 v;
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = act[asw(rq + u, col)];
-      if (m0 + rq + 8 <= a.M) *(bf8*)(a.hT[li] + (long)col * a.M + m0 + rq) = v;
+      if (m0 + rq + 8 <= a.M) __builtin_nontemporal_store(v, (bf8*)(a.hT[li] + (long)col * a.M + m0 + rq));
     }
   }
 }
