@@ -23,6 +23,10 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from emitting packed-fp32 VALU forms
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # fuse a multiply into an add only within one source expression, so
+         # every kernel's rounding follows its source and not the optimizer's
+         # choices (which otherwise change from build to build)
+         "-ffp-contract=on",
          "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
