@@ -127,6 +127,21 @@ def test_rbgs_many_tiles_parity(dtype):
     assert rel_err(to_np(u), ref) <= (1e-12 if dtype == helm.C128 else 2e-6)
 
 
+def test_residual_and_jacobi_full_size_256():
+    """Residual and one damped Jacobi sweep at 256^3, where the stencil kernels
+    stream their once-read inputs (s, f, code) with non-temporal loads and
+    their outputs with non-temporal stores, against the oracle on every node."""
+    n = (256, 256, 256)
+    P, s = _problem(n, 10, helm.C128)
+    op = make_op(helm, P, helm.C128)
+    f = op.field(P["f"])
+    r = to_np(op.residual(f, op.field(P["x"])))
+    assert rel_err(r, op_or.residual(P["x"], P["f"], s, P["mask"]).ravel()) <= 1e-13
+    u = op.field(P["x"])
+    op.relax(helm.JACOBI, 0.6, 1, f, u)
+    assert rel_err(to_np(u), op_or.jacobi_sweep(P["x"], P["f"], s, P["mask"], 0.6).ravel()) <= 1e-13
+
+
 def test_rbgs_full_size_256():
     """One red-black sweep at 256^3, the bandwidth-run size (streaming output
     stores), against the oracle on every node."""
