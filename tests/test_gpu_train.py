@@ -142,3 +142,20 @@ def test_branch_input_mode_matches_oracle_sampling():
     smp = don_or.sample_to(C["f"] / s, (16, 16, 16))
     ref = np.concatenate([smp.real.ravel(), smp.imag.ravel(), [7.5]])
     assert rel_err(x, ref) <= 1e-13
+
+
+def test_trainer_rejects_unsupported_networks():
+    """Trainer creation checks what the fused kernels assume: widths after the
+    input multiples of 64 and <= 256, at most 8 trunk layers, p a multiple of
+    64; each violation is HELM_E_INVAL."""
+    g = np.random.default_rng([77, 9])
+    X = I.node_points(NPTS)
+    branch = I.glorot_mlp([129, 64, 64, 128], g)
+    cases = [I.glorot_mlp([3] + [64] * 9 + [64], g),   # 10 trunk layers
+             I.glorot_mlp([3, 96, 64], g),             # width not a multiple of 64
+             I.glorot_mlp([3, 320, 64], g)]            # width above 256
+    for trunk in cases:
+        net = _load(branch, trunk)
+        with pytest.raises(helm.HelmError) as e:
+            helm.Trainer(net, X, batch=64, max_steps=2)
+        assert e.value.status == helm.E_INVAL
