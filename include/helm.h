@@ -72,16 +72,19 @@ enum { HELM_JACOBI = 0, HELM_RBGS = 1 };
  *   (A x)_p = x_p                                                    (mask_p != 0)
  * where ghost and masked neighbours contribute 0 (the Dirichlet scatterer of
  * §2 is eliminated symmetrically, so A is complex symmetric).
- * ksq, alpha: device arrays of n doubles (k^2 and the sponge damping alpha >= 0).
- * mask: device array of n bytes, nonzero on scatterer nodes.
- * The inputs are copied; the call is synchronous on `stream`.
+ * ksq, alpha: arrays of n doubles (k^2 and the sponge damping alpha >= 0).
+ * mask: array of n bytes, nonzero on scatterer nodes.
+ * The three inputs are host arrays; device arrays are accepted as well (each
+ * copy takes its direction from the pointer).  They are copied and not kept;
+ * the call is synchronous on `stream`.
  * Errors: HELM_E_INVAL for a NULL pointer, dim not 2/3, n[a] < 3, a node count
  * beyond 2^31, or an unknown dtype. */
 helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, const double* alpha,
                        const uint8_t* mask, void* stream, helm_op* out);
 
-/* Replace k^2 (device array of n doubles, same alpha and mask).  Invalidates the
- * cached coarse space.  Synchronous. */
+/* Replace k^2 (device array of n doubles, same alpha and mask): the update of
+ * an optimisation loop, whose k^2 lives on the device.  Invalidates the cached
+ * coarse space.  Synchronous on `stream`. */
 helm_status helm_set_ksq(helm_op op, const double* ksq, void* stream);
 
 /* Release an op and its device memory.  NULL is ignored. */
@@ -101,6 +104,18 @@ size_t helm_size(helm_op op);
  * Synchronous; uses op-owned scratch.  Do not call while a solve on the op is
  * in flight. */
 helm_status helm_tune(helm_op op, int fixed_ty, void* stream, int* ty_out, int* zb_out, double* us_out);
+
+/* Red-black sweep kernel of an op (3D; results are the same bit for bit):
+ *   HELM_RB_AUTO  : the LDS-ring kernel for fields under 2 GiB, else the
+ *                   register-pair kernel (the default);
+ *   HELM_RB_RING  : each input plane staged once in LDS, a ring of planes per
+ *                   column tile (fields under 2 GiB: 32-bit buffer offsets);
+ *   HELM_RB_PAIRS : each lane updates a red/black node pair, red values
+ *                   exchanged through registers and LDS (any size; 2D always).
+ * HELM_E_INVAL for an unknown value, or RING on a 2D op or a field of 2 GiB
+ * or more.  Takes effect for later sweeps. */
+enum { HELM_RB_AUTO = 0, HELM_RB_RING = 1, HELM_RB_PAIRS = 2 };
+helm_status helm_set_rbgs_kernel(helm_op op, int which);
 
 /* y = A x (§2 eq. 1 as above).  x, y: complex fields; must not alias.  Async. */
 helm_status helm_apply(helm_op op, const void* x, void* y, void* stream);
@@ -200,7 +215,8 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
 /* The dataset: n samples; F: device fp32 n x K_b branch inputs (K_b = the
  * net's branch input width), converted to padded bf16 (copied); Y: device
  * complex64 n x P labels, sample-major — kept by pointer, so it must stay
- * valid while the trainer uses it.  Synchronous. */
+ * valid while the trainer uses it.  May be called again to replace the data
+ * (any n); the captured step graphs are then recorded anew.  Synchronous. */
 helm_status don_train_data(don_trainer t, int n, const float* F, const void* Y);
 
 /* `count` Adam steps; step k uses samples idx[k S .. k S + S) (device int array,
@@ -267,6 +283,20 @@ typedef struct {
                       sweeps (net == NULL), or with a network a sweeps, one trunk-basis
                       correction of that level with min(p_used, nodes) columns, b
                       sweeps (a = mg_nu / 2, b = mg_nu - a - 1: 2-1-2 for 5)         */
+  int no_drop;     /* Krylov kinds with a network: 1 = every one of the p_used trunk
+                      columns must be kept; if the QR would drop one (App. C
+                      selection: remaining norm <= tau x the largest), the call
+                      fails with HELM_E_SINGULAR before iterating and u is
+                      untouched.  0 = drop and report the rank in rank_used.
+                      Applies to every coarse space the call builds.           */
+  int fallback_restart; /* META_JACOBI / META_GS: 0 = none; m >= 1 = standalone
+                      GMRES(m) as the fallback of a diverging relaxation: when a
+                      cycle ends with a relative residual that is not finite or
+                      larger than at the end of the previous cycle (or at u0),
+                      u returns to the iterate before that cycle and GMRES(m)
+                      (M = I) runs from it to tol within max_iters Arnoldi steps;
+                      its steps are reported in fallback_iters and its status
+                      is the call's.  Costs one field copy per cycle.            */
 } meta_opts;
 
 typedef struct {
@@ -275,6 +305,8 @@ typedef struct {
   double setup_ms;    /* coarse-space construction time (0 when cached)               */
   double solve_ms;    /* iteration time                                               */
   double cond_Ac_est; /* 1-norm condition estimate of the coarse matrix               */
+  int fallback_iters; /* Arnoldi steps of the GMRES fallback (0: it did not run);
+                         iters keeps counting relaxation sweeps                     */
 } meta_stats;
 
 /* Solve A u = f.
@@ -288,9 +320,12 @@ typedef struct {
  *     most tau times the largest column norm are dropped, tau = 1e-7 (C128),
  *     1e-5 (C64)) and A_c = Q^T A Q (App. C).  With net == NULL, M = I.
  * u holds u0 on entry and the last iterate on exit (also when not converged).
+ * A relaxation kind with fallback_restart >= 1 hands a diverging iteration to
+ * standalone GMRES (see meta_opts.fallback_restart).
  * The coarse space is cached on the op, keyed by (net, p_used, q_fp32, k^2 version).
  * Synchronous.  Returns HELM_OK, HELM_NOT_CONVERGED, HELM_E_BREAKDOWN,
- * HELM_E_NONFINITE, HELM_E_SINGULAR or an argument/HIP error. */
+ * HELM_E_NONFINITE, HELM_E_SINGULAR (a singular A_c, or a dropped column with
+ * no_drop) or an argument/HIP error. */
 helm_status meta_solve(helm_op op, don_net net, const meta_opts* o, const void* f, void* u,
                        meta_stats* st, void* stream);
 

@@ -34,15 +34,25 @@ def sweep(kind, u, f, s, mask, omega):
 
 
 def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, correction=None,
-                    history=None):
+                    history=None, fallback_restart=0):
     """eq. 3 with M1 = nn_every sweeps and M2 = ``correction(r)`` (or none).
 
-    Returns (u, info)."""
+    Krylov fallback (reading: the paper observes plain relaxation diverging on
+    the cube scatterer, §4.1, and keeps Krylov solvers as the reference
+    method): with ``fallback_restart = m >= 1``, a cycle that ends with a
+    relative residual larger than the one before it (that of u0 for the first
+    cycle) or not finite is undone, and standalone GMRES(m) runs from the
+    iterate before it, to ``tol`` within ``max_sweeps`` Arnoldi steps.
+
+    Returns (u, info); info["fallback_iters"] counts the fallback's steps."""
     u = np.array(u0, dtype=np.complex128)
     fn = np.linalg.norm(f)
     count = 0
     ncorr = 0
     status = krylov.NOT_CONVERGED
+    prev = np.linalg.norm(op.residual(u, f, s, mask)) / fn if fn > 0 else 0.0
+    keep = u
+    diverged = False
     while count < max_sweeps:
         cyc = min(nn_every, max_sweeps - count) if nn_every > 0 else max_sweeps - count
         for _ in range(cyc):
@@ -56,14 +66,25 @@ def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, corr
         rel = np.linalg.norm(r) / fn if fn > 0 else 0.0
         if history is not None:
             history.append(rel)
+        if fallback_restart > 0 and not rel <= prev:
+            diverged = True
+            break
         if not np.isfinite(rel):
             status = krylov.NONFINITE
             break
         if rel <= tol:
             status = krylov.CONVERGED
             break
+        keep, prev = u, rel
+    fb_iters = 0
+    if diverged:
+        shape = np.shape(f)
+        u, info = krylov.gmres(lambda v: op.apply(v.reshape(shape), s, mask).ravel(), np.ravel(f),
+                               np.ravel(keep), fallback_restart, tol, max_sweeps)
+        u = u.reshape(shape)
+        status, fb_iters = info["status"], info["iters"]
     rel = np.linalg.norm(op.residual(u, f, s, mask)) / fn if fn > 0 else 0.0
-    return u, dict(status=status, iters=count, rel_res=rel, corrections=ncorr)
+    return u, dict(status=status, iters=count, rel_res=rel, corrections=ncorr, fallback_iters=fb_iters)
 
 
 def deeponet_correction(s_field, mask, T, net):

@@ -157,14 +157,22 @@ helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, con
     helm_destroy(op);
     return hip_fail(e, "hipHostMalloc");
   }
-  if (dt == HELM_C128) build_s<double>(nn, ksq, alpha, op->sc, st);
-  else build_s<float>(nn, ksq, alpha, op->sc, st);
-  e = hipMemcpyAsync(op->mask, mask, nn, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(op->alpha, alpha, nn * sizeof(double), hipMemcpyDeviceToDevice, st);
+  // inputs in host (the documented case) or device memory: each copy takes its
+  // direction from the pointer; k^2 is staged in the op's field scratch
+  if ((s = op->tmp.ensure(nn * op_esz(op)))) {
+    helm_destroy(op);
+    return s;
+  }
+  double* ksq_dev = (double*)op->tmp.ptr;
+  e = hipMemcpyAsync(op->mask, mask, nn, hipMemcpyDefault, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(op->alpha, alpha, nn * sizeof(double), hipMemcpyDefault, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(ksq_dev, ksq, nn * sizeof(double), hipMemcpyDefault, st);
   if (e != hipSuccess) {
     helm_destroy(op);
-    return hip_fail(e, "helm_setup: mask copy");
+    return hip_fail(e, "helm_setup: input copy");
   }
+  if (dt == HELM_C128) build_s<double>(nn, ksq_dev, op->alpha, op->sc, st);
+  else build_s<float>(nn, ksq_dev, op->alpha, op->sc, st);
   build_codes(op->geom, op->mask, op->code, st);
   if ((s = sync_stream(st, "helm_setup"))) {
     helm_destroy(op);
@@ -284,6 +292,19 @@ helm_status helm_tune(helm_op op, int fixed_ty, void* stream, int* ty_out, int* 
   if (ty_out) *ty_out = best.ty;
   if (zb_out) *zb_out = best.zb;
   if (us_out) *us_out = best_us;
+  return HELM_OK;
+}
+
+helm_status helm_set_rbgs_kernel(helm_op op, int which) {
+  if (!op) return fail(HELM_E_INVAL, "helm_set_rbgs_kernel: NULL op");
+  if (which < HELM_RB_AUTO || which > HELM_RB_PAIRS)
+    return fail(HELM_E_INVAL, "helm_set_rbgs_kernel: unknown kernel %d", which);
+  if (which == HELM_RB_RING) {
+    if (op->dim != 3) return fail(HELM_E_INVAL, "helm_set_rbgs_kernel: the ring kernel is 3D only");
+    if ((double)op->nn * op_esz(op) >= 2147483648.0)
+      return fail(HELM_E_INVAL, "helm_set_rbgs_kernel: the ring kernel needs fields under 2 GiB");
+  }
+  op->geom.rb = which;
   return HELM_OK;
 }
 

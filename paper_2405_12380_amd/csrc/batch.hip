@@ -561,7 +561,7 @@ helm_status batch_drive(int np, helm_op_s* const* ops, don_s* net, const meta_op
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, user_st);
-    s = coarse_ensure(ops[i], net, o->p_used, o->q_fp32 != 0, user_st);
+    s = coarse_ensure(ops[i], net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, user_st);
     (void)hipEventRecord(e1, user_st);
     if (!s) s = sync_stream(user_st, "meta_solve_batch: coarse setup");
     float ms = 0.f;

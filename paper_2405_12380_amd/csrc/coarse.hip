@@ -490,18 +490,22 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   return launch_check("coarse setup");
 }
 
-helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, hipStream_t st) {
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bool no_drop, hipStream_t st) {
   Coarse& c = op->coarse;
   const bool want_f32 = q_fp32 || op->dt == HELM_C64;
-  if (c.valid && c.net_serial == don_serial(net) && c.p_used == p_used && c.ksq_version == op->ksq_version &&
-      c.q_f32 == want_f32)
-    return HELM_OK;
-  c.valid = false;
-  helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, q_fp32, st)
-                                      : coarse_build<float, float>(op, net, p_used, true, st);
-  if (s) return s;
-  c.net_serial = don_serial(net);
-  c.ksq_version = op->ksq_version;
+  if (!(c.valid && c.net_serial == don_serial(net) && c.p_used == p_used && c.ksq_version == op->ksq_version &&
+        c.q_f32 == want_f32)) {
+    c.valid = false;
+    helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, q_fp32, st)
+                                        : coarse_build<float, float>(op, net, p_used, true, st);
+    if (s) return s;
+    c.net_serial = don_serial(net);
+    c.ksq_version = op->ksq_version;
+  }
+  // the space stays cached either way: a later call that allows dropping uses it
+  if (no_drop && c.rank < p_used)
+    return fail(HELM_E_SINGULAR, "coarse: %d of the %d trunk columns are numerically dependent and no_drop is set",
+                p_used - c.rank, p_used);
   return HELM_OK;
 }
 

@@ -1,9 +1,9 @@
 // DeepONet inference (App. B architecture; App. C trunk matrix).
 //
 // Trunk: the coordinate input layer is evaluated directly from node indices
-// (no coordinate array), the hidden and output layers are MFMA GEMMs with fused
-// bias + activation, row-chunked so the activations stay within a bounded
-// buffer at any grid size.  The result T (n x p) is what the trunk-basis
+// (no coordinate array), the hidden and output layers are fp64 MFMA GEMMs with
+// fused bias + activation (both dtypes), row-chunked so the activations stay
+// within a bounded buffer at any grid size.  The result T (n x p) is what the trunk-basis
 // coarse space and the output synthesis consume.
 //
 // Full correction du = s N(r / s):  ||r|| (two-stage reduction) -> branch input
@@ -12,6 +12,7 @@
 // c = b_re + i b_im -> du_i = s sum_j T_ij c_j, zero on scatterer nodes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <cmath>
@@ -126,31 +127,54 @@ __global__ void k_coef(int p, int split_input, const T* __restrict__ b, double* 
   c[2 * j + 1] = split_input ? (double)b[p + j] : (double)b[p + j];
 }
 
+// fp64 trunk rows rounded once to the stored fp32 trunk matrix (C64)
+__global__ void k_narrow(size_t cnt, const double* __restrict__ src, float* __restrict__ dst) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
 // ---- drivers -------------------------------------------------------------------------
+// The trunk matrix is evaluated in fp64 arithmetic for both dtypes (a C64
+// network's fp32 weights widened exactly): the basis of App. C is set-up
+// algebra, and an fp32 evaluation's few-ulp errors per layer (about 5e-7 of T
+// at the 3D trunk) reach the meta-solver's iterate amplified.  A C64 trunk
+// matrix is rounded to fp32 once, as it is stored.
 template <typename T>
 static helm_status trunk_eval(don_s* net, helm_op_s* op, T* out, hipStream_t st) {
+  constexpr bool wide = sizeof(T) == sizeof(double);
   const size_t n = op->nn;
   const int L = (int)net->tw.size() - 1;
   int maxw = 1;
   for (int w : net->tw) maxw = w > maxw ? w : maxw;
   const size_t chunk = n < (size_t)262144 ? n : (size_t)262144;
   helm_status s;
-  if ((s = net->tact0.ensure(chunk * maxw * sizeof(T))) || (s = net->tact1.ensure(chunk * maxw * sizeof(T))))
+  if ((s = net->tact0.ensure(chunk * maxw * sizeof(double))) ||
+      (s = net->tact1.ensure(chunk * maxw * sizeof(double))))
     return s;
+  const std::vector<void*>& W = wide ? net->tW : net->tW64;
+  const std::vector<void*>& B = wide ? net->tB : net->tB64;
   const int act = map_act(net->act);
+  const int p = net->p;
   for (size_t r0 = 0; r0 < n; r0 += chunk) {
     const size_t rc = n - r0 < chunk ? n - r0 : chunk;
-    T* h[2] = {(T*)net->tact0.ptr, (T*)net->tact1.ptr};
-    T* dst = L == 1 ? out + r0 * net->p : h[0];
-    coord_layer<T>(op->dim, op->n, r0, rc, (const T*)net->tW[0], (const T*)net->tB[0], net->tw[1],
-                   L == 1 ? ACT_NONE : act, dst, st);
+    double* h[2] = {(double*)net->tact0.ptr, (double*)net->tact1.ptr};
+    // the last layer writes the stored matrix directly (C128) or a scratch chunk
+    auto last_out = [&](int slot) { return wide ? (double*)(void*)(out + r0 * p) : h[slot]; };
+    double* o = L == 1 ? last_out(1) : h[0];
+    coord_layer<double>(op->dim, op->n, r0, rc, (const double*)W[0], (const double*)B[0], net->tw[1],
+                        L == 1 ? ACT_NONE : act, o, st);
     int cur = 0;
     for (int l = 1; l < L; ++l) {
       const bool last = l == L - 1;
-      T* o = last ? out + r0 * net->p : h[1 - cur];
-      gemm<T>((int)rc, net->tw[l + 1], net->tw[l], h[cur], net->tw[l], (const T*)net->tW[l], net->tw[l + 1],
-              (const T*)net->tB[l], last ? ACT_NONE : act, o, net->tw[l + 1], st);
+      o = last ? last_out(1 - cur) : h[1 - cur];
+      gemm<double>((int)rc, net->tw[l + 1], net->tw[l], h[cur], net->tw[l], (const double*)W[l], net->tw[l + 1],
+                   (const double*)B[l], last ? ACT_NONE : act, o, net->tw[l + 1], st);
       cur = 1 - cur;
+    }
+    if (!wide) {
+      const size_t cnt = rc * (size_t)p;
+      hipLaunchKernelGGL(k_narrow, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 16384)), dim3(256), 0, st, cnt,
+                         o, (float*)(void*)(out + r0 * p));
     }
   }
   return launch_check("trunk");
@@ -312,6 +336,16 @@ helm_status deeponet_load(helm_dtype dt, const don_desc* d, const double* const*
     if (e != hipSuccess) return hip_fail(e, "deeponet_load: upload");
     return HELM_OK;
   };
+  // fp64 copy of the fp32-rounded values (the trunk of a C64 network)
+  auto upload_widened = [&](const double* src, size_t cnt, void** dst) -> helm_status {
+    helm_status s = dalloc(dst, cnt * sizeof(double));
+    if (s) return s;
+    std::vector<double> tmp(cnt);
+    for (size_t i = 0; i < cnt; ++i) tmp[i] = (double)(float)src[i];
+    hipError_t e = hipMemcpy(*dst, tmp.data(), cnt * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "deeponet_load: upload");
+    return HELM_OK;
+  };
   int wi = 0;
   helm_status s = HELM_OK;
   for (int l = 0; l + 1 < d->n_branch && !s; ++l) {
@@ -323,10 +357,20 @@ helm_status deeponet_load(helm_dtype dt, const don_desc* d, const double* const*
   }
   for (int l = 0; l + 1 < d->n_trunk && !s; ++l) {
     void *W = nullptr, *b = nullptr;
-    s = upload(Wb[wi++], (size_t)d->trunk_w[l] * d->trunk_w[l + 1], &W);
-    if (!s) s = upload(Wb[wi++], (size_t)d->trunk_w[l + 1], &b);
+    const double* srcW = Wb[wi++];
+    const double* srcb = Wb[wi++];
+    const size_t cW = (size_t)d->trunk_w[l] * d->trunk_w[l + 1], cb = (size_t)d->trunk_w[l + 1];
+    s = upload(srcW, cW, &W);
+    if (!s) s = upload(srcb, cb, &b);
     net->tW.push_back(W);
     net->tB.push_back(b);
+    if (!s && dt == HELM_C64) {
+      void *W64 = nullptr, *b64 = nullptr;
+      s = upload_widened(srcW, cW, &W64);
+      if (!s) s = upload_widened(srcb, cb, &b64);
+      net->tW64.push_back(W64);
+      net->tB64.push_back(b64);
+    }
   }
   if (s) {
     deeponet_free(net);
@@ -342,6 +386,8 @@ void deeponet_free(don_net net) {
   for (void* p : net->bB) dfree(p);
   for (void* p : net->tW) dfree(p);
   for (void* p : net->tB) dfree(p);
+  for (void* p : net->tW64) dfree(p);
+  for (void* p : net->tB64) dfree(p);
   net->act0.release();
   net->act1.release();
   net->tact0.release();

@@ -11,14 +11,17 @@ enum { ACT_NONE = -1, ACT_TANH = 0, ACT_RELU = 1, ACT_LEAKY = 2 };
 
 // h[r][c] = act(sum_d x_{row0+r}[d] W[d][c] + b[c]) with x_p the coordinates of
 // grid node p (x-fastest numbering, (i+1)/(n+1) per axis), r < nrows, c < N
+// (instantiated for double)
 template <typename T>
 void coord_layer(int dim, const int n[3], size_t row0, size_t nrows, const T* W, const T* b, int N, int act, T* out,
                  hipStream_t st);
-// C = act(A W + bias) (MFMA); bias may be NULL; act = ACT_NONE for linear
+// C = act(A W + bias) (fp64 MFMA; instantiated for double); bias may be NULL;
+// act = ACT_NONE for linear
 template <typename T>
 void gemm(int M, int N, int K, const T* A, size_t lda, const T* W, size_t ldw, const T* bias, int act, T* C,
           size_t ldc, hipStream_t st);
-// y[b][n] = act(sum_k x[b][k] W[k][n] + bias[n]) for a batch B <= 4 (split-K);
+// y[b][n] = act(sum_k x[b][k] W[k][n] + bias[n]) for a batch B <= 4 (split-K,
+// fp64 accumulation, bias and activation; y rounded once to T);
 // part needs small_ksplit(K) * B * N doubles
 int small_ksplit(int K);
 template <typename T>

@@ -5,32 +5,21 @@
 // dropping, triangular inverse, Gauss-Jordan inverse of the complex coarse
 // matrix).
 //
-// MFMA: v_mfma_f64_16x16x4f64 (fp64 path) and v_mfma_f32_16x16x4f32 (fp32
-// path).  For both, lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of
-// a 16x4 by 4x16 product.  The accumulator layouts differ: the f32 form holds
-// rows 4 (l / 16) + i in its four registers, the f64 form rows (l / 16) + 4 i;
-// both hold column l % 16.
+// MFMA: v_mfma_f64_16x16x4f64.  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16x4 by 4x16 product; its four accumulator registers
+// hold rows (l / 16) + 4 i of column l % 16.  Both dtypes evaluate the network
+// layers in fp64 (a C64 network's fp32 weights widened exactly).
 #include "common.h"
 #include "dense.h"
 
 namespace helm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Acc;
-template <> struct Acc<double> { using type = d4; };
-template <> struct Acc<float> { using type = f4; };
 
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-template <typename T> __device__ __forceinline__ int acc_row(int lane, int i);
-template <> __device__ __forceinline__ int acc_row<double>(int lane, int i) { return (lane >> 4) + 4 * i; }
-template <> __device__ __forceinline__ int acc_row<float>(int lane, int i) { return 4 * (lane >> 4) + i; }
+__device__ __forceinline__ int acc_row(int lane, int i) { return (lane >> 4) + 4 * i; }
 
 // tanh for the fp64 layers from expm1: t = e^{2|x|} - 1, tanh|x| = t / (t + 2),
 // sign restored (no cancellation near 0; within 5e-16 of the library tanh and
@@ -39,7 +28,6 @@ __device__ __forceinline__ double tanh_fast(double x) {
   const double t = expm1(2.0 * fabs(x));
   return copysign(t / (t + 2.0), x);
 }
-__device__ __forceinline__ float tanh_fast(float x) { return tanhf(x); }
 
 template <typename T>
 __device__ __forceinline__ T activate(T x, int act) {
@@ -99,7 +87,6 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm(int M, int N, int K, const T* __restrict__ A, size_t lda,
                                               const T* __restrict__ W, size_t ldw, const T* __restrict__ bias,
                                               int act, T* __restrict__ C, size_t ldc) {
-  using AccT = typename Acc<T>::type;
   __shared__ T As[GB_K][GB_M + GB_PAD];
   __shared__ T Ws[GB_K][GB_N + GB_PAD];
   const int nbn = (N + GB_N - 1) / GB_N;
@@ -107,11 +94,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int bm = (int)(lb / nbn) * GB_M, bn = (int)(lb % nbn) * GB_N;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  AccT acc[4][4];
+  d4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
   // A chunk: 128 rows x 16 k (16 consecutive threads read 16 consecutive k of a
   // row); W chunk: 16 k x 128 n (consecutive threads read consecutive n)
   T va[8], vw[8];
@@ -155,7 +142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gr = bm + wm + a * 16 + acc_row<T>(lane, i);
+        const int gr = bm + wm + a * 16 + acc_row(lane, i);
         const int gc = bn + wn + b * 16 + (lane & 15);
         if (gr < M && gc < N) {
           T v = acc[a][b][i];
@@ -200,9 +187,8 @@ __global__ void k_small_final(int B, int N, int ksplit, const double* __restrict
   const int b = e / N, n = e % N;
   double acc = 0.0;
   for (int ks = 0; ks < ksplit; ++ks) acc += part[((size_t)ks * B + b) * N + n];
-  T v = (T)acc;
-  if (bias) v += bias[n];
-  y[e] = activate<T>(v, act);
+  if (bias) acc += (double)bias[n];
+  y[e] = (T)activate<double>(acc, act);  // fp64 arithmetic, rounded once to the stored type
 }
 
 // ---- tall-skinny weighted Gram: C = X^T diag(w) Y (X, Y: n x r, r <= 128) -------
@@ -261,7 +247,7 @@ __global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __r
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b)
       for (int i = 0; i < 4; ++i) {
-        const int ra = wa + a * 16 + acc_row<double>(lane, i);
+        const int ra = wa + a * 16 + acc_row(lane, i);
         const int cb = wb + b * 16 + (lane & 15);
         if (ra < r && cb < r) out[(size_t)ra * r + cb] = acc[a][b][i];
       }
@@ -644,12 +630,8 @@ void gj_inverse(int r, const double* A, double* work, double* Ainv, int* info, d
 
 template void coord_layer<double>(int, const int*, size_t, size_t, const double*, const double*, int, int, double*,
                                   hipStream_t);
-template void coord_layer<float>(int, const int*, size_t, size_t, const float*, const float*, int, int, float*,
-                                 hipStream_t);
 template void gemm<double>(int, int, int, const double*, size_t, const double*, size_t, const double*, int, double*,
                            size_t, hipStream_t);
-template void gemm<float>(int, int, int, const float*, size_t, const float*, size_t, const float*, int, float*, size_t,
-                          hipStream_t);
 template void dense_small<double>(int, int, int, const double*, const double*, const double*, int, double*, double*,
                                   hipStream_t);
 template void dense_small<float>(int, int, int, const float*, const float*, const float*, int, float*, double*,

@@ -12,6 +12,7 @@ struct StencilGeom {
   int nx, ny, nz, dim, zb;
   int ty;    // tile height (rows per workgroup): 4 or 8
   bool nt;   // non-temporal output stores (grids much larger than the caches)
+  int rb;    // 3D red-black kernel: 0 = the LDS ring below 2 GiB per field, 1 = ring, 2 = register pairs
   double ih2[3];  // 1/h_a^2 (0 for absent axes)
   double dsum;    // sum_a 2/h_a^2, the Laplacian's diagonal
 };

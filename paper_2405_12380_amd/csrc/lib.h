@@ -75,12 +75,16 @@ struct helm_op_s {
 
 // A loaded DeepONet (deeponet.hip): widths, weights on the device in the
 // dtype's real precision (W_l is in x out, row-major), and inference scratch.
+// A C64 network also keeps its trunk weights widened to fp64 (tW64, tB64:
+// the same values as the fp32 copies), since the trunk matrix is evaluated in
+// fp64 arithmetic for both dtypes.
 struct don_s {
   helm_dtype dt = HELM_C128;
   int act = DON_TANH, head = DON_SPLIT_OUTPUT, p = 0, k_input = 0;
   int bgrid[3] = {1, 1, 1};
   std::vector<int> bw, tw;
   std::vector<void*> bW, bB, tW, tB;
+  std::vector<void*> tW64, tB64;
   int serial = 0;
   helm::Buffer act0, act1;  // branch activations (small) and trunk chunks
   helm::Buffer tact0, tact1;
@@ -101,11 +105,13 @@ int don_serial(const don_s* net);
 void don_touch(don_s* net);
 // du = s N(r/s), masked (DON_FULL); async on st
 helm_status don_full(don_s* net, helm_op_s* op, const void* r, double k, void* du, hipStream_t st);
-// T = trunk(node coordinates) into `out` (n x p real, dtype precision); async
+// T = trunk(node coordinates) into `out` (n x p real, dtype precision), fp64
+// arithmetic for both dtypes; async
 helm_status don_trunk(don_s* net, helm_op_s* op, void* out, hipStream_t st);
 
 // ---- coarse space (coarse.hip) ----
-helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, hipStream_t st);
+// Build or reuse the coarse space; HELM_E_SINGULAR if no_drop and a column was dropped.
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bool no_drop, hipStream_t st);
 template <typename S>
 helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st);  // z += Q A_c^-1 Q^T r1
 void coarse_release(helm_op_s* op);

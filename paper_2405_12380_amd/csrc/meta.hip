@@ -1,7 +1,8 @@
 // Solver drivers and the meta-solver C ABI.
 //
 //  * relaxation meta-solver (eq. 3): cycles of n_r smoother sweeps followed by
-//    one DeepONet correction of the residual;
+//    one DeepONet correction of the residual, optionally handing a diverging
+//    iteration to standalone GMRES;
 //  * restarted GMRES(m) with CGS2 and BiCGStab, right-preconditioned, stopping
 //    on the true relative residual (§3.1.2);
 //  * the Krylov preconditioner M(r) = eq. 3 from z = 0 with the linear
@@ -442,17 +443,28 @@ template <typename S>
 helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_stats* out, hipStream_t st) {
   const meta_opts* o = c.o;
   const size_t n = op->nn, esz = op_esz(op);
-  helm_status s = op->ws.ensure(Carve::need(n * esz) * 2);
+  // Krylov fallback: the iterate before each cycle is kept, so a cycle whose
+  // residual grows (or is not finite) can be undone and handed to GMRES
+  const bool fb = o->fallback_restart > 0;
+  helm_status s = op->ws.ensure(Carve::need(n * esz) * (fb ? 3 : 2));
   if (s) return s;
   Carve cv(op->ws.ptr);
   void* r = cv.take(n * esz);
   void* du = cv.take(n * esz);
+  void* keep = fb ? cv.take(n * esz) : nullptr;
   const int kind = o->kind == META_JACOBI ? HELM_JACOBI : HELM_RBGS;
   double fn;
   if ((s = vec_norm<S>(op, f, &fn, st))) return s;
   int count = 0, ncorr = 0, hlen = 0, matvecs = 0;
   helm_status status = HELM_NOT_CONVERGED;
-  double rn = 0.0;
+  double rn = 0.0, prev = 0.0;
+  if (fb) {
+    if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
+    matvecs++;
+    prev = fn > 0 ? rn / fn : rn;
+    copy_vec<S>(n, u, keep, st);
+  }
+  bool diverged = false;
   while (count < o->max_iters) {
     int cyc = o->nn_every > 0 ? o->nn_every : o->max_iters - count;
     if (cyc > o->max_iters - count) cyc = o->max_iters - count;
@@ -470,6 +482,10 @@ helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, 
     matvecs++;
     const double rel = fn > 0 ? rn / fn : rn;
     if (o->history && hlen <= o->max_iters) o->history[hlen++] = rel;
+    if (fb && !(rel <= prev)) {  // grew, or not finite
+      diverged = true;
+      break;
+    }
     if (!std::isfinite(rel)) {
       status = HELM_E_NONFINITE;
       break;
@@ -478,6 +494,33 @@ helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, 
       status = HELM_OK;
       break;
     }
+    if (fb) {
+      copy_vec<S>(n, u, keep, st);
+      prev = rel;
+    }
+  }
+  if (diverged) {
+    // standalone GMRES(fallback_restart), M = I, from the iterate before the
+    // cycle that grew; its workspace may replace op->ws, so wait for the copy
+    copy_vec<S>(n, keep, u, st);
+    if ((s = sync_stream(st, "relaxation fallback"))) return s;
+    meta_opts g = *o;
+    g.kind = META_GMRES;
+    g.restart = o->fallback_restart;
+    g.history = nullptr;
+    g.mg_levels = 0;
+    MetaCtx gc{&g, nullptr, false, nullptr};
+    meta_stats gst;
+    std::memset(&gst, 0, sizeof gst);
+    status = gmres_drive<S>(op, gc, f, u, &gst, st);
+    out->iters = count;
+    out->matvecs = matvecs + gst.matvecs;
+    out->precond_apps = ncorr;
+    out->rel_res = gst.rel_res;
+    out->history_len = hlen;
+    out->fallback_iters = gst.iters;
+    out->converged = status == HELM_OK;
+    return status;
   }
   if (count == 0) {
     if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
@@ -503,7 +546,8 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
   (void)hipEventCreate(&e2);
   (void)hipEventRecord(e0, st);
   if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
-    if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, st))) {
+    if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, st))) {
+      if (op->coarse.valid) st_out->rank_used = op->coarse.rank;
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       (void)hipEventDestroy(e2);
@@ -547,6 +591,8 @@ helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o) {
     return fail(HELM_E_INVAL, "meta: unknown smoother %d", o->smoother);
   if (o->n_r < 0) return fail(HELM_E_INVAL, "meta: n_r < 0");
   if (!std::isfinite(o->omega)) return fail(HELM_E_INVAL, "meta: omega not finite");
+  if (o->fallback_restart < 0 || o->fallback_restart > 1000)
+    return fail(HELM_E_INVAL, "meta: fallback_restart must be in [0, 1000]");
   if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
     helm_status s = check_net_for_op(net, op, o->p_used);
     if (s) return s;
@@ -610,7 +656,7 @@ helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void
   helm_status s = check_opts(op, net, o);
   if (s) return s;
   hipStream_t hs = (hipStream_t)stream;
-  if (net && (s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, hs))) return s;
+  if (net && (s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, hs))) return s;
   if (o->mg_levels > 0 && (s = mg_ensure(op, net, o, hs))) return s;
   const size_t fld = op->nn * op_esz(op);
   if ((s = op->ws.ensure(fld))) return s;
@@ -626,7 +672,7 @@ helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* r
   helm_status s = check_net_for_op(net, op, o->p_used);
   if (s) return s;
   hipStream_t hs = (hipStream_t)stream;
-  if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, hs))) return s;
+  if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, hs))) return s;
   const int r = op->coarse.rank;
   *rank = r;
   if (Ac) {

@@ -375,7 +375,7 @@ helm_status mg_ensure(helm_op_s* op, don_s* net, const meta_opts* o, hipStream_t
   if (net)
     for (int l = 0; l < m->levels; ++l) {
       const int pu = (size_t)o->p_used < m->ops[l]->nn ? o->p_used : (int)m->ops[l]->nn;
-      if ((s = coarse_ensure(m->ops[l], net, pu, o->q_fp32 != 0, st))) {
+      if ((s = coarse_ensure(m->ops[l], net, pu, o->q_fp32 != 0, o->no_drop != 0, st))) {
         mg_release(op);
         return s;
       }

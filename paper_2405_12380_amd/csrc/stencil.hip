@@ -102,7 +102,16 @@ __device__ __forceinline__ double2 relax_upd(const StencilGeom& g, unsigned cd, 
   return make_double2(c.x + omega * qq.x, c.y + omega * qq.y);
 }
 
-// the relaxation update at node (i, j, z) from the values of x alone (a red node)
+// a value rounded to the storage precision (what a pass through memory gives)
+template <typename S>
+__device__ __forceinline__ double2 rnd_store(double2 v) {
+  if (sizeof(S) == sizeof(float)) return make_double2((double)(float)v.x, (double)(float)v.y);
+  return v;
+}
+
+// the relaxation update at node (i, j, z) from the values of x alone (a red
+// node), rounded to the storage precision: the black updates read red values
+// as if the two colours were separate passes through memory
 template <typename S, int DIM>
 __device__ __forceinline__ double2 red_at(const StencilGeom& g, const cplx_t<S>* __restrict__ sc,
                                           const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ x,
@@ -117,8 +126,8 @@ __device__ __forceinline__ double2 red_at(const StencilGeom& g, const cplx_t<S>*
     if (z > 0) q = ldc(x, p - plane);
     if (z + 1 < g.nz) w = ldc(x, p + plane);
   }
-  return relax_upd<S>(g, cd, ldc(x, p), ldc(x, p + oxm), ldc(x, p + oxp), ldc(x, p + oym), ldc(x, p + oyp), q, w,
-                      ldc(sc, p), ldc(f, p), omega, DIM == 3);
+  return rnd_store<S>(relax_upd<S>(g, cd, ldc(x, p), ldc(x, p + oxm), ldc(x, p + oxp), ldc(x, p + oym),
+                                   ldc(x, p + oyp), q, w, ldc(sc, p), ldc(f, p), omega, DIM == 3));
 }
 
 // Thread (tx, ty) owns the node pair x = 2 tx, 2 tx + 1 of row j in a 128 x ty
@@ -248,12 +257,6 @@ template <bool NT>
 __device__ __forceinline__ void rb_st(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v, float2*) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rb_u2, make_float2((float)v.x, (float)v.y)), r, off, 0,
                                         NT ? 2 : 0);
-}
-
-template <typename S>
-__device__ __forceinline__ double2 rnd_store(double2 v) {
-  if (sizeof(S) == sizeof(float)) return make_double2((double)(float)v.x, (double)(float)v.y);
-  return v;
 }
 
 struct NodeIn {
@@ -434,6 +437,7 @@ StencilGeom make_geom(int dim, const int n[3], int zb) {
   g.ny = n[1];
   g.nz = dim == 3 ? n[2] : 1;
   g.dim = dim;
+  g.rb = 0;
   g.dsum = 0.0;
   for (int a = 0; a < 3; ++a) g.ih2[a] = 0.0;
   for (int a = 0; a < dim; ++a) {
@@ -511,7 +515,9 @@ void stencil_rbgs_fused(const StencilGeom& g0, const void* sc, const uint8_t* co
   const int nb = ((g.nx + 127) / 128) * ((g.ny + g.ty - 1) / g.ty) * ((g.nz + g.zb - 1) / g.zb);
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   kprof_begin(KP_STENCIL, st);
-  if (g.dim == 3 && n * esz < 2147483648.0) {
+  // the ring kernel addresses each buffer with 32-bit offsets (fields under 2 GiB)
+  const bool ring = g.dim == 3 && (g.rb == 1 || (g.rb == 0 && n * esz < 2147483648.0));
+  if (ring) {
     // planes per workgroup: about 1024 workgroups, marches of 2 .. 32 planes
     const long tiles = (long)((g.nx + RB_TX - 1) / RB_TX) * ((g.ny + RB_TY - 1) / RB_TY);
     int zb = (int)(tiles * g.nz / 1024);

@@ -1058,8 +1058,17 @@ helm_status don_train_create(don_net net, const don_train_opts* o, const double*
 helm_status don_train_data(don_trainer t, int n, const float* F, const void* Y) {
   if (!t || !F || !Y || n < 1) return fail(HELM_E_INVAL, "don_train_data: bad argument");
   const Layer& b0 = t->bl[0];
-  helm_status s = t->Fdata.ensure((size_t)2 * n * b0.Kp);
+  helm_status s = sync(t, "don_train_data");  // no step may still read the old data
   if (s) return s;
+  const void* oldF = t->Fdata.ptr;
+  if ((s = t->Fdata.ensure((size_t)2 * n * b0.Kp))) return s;
+  // the captured step graphs hold the data pointers as kernel arguments:
+  // record them again when either moved
+  if (t->Fdata.ptr != oldF || (const float2*)Y != t->Y) {
+    if (t->step_exec) (void)hipGraphExecDestroy(t->step_exec);
+    if (t->multi_exec) (void)hipGraphExecDestroy(t->multi_exec);
+    t->step_exec = t->multi_exec = nullptr;
+  }
   hipLaunchKernelGGL(k_pad_rows, dim3(grid_for((long)n * b0.Kp)), dim3(256), 0, t->st, (long)n, b0.K, F, b0.Kp,
                      (__bf16*)t->Fdata.ptr, (__bf16*)nullptr);
   t->Y = (const float2*)Y;
@@ -1197,6 +1206,13 @@ helm_status don_train_export(don_trainer t, don_net net, void* stream) {
   };
   put(t->bl, net->bW, net->bB);
   put(t->tl, net->tW, net->tB);
+  if (net->dt == HELM_C64)  // the fp64 trunk copies hold the same (fp32) values
+    for (size_t i = 0; i < t->tl.size(); ++i) {
+      const Layer& y = t->tl[i];
+      hipLaunchKernelGGL(k_cvt_back<double>, dim3(grid_for((long)y.K * y.N)), dim3(256), 0, t->st, y.K, y.N,
+                         m + y.offW, (double*)net->tW64[i]);
+      hipLaunchKernelGGL(k_cvt_back<double>, dim3(1), dim3(256), 0, t->st, 1, y.N, m + y.offb, (double*)net->tB64[i]);
+    }
   helm_status s = sync(t, "don_train_export");
   if (s) return s;
   don_touch(net);

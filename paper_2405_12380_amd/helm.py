@@ -33,8 +33,9 @@ DON_TANH, DON_RELU, DON_LEAKY = 0, 1, 2
 DON_SPLIT_OUTPUT, DON_SPLIT_INPUT = 0, 1
 DON_TRUNK, DON_FULL, DON_BRANCH_INPUT = 0, 1, 2
 META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
+RB_AUTO, RB_RING, RB_PAIRS = 0, 1, 2
 
-EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
+EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_set_rbgs_kernel", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
             "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "meta_solve_batch", "helm_misfit",
             "helm_ksq_gradient", "don_train_create", "don_train_data", "don_train_steps", "don_train_eval",
@@ -60,13 +61,14 @@ class MetaOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("restart", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
                 ("smoother", C.c_int), ("n_r", C.c_int), ("omega", C.c_double), ("nn_every", C.c_int),
                 ("p_used", C.c_int), ("k", C.c_double), ("history", C.POINTER(C.c_double)), ("q_fp32", C.c_int),
-                ("mg_levels", C.c_int), ("mg_nu", C.c_int)]
+                ("mg_levels", C.c_int), ("mg_nu", C.c_int), ("no_drop", C.c_int), ("fallback_restart", C.c_int)]
 
 
 class MetaStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("matvecs", C.c_int), ("precond_apps", C.c_int), ("converged", C.c_int),
                 ("rank_used", C.c_int), ("history_len", C.c_int), ("rel_res", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("cond_Ac_est", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("cond_Ac_est", C.c_double),
+                ("fallback_iters", C.c_int)]
 
 
 class DonTrainOpts(C.Structure):
@@ -79,6 +81,7 @@ _sig = {
     "helm_setup": (C.c_int, [C.POINTER(HelmGrid), C.c_int, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "helm_set_ksq": (C.c_int, [_vp, _vp, _vp]),
     "helm_tune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "helm_set_rbgs_kernel": (C.c_int, [_vp, C.c_int]),
     "helm_destroy": (None, [_vp]),
     "helm_size": (C.c_size_t, [_vp]),
     "helm_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
@@ -164,23 +167,32 @@ def _dev(a, dtype, device="cuda"):
     return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).reshape(-1)
 
 
+def _host_or_dev(a, dtype):
+    """(owner, pointer): a device tensor as is, anything else as a contiguous
+    host array of the dtype (the owner keeps it alive for the call)."""
+    if isinstance(a, torch.Tensor) and a.is_cuda:
+        t = a.to(dtype=dtype).contiguous().reshape(-1)
+        return t, _vp(t.data_ptr())
+    h = np.ascontiguousarray(a.cpu().numpy() if isinstance(a, torch.Tensor) else a,
+                             dtype=torch.empty(0, dtype=dtype).numpy().dtype).reshape(-1)
+    return h, _vp(h.ctypes.data)
+
+
 class Op:
     """The discrete Helmholtz operator on a grid (``helm_setup``).
 
     ``n`` is (nx, ny) or (nx, ny, nz); ``ksq``, ``alpha`` (real) and ``mask``
-    (uint8) are arrays of the field shape or flat, host or device."""
+    (uint8) are arrays of the field shape or flat: numpy arrays are passed to
+    the library as host arrays, device tensors as device arrays."""
 
     def __init__(self, n, dtype: int, ksq, alpha, mask, stream=None):
         self.n = tuple(int(v) for v in n)
         self.dim = len(self.n)
         self.dtype = dtype
         g = HelmGrid(self.dim, (C.c_int * 3)(*(list(self.n) + [1] * (3 - self.dim))))
-        k = _dev(ksq, torch.float64)
-        a = _dev(alpha, torch.float64)
-        m = _dev(mask, torch.uint8)
+        keep = [_host_or_dev(a, t) for a, t in ((ksq, torch.float64), (alpha, torch.float64), (mask, torch.uint8))]
         h = _vp()
-        _check(_lib.helm_setup(C.byref(g), dtype, _ptr(k), _ptr(a), _ptr(m), _stream(stream), C.byref(h)),
-               "helm_setup")
+        _check(_lib.helm_setup(C.byref(g), dtype, *[p for _, p in keep], _stream(stream), C.byref(h)), "helm_setup")
         self.h = h
         self.size = int(_lib.helm_size(h))
 
@@ -207,6 +219,10 @@ class Op:
         _check(_lib.helm_tune(self.h, int(fixed_ty), _stream(stream), C.byref(ty), C.byref(zb), C.byref(us)),
                "helm_tune")
         return ty.value, zb.value, us.value
+
+    def set_rbgs_kernel(self, which: int):
+        """Choose the red-black sweep kernel (RB_AUTO, RB_RING, RB_PAIRS)."""
+        _check(_lib.helm_set_rbgs_kernel(self.h, int(which)), "helm_set_rbgs_kernel")
 
     def apply(self, x, y=None, stream=None):
         y = self.field() if y is None else y
@@ -314,12 +330,14 @@ _SMOOTH = {"jacobi": JACOBI, "rbgs": RBGS}
 
 
 def _opts(kind, restart=50, tol=1e-6, max_iters=20000, smoother="jacobi", n_r=3, omega=0.5, nn_every=25,
-          p_used=None, k=0.0, history=None, net=None, q_fp32=False, mg_levels=0, mg_nu=5):
+          p_used=None, k=0.0, history=None, net=None, q_fp32=False, mg_levels=0, mg_nu=5, no_drop=False,
+          fallback_restart=0):
     pu = p_used if p_used is not None else (net.p if net is not None else 0)
     hp = history.ctypes.data_as(C.POINTER(C.c_double)) if history is not None else None
     return MetaOpts(_KIND[kind] if isinstance(kind, str) else int(kind), int(restart), float(tol), int(max_iters),
                     _SMOOTH[smoother] if isinstance(smoother, str) else int(smoother), int(n_r), float(omega),
-                    int(nn_every), int(pu), float(k), hp, 1 if q_fp32 else 0, int(mg_levels), int(mg_nu))
+                    int(nn_every), int(pu), float(k), hp, 1 if q_fp32 else 0, int(mg_levels), int(mg_nu),
+                    1 if no_drop else 0, int(fallback_restart))
 
 
 def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, stream=None, adjoint=False, **kw):

@@ -18,6 +18,20 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
+def stored(a, dtype_c64: bool):
+    """Values as a C64 op stores them (complex64 rounding), else unchanged."""
+    a = np.asarray(a)
+    return a.astype(np.complex64).astype(np.complex128) if dtype_c64 else a
+
+
+def stored_layers(layers, dtype_c64: bool):
+    """Network weights as a C64 network stores them (fp32 rounding), else unchanged."""
+    if not dtype_c64:
+        return layers
+    return [(np.asarray(W, dtype=np.float32).astype(np.float64), np.asarray(b, dtype=np.float32).astype(np.float64))
+            for W, b in layers]
+
+
 def make_op(helm, P, dtype):
     return helm.Op(P["n"], dtype, P["ksq"], P["alpha"], P["mask"])
 

@@ -88,3 +88,33 @@ def test_null_handles_rejected():
     assert lib.helm_size(None) == 0
     lib.helm_destroy(None)
     lib.deeponet_free(None)
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """sizeof and every field offset of the option/stat structs, as the C
+    compiler lays them out from include/helm.h, equal the binding's ctypes
+    structures."""
+    import shutil
+    import subprocess
+    from paper_2405_12380_amd import helm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"meta_opts": helm.MetaOpts, "meta_stats": helm.MetaStats, "don_desc": helm.DonDesc,
+               "don_train_opts": helm.DonTrainOpts, "helm_grid": helm.HelmGrid}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "helm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -12,7 +12,7 @@ import torch
 
 from paper_2405_12380_amd import inputs as I
 from oracle import operator as op_or, meta as meta_or, deeponet as don_or, coarse as co_or, adjoint as adj_or
-from tests.helpers import make_op, rel_err, to_np
+from tests.helpers import make_op, rel_err, stored, stored_layers, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -31,16 +31,16 @@ def test_adjoint_forced_count_parity(kind, iters, dtype):
     """DeepONet-Krylov on A^H lam = g at a forced count against the oracle's
     iterations on A(conj s) with the preconditioner built from A(conj s)."""
     C = I.config2(1, n=(16, 16, 16))
-    s = op_or.coefficient(C["ksq"], C["alpha"])
+    lo = dtype == helm.C64
+    s = stored(op_or.coefficient(C["ksq"], C["alpha"]), lo)
     op = make_op(helm, C, dtype)
     net = _net(C, dtype)
     g = np.random.default_rng(21)
     rhs = g.standard_normal(C["f"].shape) + 1j * g.standard_normal(C["f"].shape)
     rhs[C["mask"].astype(bool)] = 0
-    if dtype == helm.C64:
-        rhs = rhs.astype(np.complex64).astype(np.complex128)
+    rhs = stored(rhs, lo)
     sH = np.conj(s)
-    T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
+    T = don_or.trunk_matrix(I.node_points(C["n"]), stored_layers(C["trunk"], lo))
     cs = co_or.CoarseSpace(T, sH, C["mask"], 64, q_round="f32" if dtype == helm.C64 else None,
                            tau=co_or.TAU_C128 if dtype == helm.C128 else co_or.TAU_C64)
     M = meta_or.krylov_preconditioner(sH, C["mask"], "jacobi", 3, 0.5, cs)
@@ -49,7 +49,7 @@ def test_adjoint_forced_count_parity(kind, iters, dtype):
     st, stats = helm.meta_solve(op, net, op.field(rhs), lam, kind=kind, restart=50, tol=0.0, max_iters=iters, n_r=3,
                                 omega=0.5, p_used=64, adjoint=True)
     assert stats["iters"] == iters and stats["rank_used"] == cs.rank
-    assert rel_err(to_np(lam), lam_or) <= (1e-10 if dtype == helm.C128 else 2e-4)
+    assert rel_err(to_np(lam), lam_or) <= (1e-10 if dtype == helm.C128 else 2e-5)
 
 
 def test_adjoint_solve_against_sparse_lu():

@@ -7,14 +7,18 @@ Unpreconditioned BiCGStab on these indefinite problems amplifies rounding
 differences about 30x per iteration (the oracle itself moves by 1e-8 after
 10 iterations when f is perturbed by 1e-15), so its forced-count field
 comparison is taken at 6 iterations and its to-tolerance count is compared
-with the range of counts the oracle gives under 1e-15 perturbations of f,
-widened on each side by that range's width plus 2."""
+with the range of counts the oracle gives for the source and 30 perturbations
+of it at 1e-15 (tests/golden/bicgstab_counts_20cube.json, written by the
+script beside it): within 2 of that range, as for every other count."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2405_12380_amd import inputs as I
 from oracle import operator as op_or, meta as meta_or, deeponet as don_or
-from tests.helpers import make_op, rel_err, to_np
+from tests.helpers import make_op, rel_err, stored, stored_layers, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -46,25 +50,27 @@ def test_forced_count_parity(kind, iters, dtype):
     assert np.all(to_np(u)[C["mask"].ravel().astype(bool)] == 0)
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
 @pytest.mark.parametrize("kind", ["gmres", "bicgstab"])
 def test_to_tolerance_counts(kind):
     C = _c2(20, 1)
     s = op_or.coefficient(C["ksq"], C["alpha"])
     op = make_op(helm, C, helm.C128)
-    _, info = meta_or.krylov_meta(kind, C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 5000)
     u = op.field()
     st, stats = helm.meta_solve(op, None, op.field(C["f"]), u, kind=kind, restart=50, tol=1e-6, max_iters=5000)
-    assert st == helm.OK and info["status"] == 0
-    counts = [info["iters"]]
-    if kind == "bicgstab":
-        g = np.random.default_rng(0)
-        for _ in range(6):
-            fp = C["f"] * (1 + 1e-15 * g.standard_normal(C["f"].shape))
-            counts.append(meta_or.krylov_meta(kind, fp, np.zeros_like(fp), s, C["mask"], 50, 1e-6, 5000)[1]["iters"])
-    # within 2 of the counts the oracle itself gives; for BiCGStab the band is
-    # widened by the spread the oracle shows under 1e-15 perturbations of f
-    spread = max(counts) - min(counts)
-    assert min(counts) - spread - 2 <= stats["iters"] <= max(counts) + spread + 2, (stats["iters"], counts)
+    assert st == helm.OK
+    if kind == "gmres":
+        _, info = meta_or.krylov_meta(kind, C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 5000)
+        assert info["status"] == 0
+        lo = hi = info["iters"]
+    else:
+        with open(os.path.join(GOLDEN, "bicgstab_counts_20cube.json")) as fh:
+            ref = json.load(fh)
+        lo, hi = ref["min"], ref["max"]
+    # within 2 of the count (GMRES) or of the range of counts (BiCGStab) the oracle gives
+    assert lo - 2 <= stats["iters"] <= hi + 2, (stats["iters"], lo, hi)
     assert stats["rel_res"] <= 1e-6
     r = op_or.residual(to_np(u).reshape(C["f"].shape), C["f"], s, C["mask"])
     assert np.linalg.norm(r) / np.linalg.norm(C["f"]) <= 1e-6
@@ -102,24 +108,100 @@ def test_nonfinite_input_reported():
     assert st == helm.E_NONFINITE
 
 
+# complex64 on the seeded-network config 1 relaxation: the iteration diverges
+# (|u| ~ 1e9) and amplifies every fp32 storage rounding; the floor measured by
+# emulating fp32 storage in the oracle is ~2e-5 (Jacobi) and ~1e-4 (red-black),
+# tests/test_oracle_storage_floor.py, so that fixture is held to the floor's
+# bound; the damped-network fixture below meets the 2e-5 contract.
+C64_FLOOR_TOL = 2e-4
+
+
+def _c1_relaxation(kind, dtype, out_scale=1.0):
+    C = I.config1()
+    lo = dtype == helm.C64
+    s = stored(op_or.coefficient(C["ksq"], C["alpha"]), lo)
+    f = stored(C["f"], lo)
+    branch = list(C["branch"])
+    branch[-1] = (branch[-1][0] * out_scale, branch[-1][1] * out_scale)
+    op = make_op(helm, C, dtype)
+    net = helm.DeepONet(dtype, branch, C["trunk"], C["p"], head="split_input", branch_grid=C["n"])
+    T = don_or.trunk_matrix(I.node_points(C["n"]), stored_layers(C["trunk"], lo))
+    corr = meta_or.deeponet_correction(s, C["mask"], T, dict(branch=stored_layers(branch, lo), head="split_input",
+                                                               p=C["p"], branch_grid=C["n"]))
+    smoother = "jacobi" if kind == "jacobi" else "rbgs"
+    u_or, info = meta_or.relaxation_meta(f, np.zeros_like(f), s, C["mask"], smoother, 0.5, 200, 25, 0.0,
+                                         correction=corr)
+    u = op.field()
+    st, stats = helm.meta_solve(op, net, op.field(f), u, kind=kind, tol=0.0, max_iters=200, nn_every=25,
+                                omega=0.5)
+    assert stats["iters"] == 200 and stats["precond_apps"] == 8 == info["corrections"]
+    return rel_err(to_np(u), u_or)
+
+
 @pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
 @pytest.mark.parametrize("kind", ["jacobi", "gs"])
 def test_c1_relaxation_meta(kind, dtype):
     """Config 1 (iii): relaxation with the DeepONet correction after every 25
-    sweeps, 200 sweeps (8 corrections), omega 0.5."""
+    sweeps, 200 sweeps (8 corrections), omega 0.5, seeded network."""
+    err = _c1_relaxation(kind, dtype)
+    assert err <= (FIELD_TOL[dtype] if dtype == helm.C128 else C64_FLOOR_TOL), err
+
+
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+@pytest.mark.parametrize("kind", ["jacobi", "gs"])
+def test_c1_relaxation_meta_damped_net(kind, dtype):
+    """The same, with the network's output layer scaled by 1e-3 (corrections
+    that do not amplify the residual): the field contract, 2e-5 in complex64."""
+    assert _c1_relaxation(kind, dtype, out_scale=1e-3) <= FIELD_TOL[dtype]
+
+
+def _c1_fallback(kind, net_on, max_iters, tol, dtype=None):
+    dtype = dtype or helm.C128
     C = I.config1()
     s = op_or.coefficient(C["ksq"], C["alpha"])
     op = make_op(helm, C, dtype)
-    net = helm.DeepONet(dtype, C["branch"], C["trunk"], C["p"], head="split_input", branch_grid=C["n"])
-    T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
-    corr = meta_or.deeponet_correction(s, C["mask"], T, dict(branch=C["branch"], head="split_input", p=C["p"],
-                                                               branch_grid=C["n"]))
     smoother = "jacobi" if kind == "jacobi" else "rbgs"
-    u_or, info = meta_or.relaxation_meta(C["f"], np.zeros_like(C["f"]), s, C["mask"], smoother, 0.5, 200, 25, 0.0,
-                                         correction=corr)
+    net, corr = None, None
+    if net_on:
+        net = helm.DeepONet(dtype, C["branch"], C["trunk"], C["p"], head="split_input", branch_grid=C["n"])
+        T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
+        corr = meta_or.deeponet_correction(s, C["mask"], T, dict(branch=C["branch"], head="split_input", p=C["p"],
+                                                                   branch_grid=C["n"]))
+    u_or, info = meta_or.relaxation_meta(C["f"], np.zeros_like(C["f"]), s, C["mask"], smoother, 0.5, max_iters, 25,
+                                         tol, correction=corr, fallback_restart=30)
     u = op.field()
-    st, stats = helm.meta_solve(op, net, op.field(C["f"]), u, kind=kind, tol=0.0, max_iters=200, nn_every=25,
-                                omega=0.5)
-    assert stats["iters"] == 200 and stats["precond_apps"] == 8 == info["corrections"]
-    tol = FIELD_TOL[dtype] if dtype == helm.C128 else 1e-4
-    assert rel_err(to_np(u), u_or) <= tol
+    st, stats = helm.meta_solve(op, net, op.field(C["f"]), u, kind=kind, tol=tol, max_iters=max_iters,
+                                nn_every=25, omega=0.5, fallback_restart=30)
+    return C, s, u, st, stats, u_or, info
+
+
+@pytest.mark.parametrize("kind", ["jacobi", "gs"])
+def test_relaxation_fallback_forced_count(kind):
+    """Config 1 with the seeded network: its first correction multiplies the
+    residual by ~400, so the cycle is undone and standalone GMRES(30) runs
+    from u0; a forced count of 200 steps (tol = 0) compared with the oracle."""
+    C, s, u, st, stats, u_or, info = _c1_fallback(kind, True, 200, 0.0)
+    assert info["fallback_iters"] == 200 and stats["fallback_iters"] == 200
+    assert stats["iters"] == info["iters"] == 25 and stats["precond_apps"] == 1
+    assert rel_err(to_np(u), u_or) <= FIELD_TOL[helm.C128]
+
+
+def test_relaxation_fallback_after_growth():
+    """Plain damped Jacobi on config 1 contracts for 200 sweeps and then grows
+    (k^2 above the smallest eigenvalue): the fallback restarts from the
+    200-sweep iterate; forced count against the oracle."""
+    C, s, u, st, stats, u_or, info = _c1_fallback("jacobi", False, 400, 0.0)
+    assert info["iters"] == stats["iters"] == 225
+    assert info["fallback_iters"] == stats["fallback_iters"] == 400
+    assert rel_err(to_np(u), u_or) <= FIELD_TOL[helm.C128]
+
+
+def test_relaxation_fallback_to_tolerance():
+    """The fallback to 1e-8: GMRES step count within 2 of the oracle's, the
+    true residual below the tolerance."""
+    C, s, u, st, stats, u_or, info = _c1_fallback("jacobi", True, 20000, 1e-8)
+    assert st == helm.OK and info["status"] == 0
+    assert abs(stats["fallback_iters"] - info["fallback_iters"]) <= 2
+    assert stats["rel_res"] <= 1e-8
+    r = op_or.residual(to_np(u).reshape(C["f"].shape), C["f"], s, C["mask"])
+    assert np.linalg.norm(r) / np.linalg.norm(C["f"]) <= 1e-8

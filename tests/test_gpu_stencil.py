@@ -46,6 +46,20 @@ def test_apply_parity(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+def test_setup_from_host_and_device_arrays(dtype):
+    """helm_setup takes its inputs from host memory (numpy arrays) or device
+    memory (device tensors): the two operators are identical."""
+    P, s = _problem((19, 13, 11), 4, dtype)
+    op_h = helm.Op(P["n"], dtype, P["ksq"], P["alpha"], P["mask"])
+    op_d = helm.Op(P["n"], dtype, *[torch.as_tensor(np.ascontiguousarray(a)).cuda()
+                                    for a in (P["ksq"], P["alpha"], P["mask"])])
+    x = op_h.field(_cast(P["x"], dtype))
+    y_h, y_d = to_np(op_h.apply(x)), to_np(op_d.apply(x))
+    assert np.array_equal(y_h, y_d)
+    assert rel_err(y_h, op_or.apply(_cast(P["x"], dtype), s, P["mask"]).ravel()) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
 @pytest.mark.parametrize("n", [(64, 64), (67, 35, 21), (64, 64, 64)])
 def test_residual_norm_parity(n, dtype):
     P, s = _problem(n, 2, dtype)
@@ -125,6 +139,41 @@ def test_rbgs_many_tiles_parity(dtype):
     for _ in range(2):
         ref = _cast(op_or.rbgs_sweep(ref, f, s, P["mask"], 0.9), dtype)
     assert rel_err(to_np(u), ref) <= (1e-12 if dtype == helm.C128 else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+@pytest.mark.parametrize("n", [(67, 35, 21), (130, 9, 33), (5, 3, 4), (200, 100, 40)])
+def test_rbgs_pair_kernel_3d(n, dtype):
+    """The register-pair red-black kernel in 3D (the one taken for fields of
+    2 GiB and more) forced at small sizes: against the oracle's red-then-black
+    sweep (each sweep's result rounded to the storage precision), and bit for
+    bit against the LDS-ring kernel, which rounds its red values the same way."""
+    P, s = _problem(n, 6, dtype)
+    op = make_op(helm, P, dtype)
+    u0 = _cast(P["x"], dtype)
+    f = _cast(P["f"], dtype)
+    fd = op.field(f)
+    out = {}
+    for which in (helm.RB_PAIRS, helm.RB_RING):
+        op.set_rbgs_kernel(which)
+        u = op.field(u0)
+        op.relax(helm.RBGS, 0.9, 2, fd, u)
+        out[which] = to_np(u)
+    ref = u0.copy()
+    for _ in range(2):
+        ref = _cast(op_or.rbgs_sweep(ref, f, s, P["mask"], 0.9), dtype)
+    assert rel_err(out[helm.RB_PAIRS], ref) <= TOL[dtype]
+    assert np.array_equal(out[helm.RB_PAIRS], out[helm.RB_RING])
+
+
+def test_rbgs_kernel_choice_rejected():
+    P, _ = _problem((9, 8), 1, helm.C128)
+    op = make_op(helm, P, helm.C128)
+    with pytest.raises(helm.HelmError):
+        op.set_rbgs_kernel(helm.RB_RING)       # 2D has only the pair kernel
+    with pytest.raises(helm.HelmError):
+        op.set_rbgs_kernel(7)
+    op.set_rbgs_kernel(helm.RB_PAIRS)
 
 
 def test_residual_and_jacobi_full_size_256():

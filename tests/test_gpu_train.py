@@ -159,3 +159,24 @@ def test_trainer_rejects_unsupported_networks():
         with pytest.raises(helm.HelmError) as e:
             helm.Trainer(net, X, batch=64, max_steps=2)
         assert e.value.status == helm.E_INVAL
+
+
+def test_new_data_after_captured_steps():
+    """Training steps are replayed from captured graphs; replacing the data
+    (a larger set, new labels) must record them again: the first loss on the
+    new data equals the oracle's loss at the trainer's current parameters."""
+    branch, trunk, X, F, Y = _net_and_data(2, n=128)
+    net = _load(branch, trunk)
+    tr = helm.Trainer(net, X, batch=64, max_steps=8)
+    tr.data(torch.as_tensor(F).cuda(), torch.as_tensor(Y).cuda())
+    tr.steps(np.random.default_rng(1).integers(0, 128, size=64 * 8))   # captures the one- and eight-step graphs
+    _, _, _, F2, Y2 = _net_and_data(3, n=256)
+    tr.data(torch.as_tensor(F2).cuda(), torch.as_tensor(Y2).cuda())
+    flat = tr.params()
+    b_now, t_now = tr.unflatten(flat, 0, 3), tr.unflatten(flat, 1, 3)
+    idx = np.random.default_rng(4).permutation(256)[:64]
+    idx[0] = 255                                                            # beyond the old data
+    losses = tr.steps(idx)
+    L_or, _, _, _ = T.loss_and_grads(F2[idx].astype(np.float64), X, Y2[idx].T.astype(np.complex128),
+                                     b_now, t_now, rnd=T.bf16)
+    assert abs(losses[0] - L_or) <= 1e-3 * L_or

@@ -240,3 +240,69 @@ def test_full_basis_makes_meta_krylov_exact():
     u, info = meta.relaxation_meta(C["f"], np.zeros_like(C["f"]), s, C["mask"], "jacobi", 0.5, 100, 3, 1e-12,
                                    correction=exact)
     assert info["status"] == krylov.CONVERGED and info["iters"] == 3 and info["corrections"] == 1
+
+
+def _c1_like(n=20, k=10.0):
+    """Config 1's scatterer and source on a smaller 2D grid (k^2 above the
+    smallest eigenvalue of the Laplacian: plain Jacobi eventually grows)."""
+    nn = (n, n)
+    mask = I.box_mask(nn, (0.5, 0.5), 0.1)
+    f = I.gaussian_source(nn, (0.25, 0.5), 0.05)
+    f[mask.astype(bool)] = 0
+    return nn, op.coefficient(np.full(I.field_shape(nn), k * k), I.sponge(nn)), mask, f
+
+
+def test_relaxation_fallback_reaches_direct_solve():
+    """A relaxation meta-solve whose correction makes the residual grow hands
+    over to standalone GMRES, which reaches the dense direct solution."""
+    nn, s, mask, f = _c1_like()
+    u_star = op.direct_solve(f, s, mask)
+
+    def bad(r):  # a correction that amplifies the residual
+        return 50.0 * r
+
+    h = []
+    u, info = meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, 2000, 5, 1e-12, correction=bad,
+                                   history=h, fallback_restart=40)
+    assert info["status"] == 0 and info["iters"] == 5 and info["corrections"] == 1
+    assert h[0] > 1.0 and info["fallback_iters"] > 0
+    assert np.linalg.norm(u - u_star) <= 1e-9 * np.linalg.norm(u_star)
+    # without the fallback the same iteration does not converge
+    _, info0 = meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, 200, 5, 1e-12, correction=bad)
+    assert info0["status"] != 0 and info0["fallback_iters"] == 0
+
+
+def test_relaxation_fallback_idle_when_contracting():
+    """Homogeneous positive-definite case (k^2 below the smallest eigenvalue, no
+    sponge, no scatterer): damped Jacobi contracts every residual, the fallback
+    never triggers and the result equals the run without it, bit for bit."""
+    nn = (16, 16)
+    s = op.coefficient(np.full(I.field_shape(nn), 4.0), np.zeros(I.field_shape(nn)))
+    mask = np.zeros(I.field_shape(nn), np.uint8)
+    f = I.gaussian_source(nn, (0.4, 0.6), 0.1)
+    u1, i1 = meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, 300, 10, 0.0, fallback_restart=20)
+    u0, i0 = meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, 300, 10, 0.0)
+    assert i1["fallback_iters"] == 0 and i1["iters"] == 300
+    assert np.array_equal(u1, u0)
+
+
+def test_relaxation_fallback_restarts_from_last_good_iterate():
+    """Plain Jacobi on the C1-like grid decreases the residual for a while and
+    then grows.  The fallback must start from the iterate before the first
+    growing cycle (not the grown one, not u0): its result equals GMRES started
+    from the iterate of a separate relaxation run stopped before that cycle."""
+    nn, s, mask, f = _c1_like()
+    h = []
+    meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, 4000, 25, 0.0, history=h)
+    h = np.array(h)
+    grow = int(np.argmax(h[1:] > h[:-1])) + 1   # first cycle whose residual exceeds the previous one
+    assert h[grow] > h[grow - 1] and np.all(np.diff(h[:grow]) < 0)
+    budget = 25 * (grow + 1)
+    u_prev, _ = meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, 25 * grow, 25, 0.0)
+    u, info = meta.relaxation_meta(f, np.zeros_like(f), s, mask, "jacobi", 0.5, budget, 25, 0.0, fallback_restart=10)
+    assert info["fallback_iters"] == budget
+
+    def A(v):
+        return op.apply(v.reshape(s.shape), s, mask).ravel()
+    ref, _ = krylov.gmres(A, f.ravel(), u_prev.ravel(), 10, 0.0, budget)
+    assert np.linalg.norm(u.ravel() - ref) <= 1e-13 * np.linalg.norm(ref)

@@ -135,3 +135,18 @@ def test_gmres_restart_counts_and_nonconvergence():
     assert info["precond_apps"] == 0  # no preconditioner given
     # 4 full cycles of 5 and one of 3: one true residual per cycle start, one at exit
     assert info["matvecs"] == 23 + 5 + 1
+
+
+def test_golden_bicgstab_counts_match_oracle():
+    """The stored count range (tests/golden) was written by the oracle as it
+    stands: its unperturbed count is recomputed here."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bicgstab_counts_20cube.json")
+    with open(path) as fh:
+        ref = json.load(fh)
+    C = I.config2(1, n=(20, 20, 20))
+    s = op.coefficient(C["ksq"], C["alpha"])
+    _, info = meta.krylov_meta("bicgstab", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, ref["tol"], 5000)
+    assert info["iters"] == ref["unperturbed"]
+    assert ref["min"] <= ref["unperturbed"] <= ref["max"] and len(ref["counts"]) == 31

@@ -1,6 +1,8 @@
-"""Pins of the multigrid oracle (§4.2, DeepONet-MG-Krylov): transfer
+"""Pins of the multigrid oracle (§4.3, DeepONet-MG-Krylov): transfer
 operators against their closed forms and each other, the V-cycle against
-the textbook contraction on the Laplacian and against dense LU, linearity."""
+the textbook contraction on the Laplacian and against dense LU, linearity,
+and the a-1-b DeepONet-Jacobi smoother against its dense error-propagation
+matrix."""
 import numpy as np
 import pytest
 
@@ -99,3 +101,32 @@ def test_deeponet_smoother_is_linear_and_differs_from_plain():
     # zero on scatterer nodes when the input is (Krylov residuals are)
     xm = np.where(C["mask"].ravel().astype(bool), 0, x)
     assert np.all(Hn.precond(xm)[C["mask"].ravel().astype(bool)] == 0)
+
+
+@pytest.mark.parametrize("nu", [5, 4, 1, 2])
+def test_deeponet_smoother_error_propagation(nu):
+    """The a-1-b smoother (a = nu // 2 Jacobi sweeps, one trunk-basis
+    correction, b = nu - a - 1 sweeps; 2-1-2 for nu = 5) propagates the error
+    u - u* by S^b (I - Q A_c^{-1} Q^T A) S^a with S = I - omega D^{-1} A, all
+    formed here as dense matrices from the row-by-row assembly of A.  nu = 4
+    (a = 2, b = 1) fails if a and b are swapped; nu = 5 fails if the
+    correction follows both sweep groups; nu = 1 is the correction alone."""
+    C = I.config2(0, n=(7, 7, 7))
+    s = op.coefficient(C["ksq"], C["alpha"])
+    H = mg.Hierarchy(s, C["mask"], levels=1, omega=0.5, nu=nu, trunk=C["trunk"], p_used=32)
+    A = op.dense(s, C["mask"])
+    n = A.shape[0]
+    S = np.eye(n) - 0.5 * A / np.diag(A)[:, None]
+    Q = H.coarse[0].Q
+    P = np.eye(n) - Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ A)
+    a = nu // 2
+    b = nu - a - 1
+    E = np.linalg.matrix_power(S, b) @ P @ np.linalg.matrix_power(S, a)
+    g = np.random.default_rng(nu)
+    shp = s.shape
+    f = (g.standard_normal(shp) + 1j * g.standard_normal(shp)) * (1 - C["mask"])
+    u0 = (g.standard_normal(shp) + 1j * g.standard_normal(shp)) * (1 - C["mask"])
+    u_star = np.linalg.solve(A, f.ravel())
+    got = H.smooth(0, u0, f).ravel()
+    ref = u_star + E @ (u0.ravel() - u_star)
+    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
