@@ -135,6 +135,18 @@ helm_status helm_residual(helm_op op, const void* f, const void* u, void* r, dou
 helm_status helm_relax(helm_op op, int kind, double omega, int sweeps, const void* f, void* u,
                        void* stream);
 
+/* helm_relax for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same sweeps, bit for bit, with the ping-pong field that helm_relax allocates
+ * on first use taken from a static device array of 64 MiB instead, which each
+ * GPU the library runs on holds until the process ends.  Makes no allocating
+ * call.  Fields above 64 MiB (4 Mi nodes complex128, 8 Mi complex64) return
+ * HELM_E_INVAL.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialized by the caller.  Async. */
+helm_status helm_relax_noalloc(helm_op op, int kind, double omega, int sweeps, const void* f, void* u,
+                               void* stream);
+
 /* Krylov inner products (synchronous): out[0] + i out[1] = sum conj(x_p) y_p. */
 helm_status helm_dot(helm_op op, const void* x, const void* y, double out[2], void* stream);
 /* ||x||_2 (synchronous). */

@@ -35,7 +35,7 @@ DON_TRUNK, DON_FULL, DON_BRANCH_INPUT = 0, 1, 2
 META_JACOBI, META_GS, META_GMRES, META_BICGSTAB = 0, 1, 2, 3
 RB_AUTO, RB_RING, RB_PAIRS = 0, 1, 2
 
-EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_set_rbgs_kernel", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
+EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_set_rbgs_kernel", "helm_relax_noalloc", "helm_destroy", "helm_size", "helm_apply", "helm_residual",
             "helm_relax", "helm_dot", "helm_nrm2", "deeponet_load", "deeponet_free", "deeponet_infer",
             "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "meta_solve_batch", "helm_misfit",
             "helm_ksq_gradient", "don_train_create", "don_train_data", "don_train_steps", "don_train_eval",
@@ -87,6 +87,7 @@ _sig = {
     "helm_apply": (C.c_int, [_vp, _vp, _vp, _vp]),
     "helm_residual": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "helm_relax": (C.c_int, [_vp, C.c_int, C.c_double, C.c_int, _vp, _vp, _vp]),
+    "helm_relax_noalloc": (C.c_int, [_vp, C.c_int, C.c_double, C.c_int, _vp, _vp, _vp]),
     "helm_dot": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp]),
     "helm_nrm2": (C.c_int, [_vp, _vp, C.POINTER(C.c_double), _vp]),
     "deeponet_load": (C.c_int, [C.c_int, C.POINTER(DonDesc), C.POINTER(C.POINTER(C.c_double)), C.POINTER(_vp)]),
@@ -239,6 +240,12 @@ class Op:
     def relax(self, kind: int, omega: float, sweeps: int, f, u, stream=None):
         _check(_lib.helm_relax(self.h, kind, float(omega), int(sweeps), _ptr(f), _ptr(u), _stream(stream)),
                "helm_relax")
+        return u
+
+    def relax_noalloc(self, kind: int, omega: float, sweeps: int, f, u, stream=None):
+        """``helm_relax`` without device allocation (static scratch)."""
+        _check(_lib.helm_relax_noalloc(self.h, kind, float(omega), int(sweeps), _ptr(f), _ptr(u), _stream(stream)),
+               "helm_relax_noalloc")
         return u
 
     def misfit(self, axis: int, index: int, u, d, g=None, loss=True, stream=None):
