@@ -286,7 +286,7 @@ typedef struct {
                       always so for C64).  A_c is then the Galerkin matrix of the
                       stored basis; halves the bytes of the coarse correction.      */
   int mg_levels;   /* Krylov kinds: 0 = the preconditioner above; L > 0 = one
-                      geometric multigrid V-cycle with L coarsenings (§4.2,
+                      geometric multigrid V-cycle with L coarsenings (§4.3,
                       DeepONet-MG-Krylov): every second node per level, coefficient
                       and mask injected, full weighting, multilinear prolongation,
                       exact solve on the coarsest grid (<= 128 nodes); each n_a + 1

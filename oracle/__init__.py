@@ -19,6 +19,6 @@ coarse     trunk-basis prolongation, QR, Galerkin coarse matrix, M2     (App. C)
 meta       relaxation meta-solver (eq. 3) and the Krylov preconditioner (§3.1.2, App. C)
 adjoint    receiver misfit and its k^2 gradient by the conjugate-transpose solve  (§2 eq. 1)
 training   DeepONet training step: relative L2 loss, backpropagation, Adam       (App. B)
-multigrid  geometric V-cycle preconditioner with the DeepONet-Jacobi smoother  (§4.2)
+multigrid  geometric V-cycle preconditioner with the DeepONet-Jacobi smoother  (§4.3)
 """
 from . import operator, krylov, deeponet, coarse, meta, adjoint, training, multigrid  # noqa: F401

@@ -1,5 +1,5 @@
 """Geometric multigrid preconditioner with a DeepONet-Jacobi smoother
-(oracle), §4.2 (Fig. 6: DeepONet-MG-Krylov).
+(oracle), §4.3 (the multigrid comparison figure: DeepONet-MG-Krylov).
 
 Readings (the paper gives the variant in one paragraph and a figure):
 

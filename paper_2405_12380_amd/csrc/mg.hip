@@ -1,4 +1,4 @@
-// Geometric multigrid preconditioner with the DeepONet-Jacobi smoother (§4.2,
+// Geometric multigrid preconditioner with the DeepONet-Jacobi smoother (§4.3,
 // DeepONet-MG-Krylov): one V-cycle from zero per application.
 //
 // Level l + 1 keeps every second node of level l (coarse node j on fine node

@@ -38,6 +38,47 @@ def test_headline_solve_64cube(instance):
     assert np.all(uh[C["mask"].astype(bool)] == 0)
 
 
+@pytest.fixture(scope="module")
+def headline_instance2():
+    """The headline workload's instance 2 (64^3, p = 128 trunk basis, n_r = 3,
+    omega 0.5) and the oracle's coarse space and preconditioner for it."""
+    from oracle import deeponet as don_or, coarse as co_or, meta as meta_or
+    C = I.config2(2)
+    s = op_or.coefficient(C["ksq"], C["alpha"])
+    T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
+    cs = co_or.CoarseSpace(T, s, C["mask"], 128)
+    M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
+    return C, s, cs, M
+
+
+def test_headline_forced_count_64cube(headline_instance2):
+    """The timed configuration at full size (64^3, p = 128, c128): 10
+    DeepONet-GMRES(50) steps (tol = 0) against the oracle, field parity 1e-10."""
+    from oracle import meta as meta_or
+    C, s, cs, M = headline_instance2
+    u_or, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 0.0, 10, precond=M)
+    op = make_op(helm, C, helm.C128)
+    u = op.field()
+    st, stats = helm.meta_solve(op, _net(C), op.field(C["f"]), u, kind="gmres", restart=50, tol=0.0, max_iters=10,
+                                n_r=3, omega=0.5, p_used=128, k=C["k"])
+    assert stats["iters"] == info["iters"] == 10 and stats["rank_used"] == cs.rank == 128
+    assert rel_err(to_np(u), u_or) <= 1e-10
+
+
+def test_headline_to_tolerance_64cube(headline_instance2):
+    """The same to 1e-6: iteration count within 2 of the oracle's."""
+    from oracle import meta as meta_or
+    C, s, cs, M = headline_instance2
+    _, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 5000, precond=M)
+    op = make_op(helm, C, helm.C128)
+    u = op.field()
+    st, stats = helm.meta_solve(op, _net(C), op.field(C["f"]), u, kind="gmres", restart=50, tol=1e-6, max_iters=5000,
+                                n_r=3, omega=0.5, p_used=128, k=C["k"])
+    assert st == helm.OK and info["status"] == 0
+    assert abs(stats["iters"] - info["iters"]) <= 2, (stats["iters"], info["iters"])
+    assert stats["rel_res"] <= 1e-6
+
+
 def test_batch_first_problems_true_residuals():
     """The batched workload's first four problems (their real grids) to 1e-6."""
     Ps = I.config4(count=4)

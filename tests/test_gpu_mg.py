@@ -1,4 +1,4 @@
-"""GPU parity of the multigrid preconditioner (§4.2, DeepONet-MG-Krylov):
+"""GPU parity of the multigrid preconditioner (§4.3, DeepONet-MG-Krylov):
 one V-cycle (plain Jacobi smoothing and the DeepONet-Jacobi 2-1-2 smoothing
 with the trunk basis of every level) against the oracle's V-cycle, and the
 MG-preconditioned Krylov solves at a forced count and to tolerance."""
