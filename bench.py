@@ -7,14 +7,17 @@ source with length scale 0.1, 8-cell sponge): operator setup, trunk
 evaluation at the grid nodes, trunk-basis coarse space (p = 128 columns,
 CholeskyQR2, Galerkin A_c, inverse), and DeepONet-GMRES(50) with n_r = 3
 damped-Jacobi sweeps (omega 0.5) to a true relative residual of 1e-6, in
-complex128.  Inputs are resident in HBM before the timed region.  Instances
-cycle through 8 seeds.
+complex128.  The trunk is the one trained on non-scattering 48^3 solves
+(paper_2405_12380_amd/weights, written by train_deeponet.py; --trunk seeded
+uses the seeded gain-30 trunk).  Inputs are resident in HBM before the timed
+region.  Steps cycle through the 8 instances.
 
-After the timed steps the same instances are solved by standalone GMRES(50)
-and BiCGStab (and DeepONet-BiCGStab) for the meta-vs-Krylov comparison, the
-stencil kernels are timed at 256^3 (HBM-bound size), and the CPU oracle is
-timed on a bounded sample of the same workload.  One JSON line goes to
-stdout; progress goes to stderr.
+After the timed steps: the seeded-trunk, complex64 and fp32-basis lines of the
+same workload; every instance solved by standalone GMRES(50) and BiCGStab and
+by the DeepONet meta-solvers; the stencil kernels at 256^3 and 384^3 against
+8 TB/s and a streaming-copy ceiling; the batched, multigrid, training and
+adjoint workloads; and one complete solve by the CPU oracle.  One JSON line
+goes to stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -28,6 +31,7 @@ import numpy as np
 
 METRIC = "3D solve time to 1e-6 rel. residual (meta vs GMRES); stencil HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # kernel class -> source file that defines its kernel (for the traffic record's validity)
 KERNEL_SOURCE = {"qt_part": ("coarse.hip", "coarse_dev.h"), "skinny_apply": ("coarse.hip", "coarse_dev.h"),
@@ -69,15 +73,17 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=16, help="timed solves (the 8 instances in turn)")
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--n", type=int, default=64, help="grid nodes per axis of the solve workload")
+    ap.add_argument("--trunk", choices=("trained", "seeded"), default="trained",
+                    help="headline trunk: the trained 48^3 trunk (package weights) or the seeded gain-30 one")
     ap.add_argument("--stencil-n", type=int, default=256, help="grid nodes per axis of the bandwidth runs")
     ap.add_argument("--stencil-n2", type=int, default=384, help="a second, larger bandwidth grid (0 skips it)")
-    ap.add_argument("--no-compare", action="store_true", help="skip the standalone Krylov comparison runs")
+    ap.add_argument("--no-compare", action="store_true", help="skip the per-instance Krylov comparison")
+    ap.add_argument("--no-variants", action="store_true", help="skip the seeded-trunk, fp32-basis and c64 lines")
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=4, help="oracle Arnoldi steps timed for the CPU baseline")
     ap.add_argument("--q-fp32", action="store_true", help="headline solves store the trunk basis in fp32")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-problem workload")
@@ -87,14 +93,28 @@ def parse():
     ap.add_argument("--train-samples", type=int, default=1024, help="non-scattering 48^3 solves in the training set")
     ap.add_argument("--train-epochs", type=int, default=3)
     ap.add_argument("--batch-count", type=int, default=16,
-                    help="problems in the batched workload (the first ones of the 64-problem set)")
+                    help="problems of the batched workload (its configuration has 64)")
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid nodes per axis of the adjoint workload")
     ap.add_argument("--adjoint-fd", type=int, default=2,
-                    help="finite-difference directions checked against the adjoint gradient")
+                    help="finite-difference directions checked in the adjoint workload")
     ap.add_argument("--pmc-run", action="store_true",
-                    help="for counter collection: one headline solve plus a device copy of known size "
-                         "(a 256^3 complex128 field, 268,435,456 B read and written), then exit")
+                    help="counter-collection run: one solve plus a device copy of known size, no timing")
     return ap.parse_args()
+
+
+def load_nets(helm, I, n, trunk_choice):
+    """(headline network, seeded network, trained-trunk record or None).  The
+    Krylov meta-solvers use only the trunk; the branch is the seeded one."""
+    from paper_2405_12380_amd import train_deeponet as TD
+    C0 = I.config2(0, n=(8, 8, 8))
+    seeded = helm.DeepONet(helm.C128, C0["branch"], C0["trunk"], C0["p"], head="split_output",
+                           branch_grid=(16, 16, 16), k_input=True)
+    if trunk_choice == "seeded":
+        return seeded, seeded, None
+    layers, rec = TD.load_trunk()
+    trained = helm.DeepONet(helm.C128, C0["branch"], layers, C0["p"], head="split_output", branch_grid=(16, 16, 16),
+                            k_input=True)
+    return trained, seeded, {k: v for k, v in rec.items() if k not in ("history",)}
 
 
 def main():
@@ -110,6 +130,7 @@ def main():
     torch.cuda.set_device(dev)
     dt = helm.C128
     n = (args.n,) * 3
+    nn = int(np.prod(n))
 
     log("generating inputs")
     insts = []
@@ -121,33 +142,43 @@ def main():
             alpha=torch.as_tensor(C["alpha"].ravel()).to(dev),
             mask=torch.as_tensor(C["mask"].ravel()).to(dev),
             f=torch.as_tensor(C["f"].ravel()).to(dev),
-            host=C if i == 0 else None))
-    C0 = I.config2(0, n=n)
-    net = helm.DeepONet(dt, C0["branch"], C0["trunk"], C0["p"], head="split_output", branch_grid=(16, 16, 16),
-                        k_input=True)
-    u = torch.zeros(int(np.prod(n)), dtype=torch.complex128, device=dev)
+            f64=torch.as_tensor(C["f"].ravel()).to(dev).to(torch.complex64)))
+    net, seeded, trunk_rec = load_nets(helm, I, n, args.trunk)
+    net64 = None
+    u = {helm.C128: torch.zeros(nn, dtype=torch.complex128, device=dev),
+         helm.C64: torch.zeros(nn, dtype=torch.complex64, device=dev)}
     solve_kw = dict(kind="gmres", restart=50, tol=1e-6, max_iters=5000, n_r=3, omega=0.5, p_used=128,
                     q_fp32=args.q_fp32)
 
-    def step(i, **over):
+    def step(i, nt=None, dtype=helm.C128, allow=False, **over):
+        """One timed unit: operator set-up, trunk evaluation, coarse space and
+        the DeepONet-GMRES(50) solve of instance i % 8 (allow: a solve that
+        reaches its iteration cap is recorded, not an error)."""
         d = insts[i % len(insts)]
-        op = helm.Op(n, dt, d["ksq"], d["alpha"], d["mask"])
-        u.zero_()
-        s, st = helm.meta_solve(op, net, d["f"], u, k=d["k"], **dict(solve_kw, **over))
+        op = helm.Op(n, dtype, d["ksq"], d["alpha"], d["mask"])
+        uu = u[dtype]
+        uu.zero_()
+        f = d["f"] if dtype == helm.C128 else d["f64"]
+        s, st = helm.meta_solve(op, net if nt is None else nt, f, uu, k=d["k"], **dict(solve_kw, **over))
         op.close()
-        if s != helm.OK:
+        if s != helm.OK and not (allow and s == helm.NOT_CONVERGED):
             raise RuntimeError(f"meta_solve status {s}: {st}")
         return st
 
+    def timed_pass(count, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step(i, **kw) for i in range(count)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / count, sts
+
     if args.pmc_run:
-        st = step(2)  # the instance with the fewest iterations keeps counter runs short
+        st = step(2)
         N = 256
         x = torch.zeros(N ** 3, dtype=torch.complex128, device=dev)
-        f = torch.zeros_like(x)
-        cop = helm.Op((N, N, N), dt, np.full(N ** 3, 100.0), np.zeros(N ** 3), np.zeros(N ** 3, np.uint8))
-        cop.relax(helm.JACOBI, 0.5, 1, f, x)  # one sweep into scratch, then a copy of the field back
+        y = torch.empty_like(x)
+        helm.stream_copy(x, y)  # the calibration copy of known size
         torch.cuda.synchronize()
-        cop.close()
         print(json.dumps({"pmc_run": True, "iters": st["iters"], "copy_bytes_each_way": N ** 3 * 16}))
         return
 
@@ -155,113 +186,100 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    # Inside the timed region only the dominant kernel (the coarse restriction
-    # Q^T r, about a fifth of the solve) is bracketed by events: every event pair
-    # lengthens the gap between dependent launches by microseconds.
-    helm.kprof_enable(True, kinds=[helm.KP_QT])
-    log(f"timed {args.steps} steps")
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        stats.append(step(i))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kp_timed = {helm.KP_NAMES[helm.KP_QT]: helm.kprof_read(helm.KP_QT)}
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    log(f"{ms_per_step:.2f} ms/step, iters {[s['iters'] for s in stats]}")
-    # the per-class table comes from one more pass over the instances with every
-    # class timed (not part of the timed region)
+    # Inside the timed region only the dominant kernel class is bracketed by
+    # events (every event pair lengthens the gap between dependent launches by
+    # microseconds): a first untimed pass with every class timed finds it.
     helm.kprof_enable(True)
-    for i in range(min(args.steps, len(insts))):
+    for i in range(len(insts)):
         step(i)
     torch.cuda.synchronize()
     kp = {helm.KP_NAMES[k]: helm.kprof_read(k) for k in helm.KP_NAMES}
-    helm.kprof_enable(False)
-
-    # dominant kernel class by total measured time; its figures come from the
-    # timed region when it is the class timed there
     dom = max(kp, key=lambda k: kp[k][1])
-    cnt, ms, by = kp_timed.get(dom, kp[dom])
+    dom_kind = [k for k, v in helm.KP_NAMES.items() if v == dom][0]
+    helm.kprof_enable(True, kinds=[dom_kind])
+    log(f"timed {args.steps} steps (events on {dom})")
+    ms_per_step, stats = timed_pass(args.steps)
+    cnt, ms, tot = helm.kprof_read(dom_kind)
+    helm.kprof_enable(False)
+    log(f"{ms_per_step:.2f} ms/step, iters {[s['iters'] for s in stats]}")
+
     per_launch_ms = ms / max(cnt, 1)
-    achieved = (by / max(cnt, 1)) / (per_launch_ms * 1e-3) / 1e9
-    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3),
-                   "avg_us": round(1e3 * v[1] / max(v[0], 1), 2),
-                   "GBps": round((v[2] / max(v[0], 1)) / (1e-3 * v[1] / max(v[0], 1)) / 1e9, 1) if v[1] > 0 else None}
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(1e3 * v[1] / max(v[0], 1), 2),
+                   ("TFLOPs" if k == "mfma_setup" else "GBps"):
+                       (round((v[2] / max(v[0], 1)) / (1e-3 * v[1] / max(v[0], 1)) / (1e12 if k == "mfma_setup"
+                                                                                        else 1e9), 1)
+                        if v[1] > 0 else None)}
                for k, v in kp.items()}
-    traffic = measured_traffic(dom, n[0])
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": by / max(cnt, 1), "avg_launch_us": round(per_launch_ms * 1e3, 2),
-                "timed_in": "timed region" if dom in kp_timed else "profile pass"}
+    if dom == "mfma_setup":
+        achieved = (tot / max(cnt, 1)) / (per_launch_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": "k_gemm + k_gram (fp64 MFMA set-up products)",
+                    "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": tot / max(cnt, 1), "avg_launch_us": round(per_launch_ms * 1e3, 2),
+                    "timed_in": "timed region"}
+    else:
+        achieved = (tot / max(cnt, 1)) / (per_launch_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, n[0]),
+                    "bytes_per_launch": tot / max(cnt, 1), "avg_launch_us": round(per_launch_ms * 1e3, 2),
+                    "timed_in": "timed region"}
 
     out = {"metric": METRIC, "value": round(ms_per_step, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
-           "config": {"workload": f"3D {n[0]}^3 Helmholtz scattering, DeepONet-GMRES(50) with the p=128 trunk "
-                                  f"basis (Jacobi n_r=3, omega 0.5) to 1e-6, setup included; 8 seeded instances",
-                      "grid": list(n), "restart": 50, "p_used": 128, "n_r": 3, "tol": 1e-6},
+           "config": {"workload": f"3D {n[0]}^3 Helmholtz scattering, DeepONet-GMRES(50) with the p=128 basis of "
+                                  f"the {args.trunk} trunk (Jacobi n_r=3, omega 0.5) to 1e-6, operator and coarse "
+                                  f"set-up included; 8 seeded instances in turn",
+                      "grid": list(n), "restart": 50, "p_used": 128, "n_r": 3, "tol": 1e-6, "trunk": args.trunk},
+           "iters": [s["iters"] for s in stats[:8]],
            "iters_mean": float(np.mean([s["iters"] for s in stats])),
            "setup_ms_mean": round(float(np.mean([s["setup_ms"] for s in stats])), 3),
            "solve_ms_mean": round(float(np.mean([s["solve_ms"] for s in stats])), 3),
            "rel_res_max": float(max(s["rel_res"] for s in stats)),
            "roofline": roofline, "kernels": kernels}
+    if trunk_rec:
+        out["trained_trunk"] = trunk_rec
 
-    if not args.q_fp32:
-        # the same steps with the trunk basis stored in fp32 (A_c built from the
-        # stored basis, every other quantity complex128): half the bytes of the
-        # two largest streams per iteration.  Not the headline.
-        log("fp32-basis variant")
-        for i in range(2):
-            step(i, q_fp32=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st32 = [step(i, q_fp32=True) for i in range(args.steps)]
-        torch.cuda.synchronize()
-        ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
-        out["fp32_basis"] = {"ms_per_step": round(ms32, 3), "iters": [s["iters"] for s in st32],
-                             "rel_res_max": float(max(s["rel_res"] for s in st32)),
-                             "speedup": round(ms_per_step / ms32, 3)}
-        log(f"fp32 basis: {ms32:.2f} ms/step, iters {out['fp32_basis']['iters']}")
+    if not args.no_variants:
+        # other lines on the same workload (not the headline)
+        # complex64 stores the iterate in fp32: rounding it leaves a true relative
+        # residual of about |A| eps_32 |u| / |f| (|A| ~ 2.7e4 for a random vector
+        # at h = 1/65), 6e-6 .. 1.5e-4 on these instances depending on |u| / |f|
+        # (the c64_floor pass below measures it), so 1e-6 is out of reach and the
+        # complex64 line is timed to 3e-4
+        variants = [("seeded_trunk", dict(nt=seeded)), ("c64", dict(dtype=helm.C64, tol=3e-4))]
+        if not args.q_fp32:
+            variants.append(("fp32_basis", dict(q_fp32=True)))
+        for name, kw in variants:
+            if name == "c64":
+                if net64 is None:
+                    layers = I.config2(0, n=(8, 8, 8))
+                    from paper_2405_12380_amd import train_deeponet as TD
+                    tl = TD.load_trunk()[0] if args.trunk == "trained" else layers["trunk"]
+                    net64 = helm.DeepONet(helm.C64, layers["branch"], tl, 128, head="split_output",
+                                          branch_grid=(16, 16, 16), k_input=True)
+                kw = dict(kw, nt=net64)
+            log(f"variant {name}")
+            for i in range(len(insts)):
+                step(i, **kw)
+            vms, vst = timed_pass(args.steps, **kw)
+            out[name] = {"ms_per_step": round(vms, 3), "iters": [s["iters"] for s in vst[:8]],
+                         "tol": kw.get("tol", 1e-6), "converged": [s["converged"] for s in vst[:8]],
+                         "rel_res": [float(f"{s['rel_res']:.3g}") for s in vst[:8]],
+                         "rel_res_max": float(max(s["rel_res"] for s in vst)),
+                         "vs_headline": round(ms_per_step / vms, 3)}
+            log(f"{name}: {vms:.2f} ms/step, iters {out[name]['iters']}")
+
+        if net64 is not None:
+            # the residual complex64 reaches: 600 iterations towards 1e-6 per instance
+            fl = [step(i, nt=net64, dtype=helm.C64, max_iters=600, allow=True) for i in range(len(insts))]
+            out["c64_floor"] = {"max_iters": 600, "tol": 1e-6, "converged": [s["converged"] for s in fl],
+                                "rel_res": [float(f"{s['rel_res']:.3g}") for s in fl]}
+            log(f"c64 floor: {out['c64_floor']['rel_res']}")
 
     if not args.no_compare:
-        log("standalone Krylov comparison")
-        cmp = {}
-        for kind, use_net in [("gmres", False), ("bicgstab", False), ("bicgstab", True)]:
-            rows = []
-            for i in range(2):
-                d = insts[i]
-                op = helm.Op(n, dt, d["ksq"], d["alpha"], d["mask"])
-                u.zero_()
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                kw = dict(solve_kw, kind=kind, max_iters=20000)
-                s, st = helm.meta_solve(op, net if use_net else None, d["f"], u, k=d["k"], **kw)
-                torch.cuda.synchronize()
-                tb = time.perf_counter()
-                op.close()
-                rows.append(dict(status=s, iters=st["iters"], ms=(tb - ta) * 1e3, rel_res=st["rel_res"]))
-            name = ("deeponet_" if use_net else "") + kind
-            cmp[name] = {"iters": [r["iters"] for r in rows], "ms": [round(r["ms"], 2) for r in rows],
-                         "status": [r["status"] for r in rows]}
-            log(f"{name}: {cmp[name]}")
-        meta_ms = [None, None]
-        for i in range(2):
-            d = insts[i]
-            op = helm.Op(n, dt, d["ksq"], d["alpha"], d["mask"])
-            u.zero_()
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            s, st = helm.meta_solve(op, net, d["f"], u, k=d["k"], **solve_kw)
-            torch.cuda.synchronize()
-            meta_ms[i] = ((time.perf_counter() - ta) * 1e3, st["iters"])
-            op.close()
-        cmp["deeponet_gmres"] = {"iters": [m[1] for m in meta_ms], "ms": [round(m[0], 2) for m in meta_ms]}
-        g_ms = np.mean(cmp["gmres"]["ms"])
-        out["compare"] = cmp
-        out["speedup_vs_gmres_time"] = round(float(g_ms / np.mean([m[0] for m in meta_ms])), 3)
-        out["speedup_vs_gmres_iters"] = round(float(np.mean(cmp["gmres"]["iters"]) /
-                                                    np.mean([m[1] for m in meta_ms])), 3)
+        log("per-instance comparison with standalone Krylov")
+        out["compare"] = compare(helm, torch, insts, n, net, seeded, solve_kw, u[helm.C128])
 
     if not args.no_stencil:
         log(f"stencil bandwidth at {args.stencil_n}^3")
@@ -288,9 +306,48 @@ def main():
 
     if not args.no_cpu:
         log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(insts[0]["host"], out["iters_mean"], args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(n)
 
     print(json.dumps(out), flush=True)
+
+
+def compare(helm, torch, insts, n, net, seeded, solve_kw, u):
+    """Every instance solved by standalone GMRES(50) and BiCGStab and by
+    DeepONet-GMRES(50) / DeepONet-BiCGStab with the headline trunk (and
+    DeepONet-GMRES with the seeded one): iterations and the wall time of the
+    meta_solve call (coarse set-up included for the meta-solvers), per
+    instance, with the iteration and time ratios against standalone GMRES."""
+    runs = [("gmres", None, "gmres"), ("bicgstab", None, "bicgstab"), ("deeponet_gmres", net, "gmres"),
+            ("deeponet_bicgstab", net, "bicgstab"), ("deeponet_gmres_seeded", seeded, "gmres")]
+    rows = []
+    for i, d in enumerate(insts):
+        op = helm.Op(n, helm.C128, d["ksq"], d["alpha"], d["mask"])
+        row = {"instance": i, "k": round(d["k"], 3)}
+        for name, nt, kind in runs:
+            u.zero_()
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            s, st = helm.meta_solve(op, nt, d["f"], u, k=d["k"], **dict(solve_kw, kind=kind, max_iters=20000))
+            torch.cuda.synchronize()
+            row[name] = {"iters": st["iters"], "ms": round((time.perf_counter() - ta) * 1e3, 2), "status": s,
+                         "rel_res": st["rel_res"]}
+        g, m = row["gmres"], row["deeponet_gmres"]
+        row["iter_ratio_vs_gmres"] = round(g["iters"] / m["iters"], 2)
+        row["time_ratio_vs_gmres"] = round(g["ms"] / m["ms"], 2)
+        log(f"instance {i} (k {d['k']:.2f}): " + ", ".join(f"{nm} {row[nm]['iters']} it {row[nm]['ms']} ms"
+                                                          for nm, _, _ in runs))
+        rows.append(row)
+        op.close()
+    ok10 = [r["iter_ratio_vs_gmres"] >= 10 for r in rows]
+    faster = [r["time_ratio_vs_gmres"] > 1 for r in rows]
+    return {"rows": rows,
+            "instances_with_10x_fewer_iterations": int(sum(ok10)),
+            "instances_with_lower_wall_time": int(sum(faster)),
+            "all_instances_10x_fewer_iterations_and_faster": bool(all(ok10) and all(faster)),
+            "iter_ratio_min": min(r["iter_ratio_vs_gmres"] for r in rows),
+            "time_ratio_min": min(r["time_ratio_vs_gmres"] for r in rows),
+            "timing": "wall time of the meta_solve call on an existing operator; the meta-solvers' coarse "
+                      "set-up (trunk evaluation, QR, Galerkin matrix) is inside it"}
 
 
 # algorithmic HBM bytes per node of one DeepONet-BiCGStab iteration (complex128,
@@ -402,7 +459,9 @@ def training(helm, I, torch, dev, n_samples, epochs):
     """DeepONet training (App. B, the 4x256 trunk, p = 128): labels from the
     batched plain BiCGStab (to 1e-8) on non-scattering 48^3 problems, branch
     inputs from the meta-solver's own sampling (DON_BRANCH_INPUT), then bf16
-    MFMA training with Adam (batch 64, lr 1e-3); 10% held out."""
+    MFMA training with Adam (batch 64, the constant lr 1e-4 of App. B); 10% held
+    out.  A bounded run that measures the training step; the trunk the headline
+    uses comes from the full run of paper_2405_12380_amd/train_deeponet.py."""
     n = (48, 48, 48)
     P = 48 ** 3
     dt = helm.C128
@@ -432,7 +491,7 @@ def training(helm, I, torch, dev, n_samples, epochs):
     n_train = n_samples - n_val
     S = 64
     steps = n_train // S
-    tr = helm.Trainer(net, I.node_points(n), batch=S, max_steps=max(steps, n_val // S), lr=1e-3)
+    tr = helm.Trainer(net, I.node_points(n), batch=S, max_steps=max(steps, n_val // S), lr=1e-4)
     tr.data(F.float(), Y)
     del F
     flops = train_flops_per_step(tr, S, P, 5, 5, 128)
@@ -554,13 +613,15 @@ def stencil_bandwidth(helm, I, torch, dev, N, reps=40):
         us = 1e3 * ms / cnt   # one launch per sweep (red-black: one fused pass)
         gbs = by[name] * nn / (us * 1e-6) / 1e9
         out[name] = {"us": round(us, 1), "GBps": round(gbs, 1), "frac_peak": round(gbs / HBM_PEAK_GBS, 3)}
+    # copy ceiling: the library's non-temporal streaming copy of 2 GiB (read +
+    # write), timed with events on the stream it runs on
     buf = torch.empty(2 * 1024 ** 3 // 16, dtype=torch.complex128, device=dev)
     buf2 = torch.empty_like(buf)
-    buf2.copy_(buf)
+    helm.stream_copy(buf, buf2)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(10):
-        buf2.copy_(buf)
+        helm.stream_copy(buf, buf2)
     b.record()
     torch.cuda.synchronize()
     copy_gbs = 2 * buf.numel() * 16 / (a.elapsed_time(b) / 10 * 1e-3) / 1e9
@@ -572,50 +633,32 @@ def stencil_bandwidth(helm, I, torch, dev, N, reps=40):
     return out
 
 
-def cpu_baseline(C, gpu_iters, steps):
-    """The oracle (numpy, complex128) on instance 0: coarse setup components on a
-    1/16 row sample scaled by 16, plus `steps` preconditioned Arnoldi steps,
-    scaled to the GPU's mean iteration count."""
+def cpu_baseline(n):
+    """The oracle (plain numpy, complex128), measured end to end on instance 2
+    of the headline workload: trunk evaluation, Householder QR of the masked
+    p = 128 trunk columns, Galerkin matrix, then DeepONet-GMRES(50) with n_r = 3
+    Jacobi sweeps to 1e-6.  The oracle takes only inputs the seeded
+    generators produce, so it runs the seeded gain-30 trunk (the trained trunk
+    comes from the GPU path): its per-iteration cost is the comparison point."""
     from threadpoolctl import threadpool_info
     from paper_2405_12380_amd import inputs as I
     from oracle import operator as op_or, deeponet as don_or, coarse as co_or, meta as meta_or
 
+    C = I.config2(2, n=n)
     s = op_or.coefficient(C["ksq"], C["alpha"])
-    pts = I.node_points(C["n"])
-    N = pts.shape[0]
-    sub = N // 16
     t0 = time.perf_counter()
-    T_sub = don_or.trunk_matrix(pts[:sub], C["trunk"])
-    t1 = time.perf_counter()
-    P = co_or.prolongation(T_sub, C["mask"].ravel()[:sub], 128)
-    co_or.householder_qr(P)
-    t2 = time.perf_counter()
-    # Galerkin: 8 of the 128 basis columns through the operator, and Q^T (AQ) for them
-    Qf = np.random.default_rng(0).standard_normal((N, 8))
-    AQ = np.stack([op_or.apply(Qf[:, j].reshape(s.shape).astype(complex), s, C["mask"]).ravel()
-                   for j in range(8)], axis=1)
-    _ = Qf.T @ AQ
-    t3 = time.perf_counter()
-    setup_s = 16 * (t1 - t0) + 16 * (t2 - t1) + 16 * (t3 - t2)
-    # Arnoldi steps with the full preconditioner; the cost of M2 does not depend
-    # on the basis values, so a random orthonormal Q of the same shape stands in
-    cs = co_or.CoarseSpace.__new__(co_or.CoarseSpace)
-    cs.shape = s.shape
-    rng = np.random.default_rng(1)
-    cs.Q, _r = np.linalg.qr(rng.standard_normal((N, 128)))
-    cs.rank = 128
-    cs.Ac = np.eye(128, dtype=complex) * 100 + 0.1 * rng.standard_normal((128, 128))
+    T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
+    cs = co_or.CoarseSpace(T, s, C["mask"], 128)
     M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
-    t4 = time.perf_counter()
-    meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 0.0, steps, precond=M)
-    t5 = time.perf_counter()
-    per_iter = (t5 - t4) / steps
-    est_ms = (setup_s + per_iter * gpu_iters) * 1e3
+    t1 = time.perf_counter()
+    u, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 5000, precond=M)
+    t2 = time.perf_counter()
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": round(est_ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"instance 0 at {C['n'][0]}^3: trunk, QR and Galerkin timed on 1/16 of the rows/columns "
-                      f"(x16), {steps} preconditioned Arnoldi steps timed and scaled to {gpu_iters:.1f} iterations",
-            "setup_s": round(setup_s, 2), "per_iter_s": round(per_iter, 3), "host_cpus": os.cpu_count()}
+    return {"value": round((t2 - t0) * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"one complete solve, instance 2 at {n[0]}^3 (seeded gain-30 trunk, {info['iters']} "
+                      f"DeepONet-GMRES(50) iterations to {info['rel_res']:.1e}), set-up and iterations measured",
+            "iters": int(info["iters"]), "setup_s": round(t1 - t0, 2), "solve_s": round(t2 - t1, 2),
+            "per_iter_s": round((t2 - t1) / max(info["iters"], 1), 4), "host_cpus": os.cpu_count()}
 
 
 if __name__ == "__main__":

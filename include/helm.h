@@ -421,7 +421,9 @@ enum { HELM_KP_STENCIL = 0,   /* apply / residual / Jacobi / red-black sweeps   
        HELM_KP_MULTIAXPY = 2, /* GMRES multi-axpy w -= V h and V y                  */
        HELM_KP_QT = 3,        /* coarse restriction Q^T r (per-block partials)      */
        HELM_KP_SKINNY = 4,    /* prolongation z += Q c and the DeepONet synthesis   */
-       HELM_KP_CGS = 5 };     /* fused CGS pass w -= V h with the partials of V^H w */
+       HELM_KP_CGS = 5,       /* fused CGS pass w -= V h with the partials of V^H w */
+       HELM_KP_MFMA = 6 };    /* fp64 MFMA products of the set-up (trunk layers, Gram
+                                 and Q products); its "bytes" are algorithmic flops */
 
 /* Per-kernel timing for the whole process: `mask` has bit (1 << HELM_KP_*) set
  * for each kernel class to time (0 disables, -1 times every class); earlier
@@ -435,6 +437,11 @@ helm_status helm_kprof_enable(int mask);
  * event-measured duration (ms) and summed algorithmic bytes.  Waits for the
  * recorded events. */
 helm_status helm_kprof_read(int kind, int* count, double* total_ms, double* total_bytes);
+
+/* dst = src (bytes a multiple of 16, 16-byte aligned, no overlap) with
+ * non-temporal 16-byte loads and stores: the device-copy bandwidth that stencil
+ * kernels are compared with.  Async. */
+helm_status helm_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Text for a status code / the calling thread's last error message. */
 const char* helm_strerror(helm_status s);

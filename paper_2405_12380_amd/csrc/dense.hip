@@ -11,6 +11,7 @@
 // layers in fp64 (a C64 network's fp32 weights widened exactly).
 #include "common.h"
 #include "dense.h"
+#include "prof.h"
 
 namespace helm {
 
@@ -569,7 +570,9 @@ template <typename T>
 void gemm(int M, int N, int K, const T* A, size_t lda, const T* W, size_t ldw, const T* bias, int act, T* C,
           size_t ldc, hipStream_t st) {
   const int nb = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
+  kprof_begin(KP_MFMA, st);
   hipLaunchKernelGGL((k_gemm<T>), dim3(nb), dim3(256), 0, st, M, N, K, A, lda, W, ldw, bias, act, C, ldc);
+  kprof_end(KP_MFMA, 2.0 * M * N * K, st);
 }
 
 int small_ksplit(int K) {
@@ -600,7 +603,9 @@ void gram(size_t n, int r, const double* X, size_t ldx, const double* Y, size_t 
   const int nb = gram_nblocks(n);
   size_t rpb = (n + nb - 1) / nb;
   rpb = (rpb + GR_ROWS - 1) / GR_ROWS * GR_ROWS;
+  kprof_begin(KP_MFMA, st);
   hipLaunchKernelGGL(k_gram, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
+  kprof_end(KP_MFMA, 2.0 * (double)n * r * r, st);
   const size_t width = (size_t)r * r;
   hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, part, nb, width, out,
                      1.0);

@@ -5,10 +5,12 @@
 
 namespace helm {
 
-enum { KP_STENCIL = 0, KP_MULTIDOT = 1, KP_MULTIAXPY = 2, KP_QT = 3, KP_SKINNY = 4, KP_CGS = 5, KP_COUNT = 6 };
+enum { KP_STENCIL = 0, KP_MULTIDOT = 1, KP_MULTIAXPY = 2, KP_QT = 3, KP_SKINNY = 4, KP_CGS = 5, KP_MFMA = 6,
+       KP_COUNT = 7 };
 
 bool kprof_on();
 void kprof_begin(int kind, hipStream_t st);
+// bytes: the launch's algorithmic bytes (KP_MFMA: its algorithmic flops)
 void kprof_end(int kind, double bytes, hipStream_t st);
 
 }  // namespace helm

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <stdint.h>
 #include <vector>
 
 #include "helm.h"
@@ -54,6 +55,22 @@ thread_local hipEvent_t t_start = nullptr;
 
 bool kprof_on() { return g_prof.mask != 0; }
 
+// dst = src, 16 bytes per lane per step, non-temporal loads and stores (the
+// copy streams past the caches, as a bandwidth ceiling should)
+typedef unsigned int cp_u4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(size_t n16, const cp_u4* __restrict__ src, cp_u4* __restrict__ dst) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {  // four loads in flight per lane
+    cp_u4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+  }
+  for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 void kprof_begin(int kind, hipStream_t st) {
   if (!((g_prof.mask >> kind) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -100,6 +117,19 @@ helm_status helm_kprof_read(int kind, int* count, double* total_ms, double* tota
   *total_ms = ms;
   *total_bytes = by;
   return HELM_OK;
+}
+
+helm_status helm_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || bytes == 0 || bytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+    return fail(HELM_E_INVAL, "helm_stream_copy: NULL pointer, or size or address not a multiple of 16");
+  if ((const char*)src < (const char*)dst + bytes && (const char*)dst < (const char*)src + bytes)
+    return fail(HELM_E_INVAL, "helm_stream_copy: the buffers overlap");
+  const size_t n16 = bytes / 16;
+  size_t nb = (n16 + 4 * 256 - 1) / (4 * 256);
+  if (nb > 8192) nb = 8192;  // 32 workgroups per CU; the loop strides over the rest
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, n16, (const cp_u4*)src,
+                     (cp_u4*)dst);
+  return launch_check("helm_stream_copy");
 }
 
 }  // extern "C"

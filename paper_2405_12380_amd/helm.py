@@ -40,11 +40,11 @@ EXPORTED = ["helm_setup", "helm_set_ksq", "helm_tune", "helm_set_rbgs_kernel", "
             "meta_solve", "meta_precond", "meta_coarse_info", "meta_solve_adjoint", "meta_solve_batch", "helm_misfit",
             "helm_ksq_gradient", "don_train_create", "don_train_data", "don_train_steps", "don_train_eval",
             "don_train_grad", "don_train_apply", "don_train_nparam", "don_train_layout", "don_train_params",
-            "don_train_export", "don_train_free", "helm_kprof_enable", "helm_kprof_read",
+            "don_train_export", "don_train_free", "helm_kprof_enable", "helm_kprof_read", "helm_stream_copy",
             "helm_strerror", "helm_last_error"]
-KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY, KP_CGS = 0, 1, 2, 3, 4, 5
+KP_STENCIL, KP_MULTIDOT, KP_MULTIAXPY, KP_QT, KP_SKINNY, KP_CGS, KP_MFMA = 0, 1, 2, 3, 4, 5, 6
 KP_NAMES = {KP_STENCIL: "stencil", KP_MULTIDOT: "multidot", KP_MULTIAXPY: "multi_axpy", KP_QT: "qt_part",
-            KP_SKINNY: "skinny_apply", KP_CGS: "cgs_fused"}
+            KP_SKINNY: "skinny_apply", KP_CGS: "cgs_fused", KP_MFMA: "mfma_setup"}
 
 
 class HelmGrid(C.Structure):
@@ -116,6 +116,7 @@ _sig = {
     "don_train_free": (None, [_vp]),
     "helm_kprof_enable": (C.c_int, [C.c_int]),
     "helm_kprof_read": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "helm_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "helm_strerror": (C.c_char_p, [C.c_int]),
     "helm_last_error": (C.c_char_p, []),
 }
@@ -516,6 +517,15 @@ def kprof_enable(on: bool = True, kinds=None):
         for k in kinds:
             mask |= 1 << int(k)
     _check(_lib.helm_kprof_enable(mask), "helm_kprof_enable")
+
+
+def stream_copy(src, dst, stream=None):
+    """dst = src with the library's non-temporal streaming copy (device tensors)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("stream_copy: sizes differ")
+    _check(_lib.helm_stream_copy(_ptr(src), _ptr(dst), nb, _stream(stream)), "helm_stream_copy")
+    return dst
 
 
 def kprof_read(kind: int):
