@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhelm.so")
 SOURCES = ["stencil.hip", "blas1.hip", "gmres.hip", "dense.hip", "coarse.hip", "deeponet.hip", "meta.hip", "prof.hip",
-           "adjoint.hip", "batch.hip", "train.hip", "mg.hip", "noalloc.hip", "api.hip"]
+           "adjoint.hip", "batch.hip", "train.hip", "mg.hip", "noalloc.hip", "pool.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

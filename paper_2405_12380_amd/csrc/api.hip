@@ -38,22 +38,6 @@ helm_status hip_fail(hipError_t e, const char* what) {
   return fail(HELM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-helm_status dalloc(void** p, size_t bytes) {
-  *p = nullptr;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(HELM_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
-  }
-  return HELM_OK;
-}
-
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
-
 helm_status Buffer::ensure(size_t bytes) {
   if (bytes <= cap) return HELM_OK;
   dfree(ptr);
@@ -149,13 +133,14 @@ helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, con
     helm_destroy(op);
     return s;
   }
-  hipError_t e = hipHostMalloc((void**)&op->host, 4096 * sizeof(double), hipHostMallocMapped);
-  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&op->host_dev, op->host, 0);
-  if (e != hipSuccess) {
-    if (!op->host_dev && op->host) (void)hipHostFree(op->host);
-    op->host = nullptr;
+  if ((s = halloc_mapped((void**)&op->host, 4096 * sizeof(double)))) {
     helm_destroy(op);
-    return hip_fail(e, "hipHostMalloc");
+    return s;
+  }
+  hipError_t e = hipHostGetDevicePointer((void**)&op->host_dev, op->host, 0);
+  if (e != hipSuccess) {
+    helm_destroy(op);
+    return hip_fail(e, "hipHostGetDevicePointer");
   }
   // inputs in host (the documented case) or device memory: each copy takes its
   // direction from the pointer; k^2 is staged in the op's field scratch
@@ -202,7 +187,7 @@ void helm_destroy(helm_op op) {
   dfree(op->code);
   dfree(op->alpha);
   dfree(op->red);
-  if (op->host) (void)hipHostFree(op->host);
+  hfree_mapped(op->host);
   op->tmp.release();
   op->part.release();
   op->ws.release();

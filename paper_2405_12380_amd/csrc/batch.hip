@@ -439,9 +439,7 @@ __global__ __launch_bounds__(256) void kb_skinny(const BProb* __restrict__ P, co
 // ---- host side -------------------------------------------------------------------
 struct DevMem {
   void* p = nullptr;
-  ~DevMem() {
-    if (p) (void)hipFree(p);
-  }
+  ~DevMem() { dfree(p); }
 };
 
 struct Packing {

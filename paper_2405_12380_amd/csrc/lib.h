@@ -16,8 +16,13 @@ namespace helm {
 struct Mg;
 helm_status fail(helm_status s, const char* fmt, ...);
 helm_status hip_fail(hipError_t e, const char* what);
+// Device buffers and pinned host mirrors from the library's caching pool
+// (pool.hip): released blocks are kept for reuse; a release synchronizes the
+// device first, as hipFree does.
 helm_status dalloc(void** p, size_t bytes);
 void dfree(void* p);
+helm_status halloc_mapped(void** p, size_t bytes);
+void hfree_mapped(void* p);
 helm_status launch_check(const char* what);
 helm_status sync_stream(hipStream_t st, const char* what);
 

@@ -169,8 +169,11 @@ helm_status coarse_op(const helm_op_s* fine, hipStream_t st, helm_op_s** out) {
     helm_destroy(op);
     return s;
   }
-  hipError_t e = hipHostMalloc((void**)&op->host, 4096 * sizeof(double), hipHostMallocMapped);
-  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&op->host_dev, op->host, 0);
+  if ((s = halloc_mapped((void**)&op->host, 4096 * sizeof(double)))) {
+    helm_destroy(op);
+    return s;
+  }
+  hipError_t e = hipHostGetDevicePointer((void**)&op->host_dev, op->host, 0);
   if (e != hipSuccess) {
     helm_destroy(op);
     return hip_fail(e, "multigrid: pinned scalars");
