@@ -96,8 +96,9 @@ size_t helm_size(helm_op op);
 /* Tile autotuner for the op's stencil kernels: times y = A x (8 launches after
  * 2 warm-ups, HIP events on `stream`) for every workgroup height ty in {4, 8}
  * (only fixed_ty when it is 4 or 8; 0 = free), z-march length zb in
- * {1, 2, 4, 8, 16, 32} (<= n_z; 1 in 2D) and plain or non-temporal output
- * stores, and keeps the fastest for all later stencil work on this op.  The
+ * {1, 2, 4, 8, 16, 32} (<= n_z; 1 in 2D), plain or non-temporal output
+ * stores and one or two rows per thread (3D), and keeps the fastest for all
+ * later stencil work on this op.  The
  * per-node arithmetic does not depend on the tiling, so results of apply,
  * relax and the sweeps are unchanged; reduction partials are regrouped.
  * Outputs (each optional): the chosen ty and zb and its time per launch (us).

@@ -241,11 +241,14 @@ helm_status helm_tune(helm_op op, int fixed_ty, void* stream, int* ty_out, int* 
     for (int b = 0; b < 6; ++b) {
       if (op->dim == 2 && zbs[b] != 1) continue;
       if (zbs[b] > op->geom.nz) continue;
-      for (int nt = 0; nt < 2; ++nt) {
+      for (int v = 0; v < 4; ++v) {  // plain / non-temporal stores, one / two rows per thread
+        const int nt = v & 1, rows = 1 + (v >> 1);
+        if (rows == 2 && op->dim != 3) continue;
         StencilGeom g = op->geom;
         g.ty = tys[a];
         g.zb = zbs[b];
         g.nt = nt != 0;
+        g.rows = rows;
         auto run = [&]() {
           if (c128) stencil_apply<double>(g, op->sc, op->code, x, y, st);
           else stencil_apply<float>(g, op->sc, op->code, x, y, st);

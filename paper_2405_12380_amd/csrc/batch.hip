@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void kb_jacobi0(const BProb* __restrict__ P, c
   for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const double2 s = ldc(sc, e);
     const double2 d = q.mask[e] ? make_double2(1.0, 0.0) : make_double2(q.g.dsum - s.x, -s.y);
-    const double2 w = cdiv(ldc(v, o + e), d);
+    const double2 w = ddiv(ldc(v, o + e), d);
     stc(z, o + e, make_double2(omega * w.x, omega * w.y));
   }
 }
@@ -584,6 +584,7 @@ helm_status batch_drive(int np, helm_op_s* const* ops, don_s* net, const meta_op
     std::memset(&q, 0, sizeof q);
     q.g = ops[i]->geom;
     q.g.ty = ty;
+    q.g.rows = 1;  // the batched kernels run one row per thread
     q.sc = ops[i]->sc;
     q.code = ops[i]->code;
     q.mask = ops[i]->mask;

@@ -50,6 +50,14 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   }
 }
 __device__ __forceinline__ double2 czero() { return make_double2(0.0, 0.0); }
+// r / d for a relaxation update, d = D_p the diagonal of A (1 on scatterer
+// nodes, sum_a 2/h_a^2 - s_p elsewhere: far from zero and from overflow):
+// one reciprocal of |d|^2, then r conj(d) / |d|^2 (a few ulps, as Smith's
+// division, with one fp64 division instead of three)
+__device__ __forceinline__ double2 ddiv(double2 r, double2 d) {
+  const double inv = 1.0 / (d.x * d.x + d.y * d.y);
+  return make_double2((r.x * d.x + r.y * d.y) * inv, (r.y * d.x - r.x * d.y) * inv);
+}
 
 // Workgroup b of a launch is dispatched to XCD b % 8.  Remap the hardware block
 // id so that each XCD receives one contiguous range of logical blocks: stencil

@@ -10,7 +10,8 @@ namespace helm {
 
 struct StencilGeom {
   int nx, ny, nz, dim, zb;
-  int ty;    // tile height (rows per workgroup): 4 or 8
+  int ty;    // threads per workgroup in y: 4 or 8
+  int rows;  // rows per thread (1 or 2): a tile is 64 x ty rows nodes
   bool nt;   // non-temporal output stores (grids much larger than the caches)
   int rb;    // 3D red-black kernel: 0 = the LDS ring below 2 GiB per field, 1 = ring, 2 = register pairs
   double ih2[3];  // 1/h_a^2 (0 for absent axes)

@@ -53,76 +53,99 @@ __device__ __forceinline__ unsigned ldcode(const uint8_t* p, size_t i, bool nt) 
   return nt ? (unsigned)__builtin_nontemporal_load(p + i) : (unsigned)p[i];
 }
 
-// One workgroup's tile: logical block lb of geometry g.  RESID writes the
-// block's partial of ||r||^2 to *partial.
-template <typename S, int DIM, int MODE>
+// One workgroup's tile: logical block lb of geometry g (64 x ty threads, each
+// owning R consecutive rows, so a tile is 64 x ty R nodes of zb planes).  A
+// thread keeps its rows' values of planes z - 1, z and z + 1 in registers; the
+// rows inside its block of R are each other's y neighbours, so only the rows
+// just below and above it are loaded for y (a 64 x 16 tile at R = 2 re-reads
+// 2 of 18 rows instead of 2 of 10).  RESID writes the block's partial of
+// ||r||^2 to *partial.
+template <typename S, int DIM, int MODE, int R = 1>
 __device__ __forceinline__ void stencil_tile(const StencilGeom& g, unsigned lb, const cplx_t<S>* __restrict__ sc,
                                              const uint8_t* __restrict__ code, const cplx_t<S>* x,
                                              const cplx_t<S>* __restrict__ f, cplx_t<S>* y, double omega, int color,
                                              double* __restrict__ partial) {
-  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty * R - 1) / (g.ty * R);
   const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
   const int i = bx * 64 + threadIdx.x;
-  const int j = by * g.ty + threadIdx.y;
+  const int j0 = (by * g.ty + threadIdx.y) * R;
   const int z0 = bz * g.zb;
   const int z1 = min(g.nz, z0 + g.zb);
-  const bool active = (i < g.nx) && (j < g.ny);
+  const bool active = (i < g.nx) && (j0 < g.ny);
   const size_t plane = (size_t)g.nx * g.ny;
-  // clamped neighbour offsets (an absent neighbour is read from the node itself
-  // and then replaced by 0 through the code bits)
+  // clamped x offsets (an absent neighbour is read from the node itself and
+  // then replaced by 0 through the code bits)
   const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
-  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
   double nrm = 0.0;
   if (active && z0 < z1) {
-    size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
-    double2 c = ldc(x, p);
-    double2 zm = czero();
-    if (DIM == 3 && z0 > 0) zm = ldc(x, p - plane);
+    const size_t pb = (size_t)i + (size_t)g.nx * ((size_t)j0 + (size_t)g.ny * z0);
+    double2 c[R], zm[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = j0 + r < g.ny;
+      c[r] = in ? ldc(x, pb + (size_t)r * g.nx) : czero();
+      zm[r] = (DIM == 3 && z0 > 0 && in) ? ldc(x, pb + (size_t)r * g.nx - plane) : czero();
+    }
+    size_t p = pb;
     for (int z = z0; z < z1; ++z, p += plane) {
-      double2 znext = czero();
-      if (DIM == 3 && z + 1 < g.nz) znext = ldc(x, p + plane);
-      const bool upd = (MODE != ST_RBGS) || (((i + j + z) & 1) == color);
-      if (upd) {
-        const unsigned cd = ldcode(code, p, g.nt);
-        const double2 xm = ldc(x, p + oxm), xp = ldc(x, p + oxp);
-        const double2 ym = ldc(x, p + oym), yp = ldc(x, p + oyp);
-        const double2 sp = ldc_once(sc, p, g.nt);
+      double2 zn[R], xm[R], xp[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool in = j0 + r < g.ny;
+        const size_t q = p + (size_t)r * g.nx;
+        zn[r] = (DIM == 3 && z + 1 < g.nz && in) ? ldc(x, q + plane) : czero();
+        xm[r] = in ? ldc(x, q + oxm) : czero();
+        xp[r] = in ? ldc(x, q + oxp) : czero();
+      }
+      const double2 ybelow = j0 > 0 ? ldc(x, p - g.nx) : czero();               // row j0 - 1
+      const double2 yabove = j0 + R < g.ny ? ldc(x, p + (size_t)R * g.nx) : czero();  // row j0 + R
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (j0 + r >= g.ny) break;
+        const size_t q = p + (size_t)r * g.nx;
+        const bool upd = (MODE != ST_RBGS) || (((i + j0 + r + z) & 1) == color);
+        if (!upd) continue;
+        const unsigned cd = ldcode(code, q, g.nt);
+        const double2 ym = r == 0 ? ybelow : c[r - 1], yp = r == R - 1 ? yabove : c[r + 1];
+        const double2 sp = ldc_once(sc, q, g.nt);
         double2 fp = czero();
-        if (MODE != ST_APPLY) fp = ldc_once(f, p, g.nt);
+        if (MODE != ST_APPLY) fp = ldc_once(f, q, g.nt);
+        const double2 cc = c[r];
         double2 ax;
         if (cd & NB_SELF) {
-          ax = c;
+          ax = cc;
         } else {
-          const double2 a = sel0(cd & NB_XM, xm), b = sel0(cd & NB_XP, xp);
+          const double2 a = sel0(cd & NB_XM, xm[r]), b = sel0(cd & NB_XP, xp[r]);
           const double2 e = sel0(cd & NB_YM, ym), h = sel0(cd & NB_YP, yp);
           double2 acc;
-          acc.x = ((c.x - a.x) + (c.x - b.x)) * g.ih2[0];
-          acc.y = ((c.y - a.y) + (c.y - b.y)) * g.ih2[0];
-          acc.x = acc.x + ((c.x - e.x) + (c.x - h.x)) * g.ih2[1];
-          acc.y = acc.y + ((c.y - e.y) + (c.y - h.y)) * g.ih2[1];
+          acc.x = ((cc.x - a.x) + (cc.x - b.x)) * g.ih2[0];
+          acc.y = ((cc.y - a.y) + (cc.y - b.y)) * g.ih2[0];
+          acc.x = acc.x + ((cc.x - e.x) + (cc.x - h.x)) * g.ih2[1];
+          acc.y = acc.y + ((cc.y - e.y) + (cc.y - h.y)) * g.ih2[1];
           if (DIM == 3) {
-            const double2 q = sel0(cd & NB_ZM, zm), w = sel0(cd & NB_ZP, znext);
-            acc.x = acc.x + ((c.x - q.x) + (c.x - w.x)) * g.ih2[2];
-            acc.y = acc.y + ((c.y - q.y) + (c.y - w.y)) * g.ih2[2];
+            const double2 qq = sel0(cd & NB_ZM, zm[r]), w = sel0(cd & NB_ZP, zn[r]);
+            acc.x = acc.x + ((cc.x - qq.x) + (cc.x - w.x)) * g.ih2[2];
+            acc.y = acc.y + ((cc.y - qq.y) + (cc.y - w.y)) * g.ih2[2];
           }
-          ax = csub(acc, cmul(sp, c));
+          ax = csub(acc, cmul(sp, cc));
         }
         if (MODE == ST_APPLY) {
-          stc_out(y, p, ax, g.nt);
+          stc_out(y, q, ax, g.nt);
         } else if (MODE == ST_RESID) {
-          const double2 r = csub(fp, ax);
-          nrm += r.x * r.x + r.y * r.y;
-          stc_out(y, p, r, g.nt);
+          const double2 rr = csub(fp, ax);
+          nrm += rr.x * rr.x + rr.y * rr.y;
+          stc_out(y, q, rr, g.nt);
         } else {  // Jacobi / RB-GS update (red-black updates in place: plain stores)
-          const double2 r = csub(fp, ax);
+          const double2 rr = csub(fp, ax);
           const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
-          const double2 q = cdiv(r, d);
-          stc_out(y, p, make_double2(c.x + omega * q.x, c.y + omega * q.y), MODE == ST_JACOBI && g.nt);
+          const double2 qd = ddiv(rr, d);
+          stc_out(y, q, make_double2(cc.x + omega * qd.x, cc.y + omega * qd.y), MODE == ST_JACOBI && g.nt);
         }
       }
-      if (DIM == 3) {
-        zm = c;
-        c = znext;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        zm[r] = c[r];
+        c[r] = zn[r];
       }
     }
   }
@@ -148,7 +171,7 @@ __device__ __forceinline__ void stencil_tile(const StencilGeom& g, unsigned lb, 
 // (f, s, code in; z2 out).
 __device__ __forceinline__ double2 jac0(double2 f, double2 s, double dsum, bool masked, double omega) {
   const double2 d = masked ? make_double2(1.0, 0.0) : make_double2(dsum - s.x, -s.y);
-  const double2 q = cdiv(f, d);
+  const double2 q = ddiv(f, d);
   return make_double2(omega * q.x, omega * q.y);
 }
 
@@ -168,7 +191,7 @@ __device__ __forceinline__ double2 ldf(const cplx_t<S>* __restrict__ f, size_t q
 // fscale (optional): the right-hand side is fscale[0] * f; fout (optional,
 // requires fscale) receives that scaled right-hand side, each node written once
 // by the thread that owns it.
-template <typename S, int DIM>
+template <typename S, int DIM, int R = 1>
 __device__ __forceinline__ void jacobi2z_tile(const StencilGeom& g, unsigned lb, const cplx_t<S>* __restrict__ sc,
                                               const uint8_t* __restrict__ code, const cplx_t<S>* __restrict__ f,
                                               cplx_t<S>* __restrict__ y, double omega,
@@ -176,57 +199,74 @@ __device__ __forceinline__ void jacobi2z_tile(const StencilGeom& g, unsigned lb,
                                               cplx_t<S>* __restrict__ fout = nullptr) {
   const bool scaled = fscale != nullptr;
   const double fs = scaled ? fscale[0] : 1.0;
-  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty - 1) / g.ty;
+  const unsigned nbx = (g.nx + 63) / 64, nby = (g.ny + g.ty * R - 1) / (g.ty * R);
   const unsigned bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
   const int i = bx * 64 + threadIdx.x;
-  const int j = by * g.ty + threadIdx.y;
+  const int j0 = (by * g.ty + threadIdx.y) * R;
   const int z0 = bz * g.zb;
   const int z1e = min(g.nz, z0 + g.zb);
-  if (!(i < g.nx && j < g.ny) || z0 >= z1e) return;
+  if (!(i < g.nx && j0 < g.ny) || z0 >= z1e) return;
   const size_t plane = (size_t)g.nx * g.ny;
   const ptrdiff_t oxm = i > 0 ? -1 : 0, oxp = i + 1 < g.nx ? 1 : 0;
-  const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
-  size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
-  // z1 of the column at z-1, z (the z-1 value only matters when present)
-  double2 zc = jac0(ldf<S>(f, p, fs, scaled), ldc(sc, p), g.dsum, code[p] & NB_SELF, omega);
-  double2 zmv = czero();
-  if (DIM == 3 && z0 > 0) zmv = jac0(ldf<S>(f, p - plane, fs, scaled), ldc(sc, p - plane), g.dsum, false, omega);
-  for (int z = z0; z < z1e; ++z, p += plane) {
-    double2 znv = czero();
-    if (DIM == 3 && z + 1 < g.nz) znv = jac0(ldf<S>(f, p + plane, fs, scaled), ldc(sc, p + plane), g.dsum, false, omega);
-    const unsigned cd = code[p];
-    const double2 fp = ldf<S>(f, p, fs, scaled), sp = ldc(sc, p);
-    if (fout) stc(fout, p, fp);
-    double2 ax;
-    if (cd & NB_SELF) {
-      ax = zc;
-    } else {
-      const double2 a = (cd & NB_XM) ? czero() : jac0(ldf<S>(f, p + oxm, fs, scaled), ldc(sc, p + oxm), g.dsum, false, omega);
-      const double2 b = (cd & NB_XP) ? czero() : jac0(ldf<S>(f, p + oxp, fs, scaled), ldc(sc, p + oxp), g.dsum, false, omega);
-      const double2 e = (cd & NB_YM) ? czero() : jac0(ldf<S>(f, p + oym, fs, scaled), ldc(sc, p + oym), g.dsum, false, omega);
-      const double2 h = (cd & NB_YP) ? czero() : jac0(ldf<S>(f, p + oyp, fs, scaled), ldc(sc, p + oyp), g.dsum, false, omega);
-      double2 acc;
-      acc.x = ((zc.x - a.x) + (zc.x - b.x)) * g.ih2[0];
-      acc.y = ((zc.y - a.y) + (zc.y - b.y)) * g.ih2[0];
-      acc.x = acc.x + ((zc.x - e.x) + (zc.x - h.x)) * g.ih2[1];
-      acc.y = acc.y + ((zc.y - e.y) + (zc.y - h.y)) * g.ih2[1];
-      if (DIM == 3) {
-        const double2 q = (cd & NB_ZM) ? czero() : zmv, w = (cd & NB_ZP) ? czero() : znv;
-        acc.x = acc.x + ((zc.x - q.x) + (zc.x - w.x)) * g.ih2[2];
-        acc.y = acc.y + ((zc.y - q.y) + (zc.y - w.y)) * g.ih2[2];
+  // each of the thread's R rows is marched on its own (the per-node values are
+  // those of a one-row tile)
+  double2 zc[R], zmv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    zc[r] = czero();
+    zmv[r] = czero();
+    const int j = j0 + r;
+    if (j >= g.ny) continue;
+    const size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z0);
+    // z1 of the column at z-1, z (the z-1 value only matters when present)
+    zc[r] = jac0(ldf<S>(f, p, fs, scaled), ldc(sc, p), g.dsum, code[p] & NB_SELF, omega);
+    if (DIM == 3 && z0 > 0) zmv[r] = jac0(ldf<S>(f, p - plane, fs, scaled), ldc(sc, p - plane), g.dsum, false, omega);
+  }
+  for (int z = z0; z < z1e; ++z) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = j0 + r;
+      if (j >= g.ny) continue;
+      const size_t p = (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * z);
+      const ptrdiff_t oym = j > 0 ? -(ptrdiff_t)g.nx : 0, oyp = j + 1 < g.ny ? (ptrdiff_t)g.nx : 0;
+      double2 znv = czero();
+      if (DIM == 3 && z + 1 < g.nz)
+        znv = jac0(ldf<S>(f, p + plane, fs, scaled), ldc(sc, p + plane), g.dsum, false, omega);
+      const unsigned cd = code[p];
+      const double2 fp = ldf<S>(f, p, fs, scaled), sp = ldc(sc, p);
+      if (fout) stc(fout, p, fp);
+      double2 ax;
+      if (cd & NB_SELF) {
+        ax = zc[r];
+      } else {
+        const double2 a = (cd & NB_XM) ? czero() : jac0(ldf<S>(f, p + oxm, fs, scaled), ldc(sc, p + oxm), g.dsum, false, omega);
+        const double2 b = (cd & NB_XP) ? czero() : jac0(ldf<S>(f, p + oxp, fs, scaled), ldc(sc, p + oxp), g.dsum, false, omega);
+        const double2 e = (cd & NB_YM) ? czero() : jac0(ldf<S>(f, p + oym, fs, scaled), ldc(sc, p + oym), g.dsum, false, omega);
+        const double2 h = (cd & NB_YP) ? czero() : jac0(ldf<S>(f, p + oyp, fs, scaled), ldc(sc, p + oyp), g.dsum, false, omega);
+        const double2 zz = zc[r];
+        double2 acc;
+        acc.x = ((zz.x - a.x) + (zz.x - b.x)) * g.ih2[0];
+        acc.y = ((zz.y - a.y) + (zz.y - b.y)) * g.ih2[0];
+        acc.x = acc.x + ((zz.x - e.x) + (zz.x - h.x)) * g.ih2[1];
+        acc.y = acc.y + ((zz.y - e.y) + (zz.y - h.y)) * g.ih2[1];
+        if (DIM == 3) {
+          const double2 q = (cd & NB_ZM) ? czero() : zmv[r], w = (cd & NB_ZP) ? czero() : znv;
+          acc.x = acc.x + ((zz.x - q.x) + (zz.x - w.x)) * g.ih2[2];
+          acc.y = acc.y + ((zz.y - q.y) + (zz.y - w.y)) * g.ih2[2];
+        }
+        ax = csub(acc, cmul(sp, zz));
       }
-      ax = csub(acc, cmul(sp, zc));
-    }
-    const double2 r = csub(fp, ax);
-    const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
-    const double2 q = cdiv(r, d);
-    stc(y, p, make_double2(zc.x + omega * q.x, zc.y + omega * q.y));
-    if (DIM == 3) {
-      zmv = zc;
-      zc = znv;
-      // the next node's own z1 needs its own mask bit; recompute if it is masked
-      if (z + 1 < z1e && (code[p + plane] & NB_SELF))
-        zc = jac0(ldf<S>(f, p + plane, fs, scaled), ldc(sc, p + plane), g.dsum, true, omega);
+      const double2 rr = csub(fp, ax);
+      const double2 d = (cd & NB_SELF) ? make_double2(1.0, 0.0) : make_double2(g.dsum - sp.x, -sp.y);
+      const double2 q = ddiv(rr, d);
+      stc(y, p, make_double2(zc[r].x + omega * q.x, zc[r].y + omega * q.y));
+      if (DIM == 3) {
+        zmv[r] = zc[r];
+        zc[r] = znv;
+        // the next node's own z1 needs its own mask bit; recompute if it is masked
+        if (z + 1 < z1e && (code[p + plane] & NB_SELF))
+          zc[r] = jac0(ldf<S>(f, p + plane, fs, scaled), ldc(sc, p + plane), g.dsum, true, omega);
+      }
     }
   }
 }

@@ -189,10 +189,13 @@ def test_relaxation_fallback_forced_count(kind):
 def test_relaxation_fallback_after_growth():
     """Plain damped Jacobi on config 1 contracts for 200 sweeps and then grows
     (k^2 above the smallest eigenvalue): the fallback restarts from the
-    200-sweep iterate; forced count against the oracle."""
-    C, s, u, st, stats, u_or, info = _c1_fallback("jacobi", False, 400, 0.0)
+    200-sweep iterate; forced count against the oracle.  The budget (250
+    sweeps, then 250 GMRES(30) steps) keeps the field comparison meaningful:
+    perturbing f by 1e-16 moves the oracle itself by up to 5e-11 here, and by
+    up to 1.8e-10 with a 400-step budget."""
+    C, s, u, st, stats, u_or, info = _c1_fallback("jacobi", False, 250, 0.0)
     assert info["iters"] == stats["iters"] == 225
-    assert info["fallback_iters"] == stats["fallback_iters"] == 400
+    assert info["fallback_iters"] == stats["fallback_iters"] == 250
     assert rel_err(to_np(u), u_or) <= FIELD_TOL[helm.C128]
 
 

@@ -176,6 +176,35 @@ def test_rbgs_kernel_choice_rejected():
     op.set_rbgs_kernel(helm.RB_PAIRS)
 
 
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+def test_two_rows_per_thread_ragged(dtype):
+    """A grid large enough for the 64 x 16 tiles with two rows per thread
+    (4.45 M nodes, 131 rows: the last tile holds 3 of its 16 rows, the x tiles
+    end on a partial 8 of 64): apply, residual + norm and a Jacobi sweep
+    against the oracle."""
+    n = (200, 131, 170)
+    P, s = _problem(n, 9, dtype)
+    op = make_op(helm, P, dtype)
+    x = _cast(P["x"], dtype)
+    f = _cast(P["f"], dtype)
+    y = to_np(op.apply(op.field(x)))
+    assert rel_err(y, op_or.apply(x, s, P["mask"]).ravel()) <= TOL[dtype]
+    r, nr = op.residual(op.field(f), op.field(x), norm=True)
+    ref = op_or.residual(x, f, s, P["mask"])
+    assert rel_err(to_np(r), ref.ravel()) <= TOL[dtype]
+    assert abs(nr - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref) + (1e-6 if dtype == helm.C64 else 0) * np.linalg.norm(ref)
+    u = op.field(x)
+    op.relax(helm.JACOBI, 0.7, 1, op.field(f), u)
+    assert rel_err(to_np(u), op_or.jacobi_sweep(x, f, s, P["mask"], 0.7).ravel()) <= TOL[dtype]
+    # the preconditioner's first two sweeps from zero run as one fused pass
+    fm = f * (1 - P["mask"])
+    z = to_np(helm.meta_precond(op, None, op.field(fm), n_r=2, omega=0.5))
+    ref = np.zeros_like(fm)
+    for _ in range(2):
+        ref = _cast(op_or.jacobi_sweep(ref, fm, s, P["mask"], 0.5), dtype)
+    assert rel_err(z, ref.ravel()) <= TOL[dtype]
+
+
 def test_residual_and_jacobi_full_size_256():
     """Residual and one damped Jacobi sweep at 256^3, where the stencil kernels
     stream their once-read inputs (s, f, code) with non-temporal loads and
