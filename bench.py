@@ -134,7 +134,7 @@ def main():
     global TRUNK
     TRUNK = args.trunk
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the solver path has no multi-GPU implementation",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

@@ -76,6 +76,7 @@ def dataset(helm, I, torch, n_samples, n=(48, 48, 48), instance=0, chunk=512, ne
         for op in ops:
             op.close()
         del ops, us, fs
+        log(f"labels {c1}/{n_samples}: {secs:.1f} s of solves")
     del f
     rec = {"solves": n_samples, "seconds": round(secs, 2), "iters_min": int(min(iters)), "iters_max": int(max(iters)),
            "converged": int(conv)}
