@@ -301,6 +301,7 @@ def main():
     if not args.no_compare:
         log("per-instance comparison with standalone Krylov")
         out["compare"] = compare(helm, torch, insts, n, net, seeded, solve_kw, u[helm.C128])
+    out["paper"] = PAPER_CONTEXT
 
     if not args.no_stencil:
         log(f"stencil bandwidth at {args.stencil_n}^3")
@@ -369,6 +370,25 @@ def compare(helm, torch, insts, n, net, seeded, solve_kw, u):
             "time_ratio_min": min(r["time_ratio_vs_gmres"] for r in rows),
             "timing": "wall time of the meta_solve call on an existing operator; the meta-solvers' coarse "
                       "set-up (trunk evaluation, QR, Galerkin matrix) is inside it"}
+
+
+# The paper's own iteration counts and times for the same method, quoted with
+# the hardware they were measured on (context, not targets: FEM meshes,
+# variable k, PETSc on the CPU and a PyTorch DeepONet).
+PAPER_CONTEXT = {
+    "hardware": "AMD EPYC 9554 64-core CPU (PETSc solvers, C/C++) and an NVIDIA L40S (PyTorch DeepONet)",
+    "section_4_1_cube": {
+        "workload": "cube scatterer of side 0.125 at the centre of [0,1]^3, 33^3 quasi-uniform FEM mesh, "
+                    "k a GRF of mean 6, DeepONet trained on 17^3 non-scattering problems",
+        "gmres_iters": 832, "deeponet_gmres_iters": 58, "bicgstab_iters": 483, "deeponet_bicgstab_iters": 30,
+        "iteration_ratio_gmres": round(832 / 58, 1), "iteration_ratio_bicgstab": round(483 / 30, 1)},
+    "table_1_submarine": {
+        "workload": "submarine scatterer, 40^3 mesh, DeepONet trained at mean k 6, p = 32, one relaxation "
+                    "step per network call; columns: iterations and seconds",
+        "k": [6, 12, 18, 24, 30, 36],
+        "bicgstab": [[758, 2.62], [2178, 7.48], [1922, 6.51], [1716, 5.53], [1635, 4.87], [1308, 4.18]],
+        "deeponet_bicgstab": [[36, 0.43], [84, 0.91], [171, 1.69], [219, 2.23], [282, 2.91], [397, 4.25]]},
+}
 
 
 # algorithmic HBM bytes per node of one DeepONet-BiCGStab iteration (complex128,
