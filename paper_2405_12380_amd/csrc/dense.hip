@@ -195,14 +195,22 @@ __global__ void k_small_final(int B, int N, int ksplit, const double* __restrict
 // ---- tall-skinny weighted Gram: C = X^T diag(w) Y (X, Y: n x r, r <= 128) -------
 // Each workgroup reduces a contiguous range of rows into a full 128 x 128 tile
 // (four wavefronts of 64 x 64, 4 x 4 MFMA tiles each); rows are staged 16 at a
-// time through LDS.  part[b] receives the block's r x r partial.
+// time through LDS.  part[b] receives the block's r x r partial.  MODE:
+// GRAM_XY (X^T Y), GRAM_XWY (X^T diag(w) Y), GRAM_XX (X^T X: Y is X and is
+// neither loaded nor staged a second time), GRAM_XWX (X^T diag(w) X: X staged
+// once, the weights applied to the second operand as it is read from LDS).
 constexpr int GR_ROWS = 16;
-__global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __restrict__ X, size_t ldx,
+enum { GRAM_XY = 0, GRAM_XWY = 1, GRAM_XX = 2, GRAM_XWX = 3 };
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram(size_t n, int r,
+                                              const double* __restrict__ X, size_t ldx,
                                               const double* __restrict__ Y, size_t ldy,
                                               const double* __restrict__ w, size_t rows_per_block,
                                               double* __restrict__ part) {
+  constexpr bool SYM = MODE == GRAM_XX || MODE == GRAM_XWX, SW = MODE == GRAM_XWX;
   __shared__ double Xs[GR_ROWS][128 + 1];
-  __shared__ double Ys[GR_ROWS][128 + 1];
+  __shared__ double Ys[SYM ? 1 : GR_ROWS][128 + 1];
+  __shared__ double ws[GR_ROWS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wa = (wave >> 1) * 64, wb = (wave & 1) * 64;
   const size_t i0 = (size_t)blockIdx.x * rows_per_block;
@@ -210,35 +218,43 @@ __global__ __launch_bounds__(256) void k_gram(size_t n, int r, const double* __r
   d4 acc[4][4];
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  // 16 rows x 128 columns of X and Y per chunk; the next chunk's loads are in
+  // 16 rows x 128 columns of X (and Y) per chunk; the next chunk's loads are in
   // flight while the current one is multiplied
-  double xv[GR_ROWS * 128 / 256], yv[GR_ROWS * 128 / 256];
+  constexpr int NQ = GR_ROWS * 128 / 256;
+  double xv[NQ], yv[SYM ? 1 : NQ], wv = 0.0;
   auto load = [&](size_t ib) {
+    if (SW && t < GR_ROWS) wv = ib + t < i1 ? w[ib + t] : 0.0;
 #pragma unroll
-    for (int q = 0; q < GR_ROWS * 128 / 256; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int e = t + 256 * q, rr = e >> 7, cc = e & 127;
       const size_t gi = ib + rr;
       const bool in = gi < i1 && cc < r;
       xv[q] = in ? X[gi * ldx + cc] : 0.0;
-      yv[q] = in ? Y[gi * ldy + cc] : 0.0;
-      if (in && w) yv[q] *= w[gi];
+      if (!SYM) {
+        yv[q] = in ? Y[gi * ldy + cc] : 0.0;
+        if (MODE == GRAM_XWY && in) yv[q] *= w[gi];
+      }
     }
   };
   if (i0 < i1) load(i0);
   for (size_t ib = i0; ib < i1; ib += GR_ROWS) {
 #pragma unroll
-    for (int q = 0; q < GR_ROWS * 128 / 256; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int e = t + 256 * q, rr = e >> 7, cc = e & 127;
       Xs[rr][cc] = xv[q];
-      Ys[rr][cc] = yv[q];
+      if (!SYM) Ys[rr][cc] = yv[q];
     }
+    if (SW && t < GR_ROWS) ws[t] = wv;
     __syncthreads();
     if (ib + GR_ROWS < i1) load(ib + GR_ROWS);
 #pragma unroll
     for (int kk = 0; kk < GR_ROWS; kk += 4) {
       double av[4], bv[4];
       for (int a = 0; a < 4; ++a) av[a] = Xs[kk + (lane >> 4)][wa + a * 16 + (lane & 15)];
-      for (int b = 0; b < 4; ++b) bv[b] = Ys[kk + (lane >> 4)][wb + b * 16 + (lane & 15)];
+      for (int b = 0; b < 4; ++b)
+        bv[b] = SYM ? Xs[kk + (lane >> 4)][wb + b * 16 + (lane & 15)] : Ys[kk + (lane >> 4)][wb + b * 16 + (lane & 15)];
+      if (SW)
+        for (int b = 0; b < 4; ++b) bv[b] *= ws[kk + (lane >> 4)];
       for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
     }
@@ -286,9 +302,10 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
                                                     double* __restrict__ S, int* __restrict__ info) {
   extern __shared__ double G[];  // p x p
   __shared__ double xdiag[128];
+  __shared__ double pivs[128];  // sqrt of column j's pivot, or -1 where the column is dropped
   __shared__ int kept[128];
-  __shared__ int s_nk, s_fail;
-  __shared__ double s_piv, s_thr2;
+  __shared__ int s_fail;
+  __shared__ double s_thr2;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int e0 = 0; e0 < p * p; e0 += 4 * nt) {  // four loads in flight per thread
     double v[4];
@@ -300,7 +317,6 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
   }
   __syncthreads();
   if (t == 0) {
-    s_nk = 0;
     s_fail = 0;
     double mx = 0.0;  // largest squared column norm of P
     for (int j = 0; j < p; ++j) mx = fmax(mx, G[j * p + j]);
@@ -308,37 +324,50 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
   }
   __syncthreads();
   const double thr2 = s_thr2;
+  // One barrier per column.  Step j reads row j unscaled (R[j][c] = G[j][c] /
+  // piv is formed where it is used, as G[j][c] times the pivot's reciprocal,
+  // the same product the scaled row holds) and scales row j - 1, which no
+  // thread reads in step j.  Every thread takes the drop decision of column j
+  // itself from G[j][j] (final after step j - 1), so all of them count the
+  // kept columns alike.
+  int nk = 0;
   for (int j = 0; j < p; ++j) {
-    if (t == 0) {
-      const double dj = G[j * p + j];
-      if (!(dj > thr2)) {
-        s_piv = -1.0;
-        if (!allow_drop) s_fail = 1;
-      } else {
-        s_piv = sqrt(dj);
-        kept[s_nk] = j;
-        s_nk = s_nk + 1;
+    if (j > 0) {
+      const double pv = pivs[j - 1];
+      if (pv > 0.0) {
+        const double pinv = 1.0 / pv;
+        for (int c = j - 1 + t; c < p; c += nt) G[(j - 1) * p + c] = (c == j - 1) ? pv : G[(j - 1) * p + c] * pinv;
       }
     }
-    __syncthreads();
-    const double piv = s_piv;
-    if (piv > 0.0) {
-      for (int c = j + t; c < p; c += nt) G[j * p + c] = (c == j) ? piv : G[j * p + c] / piv;
-      __syncthreads();
+    const double dj = G[j * p + j];
+    const bool keep = dj > thr2;
+    const double piv = keep ? sqrt(dj) : -1.0;
+    if (t == 0) {
+      pivs[j] = piv;
+      if (keep) kept[nk] = j;
+      else if (!allow_drop) s_fail = 1;
+    }
+    if (keep) {
+      ++nk;
+      const double pinv = 1.0 / piv;
       // trailing update of the upper triangle: G[a][c] -= R[j][a] R[j][c], j < a <= c
       // (a 32 x 32 thread grid: rows a = j + 1 + ty + 32 u, columns c = a + tx + 32 v)
       for (int a = j + 1 + (t >> 5); a < p; a += nt >> 5) {
-        const double ra = G[j * p + a];
-        for (int c = a + (t & 31); c < p; c += 32) G[a * p + c] -= ra * G[j * p + c];
+        const double ra = G[j * p + a] * pinv;
+        for (int c = a + (t & 31); c < p; c += 32) G[a * p + c] -= ra * (G[j * p + c] * pinv);
       }
     }
     __syncthreads();
   }
-  const int r = s_nk;
+  if (t == 0 && pivs[p - 1] > 0.0) G[(p - 1) * p + (p - 1)] = pivs[p - 1];
+  __syncthreads();
+  const int r = nk;
   // X = R1^{-1}, R1[a][b] = G[kept[a]][kept[b]] (a <= b).  X[a][b] (a < b) is kept
   // at G[kept[b]][kept[a]] (strictly lower, unused by R), X[a][a] in xdiag.
   // Rows a = r-1 .. 0 in turn; column b of row a is formed by the 8 threads
   // 8b .. 8b+7, which split the sum over c and combine it with three shuffles.
+  // Column b only reads its own earlier entries, written by the same 8 threads
+  // of one wavefront, so the steps are ordered within the wavefront alone.
   {
     const int b = t >> 3, sub = t & 7;
     const bool colb = b < r && (t >> 3) < (nt >> 3);
@@ -357,9 +386,11 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
         if (a == b) xdiag[b] = v;
         else G[kept[b] * p + kept[a]] = v;
       }
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
   }
+  __syncthreads();
   for (int e = t; e < p * r; e += nt) S[e] = 0.0;
   __syncthreads();
   for (int e = t; e < r * r; e += nt) {
@@ -592,8 +623,9 @@ void dense_small(int B, int N, int K, const T* x, const T* W, const T* bias, int
 }
 
 int gram_nblocks(size_t n) {
-  size_t nb = (n + 1023) / 1024;
-  if (nb > 256) nb = 256;
+  // two workgroups per CU (the MFMA pipe needs two wavefronts per SIMD)
+  size_t nb = (n + 511) / 512;
+  if (nb > 512) nb = 512;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
@@ -604,7 +636,14 @@ void gram(size_t n, int r, const double* X, size_t ldx, const double* Y, size_t 
   size_t rpb = (n + nb - 1) / nb;
   rpb = (rpb + GR_ROWS - 1) / GR_ROWS * GR_ROWS;
   kprof_begin(KP_MFMA, st);
-  hipLaunchKernelGGL(k_gram, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
+  if (w && X == Y && ldx == ldy)
+    hipLaunchKernelGGL(k_gram<GRAM_XWX>, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
+  else if (w)
+    hipLaunchKernelGGL(k_gram<GRAM_XWY>, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
+  else if (X == Y && ldx == ldy)
+    hipLaunchKernelGGL(k_gram<GRAM_XX>, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
+  else
+    hipLaunchKernelGGL(k_gram<GRAM_XY>, dim3(nb), dim3(256), 0, st, n, r, X, ldx, Y, ldy, w, rpb, part);
   kprof_end(KP_MFMA, 2.0 * (double)n * r * r, st);
   const size_t width = (size_t)r * r;
   hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, part, nb, width, out,
