@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=16, help="timed solves (the 8 instances in turn)")
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--n", type=int, default=64, help="grid nodes per axis of the solve workload")
+    ap.add_argument("--gs-passes", type=int, choices=(1, 2), default=1,
+                    help="classical Gram-Schmidt passes per GMRES step, for the meta-solver and the standalone "
+                         "GMRES alike (1: the default of PETSc's GMRES; 2: CGS2)")
     ap.add_argument("--trunk", choices=("trained", "seeded"), default="trained",
                     help="headline trunk: the trained 48^3 trunk (package weights) or the seeded gain-30 one")
     ap.add_argument("--stencil-n", type=int, default=256, help="grid nodes per axis of the bandwidth runs")
@@ -162,7 +165,7 @@ def main():
     u = {helm.C128: torch.zeros(nn, dtype=torch.complex128, device=dev),
          helm.C64: torch.zeros(nn, dtype=torch.complex64, device=dev)}
     solve_kw = dict(kind="gmres", restart=50, tol=1e-6, max_iters=5000, n_r=3, omega=0.5, p_used=128,
-                    q_fp32=args.q_fp32)
+                    q_fp32=args.q_fp32, gs_passes=args.gs_passes)
 
     def step(i, nt=None, dtype=helm.C128, allow=False, **over):
         """One timed unit: operator set-up, trunk evaluation, coarse space and
@@ -251,7 +254,8 @@ def main():
            "config": {"workload": f"3D {n[0]}^3 Helmholtz scattering, DeepONet-GMRES(50) with the p=128 basis of "
                                   f"the {args.trunk} trunk (Jacobi n_r=3, omega 0.5) to 1e-6, operator and coarse "
                                   f"set-up included; 8 seeded instances in turn",
-                      "grid": list(n), "restart": 50, "p_used": 128, "n_r": 3, "tol": 1e-6, "trunk": args.trunk},
+                      "grid": list(n), "restart": 50, "p_used": 128, "n_r": 3, "tol": 1e-6, "trunk": args.trunk,
+                      "gram_schmidt_passes": args.gs_passes},
            "iters": [s["iters"] for s in stats[:8]],
            "iters_mean": float(np.mean([s["iters"] for s in stats])),
            "setup_ms_mean": round(float(np.mean([s["setup_ms"] for s in stats])), 3),

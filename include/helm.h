@@ -310,6 +310,12 @@ typedef struct {
                       (M = I) runs from it to tol within max_iters Arnoldi steps;
                       its steps are reported in fallback_iters and its status
                       is the call's.  Costs one field copy per cycle.            */
+  int gs_passes;   /* META_GMRES (and the fallback GMRES): classical Gram-Schmidt
+                      passes per Arnoldi step.  0 or 2 = CGS2 (the new vector is
+                      projected out of the basis twice); 1 = one projection, the
+                      default orthogonalization of PETSc's GMRES, whose solvers
+                      the paper's experiments used (section 4): one pass over
+                      the basis fewer per step.                                  */
 } meta_opts;
 
 typedef struct {
@@ -325,7 +331,8 @@ typedef struct {
 /* Solve A u = f.
  *   META_JACOBI / META_GS: eq. 3 with M1 = nn_every smoother sweeps and M2 = the
  *     network correction (DON_FULL) when net != NULL; plain relaxation otherwise.
- *   META_GMRES / META_BICGSTAB: right-preconditioned GMRES(restart) with CGS2, or
+ *   META_GMRES / META_BICGSTAB: right-preconditioned GMRES(restart) with classical
+ *     Gram-Schmidt (gs_passes), or
  *     BiCGStab, on the true relative residual.  With net != NULL the
  *     preconditioner is M(r) = eq. 3 from z = 0: n_r smoother sweeps on A z = r,
  *     then z += Q A_c^{-1} Q^T (r - A z) where Q spans the first p_used masked

@@ -47,11 +47,16 @@ def back_substitute(H, g, k):
     return y
 
 
-def gmres(A, f, u0, restart, tol, max_iters, M=None, history=None):
-    """Restarted, right-preconditioned GMRES(m) with CGS2.
+def gmres(A, f, u0, restart, tol, max_iters, M=None, history=None, gs_passes=2):
+    """Restarted, right-preconditioned GMRES(m).  The new Arnoldi vector is
+    orthogonalized by classical Gram-Schmidt: gs_passes = 2 projects twice
+    (CGS2, one full re-orthogonalization), gs_passes = 1 once (the default of
+    PETSc's GMRES, the solver library of the paper's experiments, section 4).
 
     Returns (u, info) with info = dict(status, iters, rel_res, matvecs,
     precond_apps)."""
+    if gs_passes not in (1, 2):
+        raise ValueError("gs_passes must be 1 or 2")
     has_m = M is not None
     M = M or _identity
     f = np.asarray(f, dtype=np.complex128)
@@ -90,9 +95,10 @@ def gmres(A, f, u0, restart, tol, max_iters, M=None, history=None):
             Vj = V[: j + 1]
             h = Vj.conj() @ w
             w = w - Vj.T @ h
-            h2 = Vj.conj() @ w
-            w = w - Vj.T @ h2
-            h = h + h2
+            if gs_passes == 2:
+                h2 = Vj.conj() @ w
+                w = w - Vj.T @ h2
+                h = h + h2
             hn = np.linalg.norm(w)
             H[: j + 1, j] = h
             H[j + 1, j] = hn

@@ -34,7 +34,7 @@ def sweep(kind, u, f, s, mask, omega):
 
 
 def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, correction=None,
-                    history=None, fallback_restart=0):
+                    history=None, fallback_restart=0, gs_passes=2):
     """eq. 3 with M1 = nn_every sweeps and M2 = ``correction(r)`` (or none).
 
     Krylov fallback (reading: the paper observes plain relaxation diverging on
@@ -42,7 +42,8 @@ def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, corr
     method): with ``fallback_restart = m >= 1``, a cycle that ends with a
     relative residual larger than the one before it (that of u0 for the first
     cycle) or not finite is undone, and standalone GMRES(m) runs from the
-    iterate before it, to ``tol`` within ``max_sweeps`` Arnoldi steps.
+    iterate before it, to ``tol`` within ``max_sweeps`` Arnoldi steps
+    (``gs_passes`` classical Gram-Schmidt passes per step).
 
     Returns (u, info); info["fallback_iters"] counts the fallback's steps."""
     u = np.array(u0, dtype=np.complex128)
@@ -80,7 +81,7 @@ def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, corr
     if diverged:
         shape = np.shape(f)
         u, info = krylov.gmres(lambda v: op.apply(v.reshape(shape), s, mask).ravel(), np.ravel(f),
-                               np.ravel(keep), fallback_restart, tol, max_sweeps)
+                               np.ravel(keep), fallback_restart, tol, max_sweeps, gs_passes=gs_passes)
         u = u.reshape(shape)
         status, fb_iters = info["status"], info["iters"]
     rel = np.linalg.norm(op.residual(u, f, s, mask)) / fn if fn > 0 else 0.0
@@ -111,8 +112,9 @@ def krylov_preconditioner(s, mask, smoother, n_r, omega, coarse: CoarseSpace | N
     return M
 
 
-def krylov_meta(kind, f, u0, s, mask, restart, tol, max_iters, precond=None, history=None):
-    """GMRES(m) or BiCGStab on A u = f, right-preconditioned by ``precond``."""
+def krylov_meta(kind, f, u0, s, mask, restart, tol, max_iters, precond=None, history=None, gs_passes=2):
+    """GMRES(m) or BiCGStab on A u = f, right-preconditioned by ``precond``
+    (``gs_passes``: GMRES's classical Gram-Schmidt passes, 1 or 2)."""
     shape = np.shape(f)
 
     def A(v):
@@ -120,7 +122,8 @@ def krylov_meta(kind, f, u0, s, mask, restart, tol, max_iters, precond=None, his
     ff = np.asarray(f, dtype=np.complex128).ravel()
     u0f = np.asarray(u0, dtype=np.complex128).ravel()
     if kind == "gmres":
-        u, info = krylov.gmres(A, ff, u0f, restart, tol, max_iters, M=precond, history=history)
+        u, info = krylov.gmres(A, ff, u0f, restart, tol, max_iters, M=precond, history=history,
+                               gs_passes=gs_passes)
     elif kind == "bicgstab":
         u, info = krylov.bicgstab(A, ff, u0f, tol, max_iters, M=precond, history=history)
     else:

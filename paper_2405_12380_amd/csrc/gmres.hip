@@ -27,7 +27,8 @@ __device__ static inline double lane_read(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One wavefront: the new column (CGS2 coefficients h1 + h2) and the previous
+// One wavefront: the new column (CGS2 coefficients h1 + h2, or h1 alone when h2
+// is NULL) and the previous
 // rotations are staged in LDS and, for the first 64 rows, in the lanes'
 // registers; lane 0 applies the rotations (inherently sequential), and the
 // column is written back in parallel.
@@ -51,9 +52,10 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
     for (int q = 0; q < 16; ++q) ns += v[q];
   }
   ns = wave_sum(ns);
+  // h2 == NULL: one Gram-Schmidt pass, the column is h1 alone
   for (int i = l; i <= j; i += 64) {
-    col[2 * i] = h1[2 * i] + h2[2 * i];
-    col[2 * i + 1] = h1[2 * i + 1] + h2[2 * i + 1];
+    col[2 * i] = h2 ? h1[2 * i] + h2[2 * i] : h1[2 * i];
+    col[2 * i + 1] = h2 ? h1[2 * i + 1] + h2[2 * i + 1] : h1[2 * i + 1];
   }
   for (int i = l; i < j; i += 64) {
     rc[i] = cs[i];
@@ -62,8 +64,10 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
   }
   // lane q also keeps entry q + 1 of the column and rotation q in registers:
   // the first 64 steps of the rotation chain read them with v_readlane
-  double2 bq = l + 1 <= j ? make_double2(h1[2 * (l + 1)] + h2[2 * (l + 1)], h1[2 * (l + 1) + 1] + h2[2 * (l + 1) + 1])
-                          : czero();
+  double2 bq = czero();
+  if (l + 1 <= j)
+    bq = h2 ? make_double2(h1[2 * (l + 1)] + h2[2 * (l + 1)], h1[2 * (l + 1) + 1] + h2[2 * (l + 1) + 1])
+            : make_double2(h1[2 * (l + 1)], h1[2 * (l + 1) + 1]);
   double cq = l < j ? cs[l] : 0.0;
   double2 sq = l < j ? make_double2(sn[2 * l], sn[2 * l + 1]) : czero();
   // lane 0 alone reads these per-lane values (v_readlane) below: pin them in

@@ -130,6 +130,7 @@ template <typename S>
 helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_stats* out, hipStream_t st) {
   const meta_opts* o = c.o;
   const int m = o->restart;
+  const bool one_pass = o->gs_passes == 1;
   const size_t n = op->nn, esz = op_esz(op);
   const size_t fld = Carve::need(n * esz);
   const size_t dsm = Carve::need(sizeof(double) * (2 * (size_t)(m + 1) * m + 8 * (size_t)(m + 1) + 64));
@@ -195,7 +196,8 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
     if (count >= o->max_iters) break;
     scale_host<S>(n, Vj(0), 1.0 / beta, Vj(0), st);
     gmres_init(beta, g, m, st);
-    // One Arnoldi step: z = M v_j, w = A z into W, CGS2, Givens.  W stays
+    // One Arnoldi step: z = M v_j, w = A z into W, CGS2 (or one classical
+    // Gram-Schmidt pass with gs_passes = 1), Givens.  W stays
     // unnormalized; the next step forms v_{j+1} = W / ||W|| as its first kernel
     // reads it (inside the two-sweep Jacobi kernel, or a scaling pass).
     // Its status record is copied to pinned slot j & 1 and an event marks it.
@@ -212,6 +214,14 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
       void* w = W;
       multidot_apply<S>(op->geom, op->sc, op->code, zj, V, ldv, j + 1, w, part, st);  // w = A z_j and V^H w
       reduce_cols(part, mdb, 2 * (j + 1), h1, st);
+      if (one_pass) {
+        // one classical Gram-Schmidt projection, then ||w||^2
+        multi_axpy<S>(n, V, ldv, j + 1, h1, -1.0, w, w, part, st);
+        arnoldi_finish(j, m, H, g, cs, sn, h1, nullptr, part, rdb, gs, slot_dev[j & 1], st);
+        hipError_t e1 = hipEventRecord(ev[j & 1], st);
+        if (e1 != hipSuccess) return hip_fail(e1, "gmres: status event");
+        return launch_check("gmres: arnoldi step");
+      }
       if (j + 1 <= cgs_fused_max_nv()) {
         // first projection and second inner products in one pass over V
         const int nb = cgs_fused<S>(n, V, ldv, j + 1, h1, w, part, st);
@@ -593,6 +603,7 @@ helm_status check_opts(helm_op_s* op, don_s* net, const meta_opts* o) {
   if (!std::isfinite(o->omega)) return fail(HELM_E_INVAL, "meta: omega not finite");
   if (o->fallback_restart < 0 || o->fallback_restart > 1000)
     return fail(HELM_E_INVAL, "meta: fallback_restart must be in [0, 1000]");
+  if (o->gs_passes < 0 || o->gs_passes > 2) return fail(HELM_E_INVAL, "meta: gs_passes must be 0, 1 or 2");
   if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
     helm_status s = check_net_for_op(net, op, o->p_used);
     if (s) return s;

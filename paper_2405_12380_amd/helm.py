@@ -61,7 +61,8 @@ class MetaOpts(C.Structure):
     _fields_ = [("kind", C.c_int), ("restart", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int),
                 ("smoother", C.c_int), ("n_r", C.c_int), ("omega", C.c_double), ("nn_every", C.c_int),
                 ("p_used", C.c_int), ("k", C.c_double), ("history", C.POINTER(C.c_double)), ("q_fp32", C.c_int),
-                ("mg_levels", C.c_int), ("mg_nu", C.c_int), ("no_drop", C.c_int), ("fallback_restart", C.c_int)]
+                ("mg_levels", C.c_int), ("mg_nu", C.c_int), ("no_drop", C.c_int), ("fallback_restart", C.c_int),
+                ("gs_passes", C.c_int)]
 
 
 class MetaStats(C.Structure):
@@ -339,13 +340,13 @@ _SMOOTH = {"jacobi": JACOBI, "rbgs": RBGS}
 
 def _opts(kind, restart=50, tol=1e-6, max_iters=20000, smoother="jacobi", n_r=3, omega=0.5, nn_every=25,
           p_used=None, k=0.0, history=None, net=None, q_fp32=False, mg_levels=0, mg_nu=5, no_drop=False,
-          fallback_restart=0):
+          fallback_restart=0, gs_passes=0):
     pu = p_used if p_used is not None else (net.p if net is not None else 0)
     hp = history.ctypes.data_as(C.POINTER(C.c_double)) if history is not None else None
     return MetaOpts(_KIND[kind] if isinstance(kind, str) else int(kind), int(restart), float(tol), int(max_iters),
                     _SMOOTH[smoother] if isinstance(smoother, str) else int(smoother), int(n_r), float(omega),
                     int(nn_every), int(pu), float(k), hp, 1 if q_fp32 else 0, int(mg_levels), int(mg_nu),
-                    1 if no_drop else 0, int(fallback_restart))
+                    1 if no_drop else 0, int(fallback_restart), int(gs_passes))
 
 
 def meta_solve(op: Op, net: DeepONet | None, f, u, kind="gmres", history=False, stream=None, adjoint=False, **kw):

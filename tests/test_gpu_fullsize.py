@@ -51,29 +51,34 @@ def headline_instance2():
     return C, s, cs, M
 
 
-def test_headline_forced_count_64cube(headline_instance2):
+@pytest.mark.parametrize("gs_passes", [2, 1])
+def test_headline_forced_count_64cube(headline_instance2, gs_passes):
     """The timed configuration at full size (64^3, p = 128, c128): 10
-    DeepONet-GMRES(50) steps (tol = 0) against the oracle, field parity 1e-10."""
+    DeepONet-GMRES(50) steps (tol = 0) against the oracle, field parity 1e-10,
+    with two and with one classical Gram-Schmidt pass per step."""
     from oracle import meta as meta_or
     C, s, cs, M = headline_instance2
-    u_or, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 0.0, 10, precond=M)
+    u_or, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 0.0, 10, precond=M,
+                                     gs_passes=gs_passes)
     op = make_op(helm, C, helm.C128)
     u = op.field()
     st, stats = helm.meta_solve(op, _net(C), op.field(C["f"]), u, kind="gmres", restart=50, tol=0.0, max_iters=10,
-                                n_r=3, omega=0.5, p_used=128, k=C["k"])
+                                n_r=3, omega=0.5, p_used=128, k=C["k"], gs_passes=gs_passes)
     assert stats["iters"] == info["iters"] == 10 and stats["rank_used"] == cs.rank == 128
     assert rel_err(to_np(u), u_or) <= 1e-10
 
 
-def test_headline_to_tolerance_64cube(headline_instance2):
+@pytest.mark.parametrize("gs_passes", [2, 1])
+def test_headline_to_tolerance_64cube(headline_instance2, gs_passes):
     """The same to 1e-6: iteration count within 2 of the oracle's."""
     from oracle import meta as meta_or
     C, s, cs, M = headline_instance2
-    _, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 5000, precond=M)
+    _, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 5000, precond=M,
+                                  gs_passes=gs_passes)
     op = make_op(helm, C, helm.C128)
     u = op.field()
     st, stats = helm.meta_solve(op, _net(C), op.field(C["f"]), u, kind="gmres", restart=50, tol=1e-6, max_iters=5000,
-                                n_r=3, omega=0.5, p_used=128, k=C["k"])
+                                n_r=3, omega=0.5, p_used=128, k=C["k"], gs_passes=gs_passes)
     assert st == helm.OK and info["status"] == 0
     assert abs(stats["iters"] - info["iters"]) <= 2, (stats["iters"], info["iters"])
     assert stats["rel_res"] <= 1e-6

@@ -77,28 +77,47 @@ def test_meta_gmres_forced_count_restarts(restart, iters):
     _forced_count("gmres", iters, helm.C128, restart)
 
 
-def _forced_count(kind, iters, dtype, restart):
+@pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
+@pytest.mark.parametrize("restart,iters", [(50, 12), (4, 11)])
+def test_meta_gmres_one_gram_schmidt_pass(restart, iters, dtype):
+    """GMRES with one classical Gram-Schmidt projection per step (gs_passes = 1,
+    PETSc's default orthogonalization) against the oracle's same variant."""
+    _forced_count("gmres", iters, dtype, restart, gs_passes=1)
+
+
+def test_gs_passes_checked():
+    C, s, op, net, cs = _setup(8, 16)
+    for bad in (-1, 3):
+        with pytest.raises(helm.HelmError):
+            helm.meta_solve(op, None, op.field(C["f"]), op.field(), kind="gmres", max_iters=2, gs_passes=bad)
+
+
+def _forced_count(kind, iters, dtype, restart, gs_passes=2):
     C, s, op, net, cs = _setup(16, 64, dtype)
     f = stored(C["f"], dtype == helm.C64)
     M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
-    u_or, info = meta_or.krylov_meta(kind, f, np.zeros_like(f), s, C["mask"], restart, 0.0, iters, precond=M)
+    u_or, info = meta_or.krylov_meta(kind, f, np.zeros_like(f), s, C["mask"], restart, 0.0, iters, precond=M,
+                                     gs_passes=gs_passes)
     u = op.field()
     st, stats = helm.meta_solve(op, net, op.field(f), u, kind=kind, restart=restart, tol=0.0, max_iters=iters, n_r=3,
-                                omega=0.5, p_used=64)
+                                omega=0.5, p_used=64, gs_passes=gs_passes)
     assert stats["iters"] == iters
     assert stats["rank_used"] == cs.rank
     tol = 1e-10 if dtype == helm.C128 else 2e-5
     assert rel_err(to_np(u), u_or) <= tol
 
 
-@pytest.mark.parametrize("kind", ["gmres", "bicgstab"])
+@pytest.mark.parametrize("kind", ["gmres", "gmres_cgs1", "bicgstab"])
 def test_meta_krylov_to_tolerance(kind):
     C, s, op, net, cs = _setup(20, 128, instance=2)
     M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
-    _, info = meta_or.krylov_meta(kind, C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 2000, precond=M)
+    passes = 1 if kind == "gmres_cgs1" else 2
+    kind = kind.split("_")[0]
+    _, info = meta_or.krylov_meta(kind, C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 1e-6, 2000, precond=M,
+                                  gs_passes=passes)
     u = op.field()
     st, stats = helm.meta_solve(op, net, op.field(C["f"]), u, kind=kind, restart=50, tol=1e-6, max_iters=2000, n_r=3,
-                                omega=0.5, p_used=128)
+                                omega=0.5, p_used=128, gs_passes=passes)
     assert st == helm.OK and info["status"] == 0
     assert abs(stats["iters"] - info["iters"]) <= 2
     assert stats["rel_res"] <= 1e-6

@@ -1,4 +1,5 @@
-"""Pins of the oracle's GMRES(m)-CGS2 and BiCGStab (CPU only): the GMRES
+"""Pins of the oracle's GMRES(m) (one or two classical Gram-Schmidt passes)
+and BiCGStab (CPU only): the GMRES
 minimal-residual property against an independent least-squares solve over an
 explicitly built Krylov basis, |g| equal to the true residual, finite
 termination on matrices with few distinct eigenvalues, agreement with the
@@ -35,7 +36,8 @@ def test_givens_rotation():
 
 @pytest.mark.parametrize("k", [1, 3, 7, 12])
 @pytest.mark.parametrize("precond", [False, True])
-def test_gmres_minimal_residual(k, precond):
+@pytest.mark.parametrize("gs_passes", [1, 2])
+def test_gmres_minimal_residual(k, precond, gs_passes):
     """After k < m steps from u0 = 0, GMRES minimises ||f - A M y|| over the
     Krylov space K_k(A M, f); the minimiser is computed here from a QR of the
     explicit power basis, independently of Arnoldi and the Givens rotations."""
@@ -44,7 +46,7 @@ def test_gmres_minimal_residual(k, precond):
     d = np.random.default_rng(7).uniform(0.5, 2.0, ff.size) * np.exp(1j * np.random.default_rng(8).uniform(0, 1, ff.size))
     M = (lambda v: d * v) if precond else None
     AM = (lambda v: A(d * v)) if precond else A
-    u, info = krylov.gmres(A, ff, np.zeros_like(ff), 30, 0.0, k, M=M)
+    u, info = krylov.gmres(A, ff, np.zeros_like(ff), 30, 0.0, k, M=M, gs_passes=gs_passes)
     assert info["iters"] == k
     K = [ff]
     for _ in range(k - 1):
@@ -62,15 +64,16 @@ def test_gmres_minimal_residual(k, precond):
     assert np.linalg.norm(u - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
 
 
-def test_gmres_residual_estimate_matches_true_residual():
+@pytest.mark.parametrize("gs_passes", [1, 2])
+def test_gmres_residual_estimate_matches_true_residual(gs_passes):
     """|g_{j+1}| after j Arnoldi steps equals ||f - A u_j|| of the iterate formed
     from those steps (right preconditioning keeps the true residual)."""
     P, s, f, A = _small()
     ff = f.ravel()
     hist = []
-    krylov.gmres(A, ff, np.zeros_like(ff), 40, 0.0, 20, history=hist)
+    krylov.gmres(A, ff, np.zeros_like(ff), 40, 0.0, 20, history=hist, gs_passes=gs_passes)
     for j in (1, 5, 11, 20):
-        u, info = krylov.gmres(A, ff, np.zeros_like(ff), 40, 0.0, j)
+        u, info = krylov.gmres(A, ff, np.zeros_like(ff), 40, 0.0, j, gs_passes=gs_passes)
         assert info["rel_res"] == pytest.approx(hist[j], rel=1e-8)
     # monotone within a cycle
     assert all(hist[i + 1] <= hist[i] * (1 + 1e-12) for i in range(1, 20))
@@ -105,12 +108,14 @@ def test_few_distinct_eigenvalues_terminate():
     assert np.allclose(u, b / (2.5 - 1j), rtol=1e-13)
 
 
-@pytest.mark.parametrize("kind", ["gmres", "bicgstab"])
+@pytest.mark.parametrize("kind", ["gmres", "gmres_cgs1", "bicgstab"])
 @pytest.mark.parametrize("n", [(8, 7, 6), (12, 12, 12)])
 def test_converged_against_direct_solve(kind, n):
     P, s, f, A = _small(n, 4)
     u_star = op.direct_solve(f, s, P["mask"])
-    u, info = meta.krylov_meta(kind, f, np.zeros_like(f), s, P["mask"], 50, 1e-13, 20000)
+    passes = 1 if kind == "gmres_cgs1" else 2
+    u, info = meta.krylov_meta(kind.split("_")[0], f, np.zeros_like(f), s, P["mask"], 50, 1e-13, 20000,
+                               gs_passes=passes)
     assert info["status"] == krylov.CONVERGED
     assert np.linalg.norm(u - u_star) <= 1e-9 * np.linalg.norm(u_star)
     m = P["mask"].astype(bool)
