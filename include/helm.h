@@ -274,7 +274,8 @@ enum { META_JACOBI = 0, META_GS = 1, META_GMRES = 2, META_BICGSTAB = 3 };
 typedef struct {
   int kind;        /* META_*                                                        */
   int restart;     /* GMRES(m): m >= 1                                              */
-  double tol;      /* stop when ||f - A u||_2 <= tol ||f||_2 (tol >= 0)             */
+  double tol;      /* stop when ||f - A u||_2 <= tol ||f||_2 (tol >= 0; <= tol when
+                      f = 0, where the relative residual is undefined)           */
   int max_iters;   /* Arnoldi steps / BiCGStab iterations / relaxation sweeps       */
   int smoother;    /* HELM_JACOBI or HELM_RBGS                                      */
   int n_r;         /* sweeps per cycle (relaxation) or per preconditioner (Krylov)  */
@@ -320,7 +321,7 @@ typedef struct {
 
 typedef struct {
   int iters, matvecs, precond_apps, converged, rank_used, history_len;
-  double rel_res;     /* true ||f - A u||_2 / ||f||_2 at exit                         */
+  double rel_res;     /* true ||f - A u||_2 / ||f||_2 at exit (||f - A u||_2 if f = 0) */
   double setup_ms;    /* coarse-space construction time (0 when cached)               */
   double solve_ms;    /* iteration time                                               */
   double cond_Ac_est; /* 1-norm condition estimate of the coarse matrix               */

@@ -6,10 +6,13 @@ Krylov backbones that the trunk-basis preconditioner accelerates (§3.1.2,
 here and followed identically by the GPU library:
 
 * right preconditioning, u0 given (zero in the workloads), stopping on the
-  true unpreconditioned residual ||f - A u||_2 <= tol ||f||_2;
-* GMRES(m): classical Gram-Schmidt with one full re-orthogonalisation
-  (CGS2); complex Givens rotations G = [[c, s], [-conj(s), c]] with real c;
-  the iteration count is the total number of Arnoldi steps over restarts;
+  true unpreconditioned residual ||f - A u||_2 <= tol ||f||_2; with f = 0
+  the relative residual is undefined and the residual is measured in
+  absolute terms (scale 1 instead of ||f||_2);
+* GMRES(m): classical Gram-Schmidt, one projection (PETSc's default) or two
+  (CGS2, one full re-orthogonalisation); complex Givens rotations
+  G = [[c, s], [-conj(s), c]] with real c; the iteration count is the total
+  number of Arnoldi steps over restarts;
 * BiCGStab: shadow vector r_hat = r0, early exit on ||s||, one count per
   iteration, breakdown on an exactly zero or non-finite rho, r_hat^H v or
   omega; if the recomputed true residual misses the tolerance after the
@@ -62,6 +65,7 @@ def gmres(A, f, u0, restart, tol, max_iters, M=None, history=None, gs_passes=2):
     f = np.asarray(f, dtype=np.complex128)
     u = np.array(u0, dtype=np.complex128)
     fn = np.linalg.norm(f)
+    fs = fn if fn > 0 else 1.0  # residual scale
     count = matvecs = papps = 0
     status = NOT_CONVERGED
     while True:
@@ -69,11 +73,11 @@ def gmres(A, f, u0, restart, tol, max_iters, M=None, history=None, gs_passes=2):
         matvecs += 1
         beta = np.linalg.norm(r)
         if history is not None and not history:
-            history.append(beta / fn if fn > 0 else beta)
+            history.append(beta / fs)
         if not np.isfinite(beta):
             status = NONFINITE
             break
-        if beta <= tol * fn:
+        if beta <= tol * fs:
             status = CONVERGED
             break
         if count >= max_iters:
@@ -117,13 +121,13 @@ def gmres(A, f, u0, restart, tol, max_iters, M=None, history=None, gs_passes=2):
             count += 1
             k = j + 1
             if history is not None:
-                history.append(abs(g[j + 1]) / fn if fn > 0 else abs(g[j + 1]))
-            if abs(g[j + 1]) <= tol * fn or count >= max_iters or hn == 0.0:
+                history.append(abs(g[j + 1]) / fs)
+            if abs(g[j + 1]) <= tol * fs or count >= max_iters or hn == 0.0:
                 break
         y = back_substitute(H, g, k)
         u = u + M(V[:k].T @ y)
         papps += has_m
-    rel = np.linalg.norm(f - A(u)) / fn if fn > 0 else 0.0
+    rel = np.linalg.norm(f - A(u)) / fs
     return u, dict(status=status, iters=count, rel_res=rel, matvecs=matvecs, precond_apps=papps)
 
 
@@ -134,17 +138,18 @@ def bicgstab(A, f, u0, tol, max_iters, M=None, history=None):
     f = np.asarray(f, dtype=np.complex128)
     u = np.array(u0, dtype=np.complex128)
     fn = np.linalg.norm(f)
+    fs = fn if fn > 0 else 1.0  # residual scale
     count = matvecs = papps = 0
     status = NOT_CONVERGED
     r = f - A(u)
     matvecs += 1
     rn = np.linalg.norm(r)
     if history is not None:
-        history.append(rn / fn if fn > 0 else rn)
+        history.append(rn / fs)
     if not np.isfinite(rn):
         return u, dict(status=NONFINITE, iters=0, rel_res=np.inf, matvecs=matvecs, precond_apps=0)
-    if rn <= tol * fn:
-        return u, dict(status=CONVERGED, iters=0, rel_res=rn / fn if fn > 0 else 0.0,
+    if rn <= tol * fs:
+        return u, dict(status=CONVERGED, iters=0, rel_res=rn / fs,
                        matvecs=matvecs, precond_apps=0)
     while True:
         # one restartable sweep of the recurrence
@@ -174,10 +179,10 @@ def bicgstab(A, f, u0, tol, max_iters, M=None, history=None):
             s = r - alpha * v
             count += 1
             sn = np.linalg.norm(s)
-            if sn <= tol * fn:
+            if sn <= tol * fs:
                 u = u + alpha * ph
                 if history is not None:
-                    history.append(sn / fn)
+                    history.append(sn / fs)
                 break
             sh = M(s)
             t = A(sh)
@@ -194,8 +199,8 @@ def bicgstab(A, f, u0, tol, max_iters, M=None, history=None):
             rho0 = rho
             rn = np.linalg.norm(r)
             if history is not None:
-                history.append(rn / fn)
-            if rn <= tol * fn:
+                history.append(rn / fs)
+            if rn <= tol * fs:
                 break
         if stopped:
             break
@@ -205,11 +210,11 @@ def bicgstab(A, f, u0, tol, max_iters, M=None, history=None):
         if not np.isfinite(rn):
             status = NONFINITE
             break
-        if rn <= tol * fn:
+        if rn <= tol * fs:
             status = CONVERGED
             break
         if count >= max_iters:
             status = NOT_CONVERGED
             break
-    rel = np.linalg.norm(f - A(u)) / fn if fn > 0 else 0.0
+    rel = np.linalg.norm(f - A(u)) / fs
     return u, dict(status=status, iters=count, rel_res=rel, matvecs=matvecs, precond_apps=papps)

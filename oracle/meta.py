@@ -48,10 +48,11 @@ def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, corr
     Returns (u, info); info["fallback_iters"] counts the fallback's steps."""
     u = np.array(u0, dtype=np.complex128)
     fn = np.linalg.norm(f)
+    fs = fn if fn > 0 else 1.0  # residual scale (absolute residual when f = 0)
     count = 0
     ncorr = 0
     status = krylov.NOT_CONVERGED
-    prev = np.linalg.norm(op.residual(u, f, s, mask)) / fn if fn > 0 else 0.0
+    prev = np.linalg.norm(op.residual(u, f, s, mask)) / fs
     keep = u
     diverged = False
     while count < max_sweeps:
@@ -64,7 +65,7 @@ def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, corr
             u = u + correction(r)
             ncorr += 1
             r = op.residual(u, f, s, mask)
-        rel = np.linalg.norm(r) / fn if fn > 0 else 0.0
+        rel = np.linalg.norm(r) / fs
         if history is not None:
             history.append(rel)
         if fallback_restart > 0 and not rel <= prev:
@@ -84,7 +85,7 @@ def relaxation_meta(f, u0, s, mask, kind, omega, max_sweeps, nn_every, tol, corr
                                np.ravel(keep), fallback_restart, tol, max_sweeps, gs_passes=gs_passes)
         u = u.reshape(shape)
         status, fb_iters = info["status"], info["iters"]
-    rel = np.linalg.norm(op.residual(u, f, s, mask)) / fn if fn > 0 else 0.0
+    rel = np.linalg.norm(op.residual(u, f, s, mask)) / fs
     return u, dict(status=status, iters=count, rel_res=rel, corrections=ncorr, fallback_iters=fb_iters)
 
 

@@ -686,6 +686,7 @@ helm_status batch_drive(int np, helm_op_s* const* ops, don_s* net, const meta_op
   for (int i = 0; i < np; ++i) {
     if ((s = vec_norm<S>(ops[i], f[i], &fn[i], st))) return s;
     if (!std::isfinite(fn[i])) return fail(HELM_E_NONFINITE, "meta_solve_batch: ||f|| of problem %d is not finite", i);
+    if (!(fn[i] > 0)) fn[i] = 1.0;  // residual scale: absolute residual when f = 0
   }
   auto restart = [&](int i, double rn) -> helm_status {
     // r (already in its segment) becomes r_hat; fresh recurrence
@@ -721,7 +722,7 @@ helm_status batch_drive(int np, helm_op_s* const* ops, don_s* net, const meta_op
     else if (rn <= o->tol * fn[i]) status[i] = HELM_OK;
     else if (o->max_iters <= 0) status[i] = HELM_NOT_CONVERGED;
     else if ((s = restart(i, rn))) return s;
-    stats[i].rel_res = fn[i] > 0 ? rn / fn[i] : rn;
+    stats[i].rel_res = rn / fn[i];
   }
   if ((s = sync_stream(st, "meta_solve_batch: init"))) return s;
 
@@ -791,7 +792,7 @@ helm_status batch_drive(int np, helm_op_s* const* ops, don_s* net, const meta_op
       double rn;
       if ((s = residual_norm<S>(ops[i], f[i], u[i], R.r + pr[i].off, &rn, st))) return s;
       checks[i]++;
-      stats[i].rel_res = fn[i] > 0 ? rn / fn[i] : rn;
+      stats[i].rel_res = rn / fn[i];
       if (!std::isfinite(rn)) status[i] = HELM_E_NONFINITE;
       else if (rn <= o->tol * fn[i]) status[i] = HELM_OK;
       else if (b.iters >= o->max_iters) status[i] = HELM_NOT_CONVERGED;

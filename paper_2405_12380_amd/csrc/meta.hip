@@ -173,7 +173,8 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   double fn;
   if ((s = vec_norm<S>(op, f, &fn, st))) return s;
   if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "gmres: ||f|| is not finite");
-  const double thr = o->tol * fn;
+  const double fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
+  const double thr = o->tol * fs;
   int count = 0, matvecs = 0, papps = 0, hlen = 0;
   helm_status status = HELM_NOT_CONVERGED;
   double beta = 0.0;
@@ -184,7 +185,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
     reduce_cols(part, stb, 1, nrm, st);
     if ((s = read_host(op, nrm, sizeof(double), st, "gmres: residual"))) return s;
     beta = std::sqrt(op->host[0]);
-    if (o->history && hlen == 0) o->history[hlen++] = fn > 0 ? beta / fn : beta;
+    if (o->history && hlen == 0) o->history[hlen++] = beta / fs;
     if (!std::isfinite(beta)) {
       status = HELM_E_NONFINITE;
       break;
@@ -253,7 +254,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
       matvecs++;
       if (c.use_M) papps++;
       k = j + 1;
-      if (o->history && hlen <= o->max_iters) o->history[hlen++] = fn > 0 ? hs.gabs / fn : hs.gabs;
+      if (o->history && hlen <= o->max_iters) o->history[hlen++] = hs.gabs / fs;
       if (hs.flag) {
         status = HELM_E_NONFINITE;
         break;
@@ -279,7 +280,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   out->iters = count;
   out->matvecs = matvecs;
   out->precond_apps = papps;
-  out->rel_res = fn > 0 ? rn / fn : rn;
+  out->rel_res = rn / fs;
   out->history_len = hlen;
   if (status == HELM_NOT_CONVERGED && rn <= thr) status = HELM_OK;
   out->converged = status == HELM_OK;
@@ -321,13 +322,14 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
   double fn;
   if ((s = vec_norm<S>(op, f, &fn, st))) return s;
   if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "bicgstab: ||f|| is not finite");
-  const double thr = o->tol * fn;
+  const double fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
+  const double thr = o->tol * fs;
   int count = 0, matvecs = 0, papps = 0, hlen = 0;
   helm_status status = HELM_NOT_CONVERGED;
   double rn;
   if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
   matvecs++;
-  if (o->history) o->history[hlen++] = fn > 0 ? rn / fn : rn;
+  if (o->history) o->history[hlen++] = rn / fs;
   if (!std::isfinite(rn)) status = HELM_E_NONFINITE;
   else if (rn <= thr) status = HELM_OK;
   while (status == HELM_NOT_CONVERGED) {
@@ -390,7 +392,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       }
       if (hb.ss <= thr) {
         axpy_dev<S>(n, ph, u, bs->alpha, st);
-        if (o->history && hlen <= o->max_iters) o->history[hlen++] = hb.ss / fn;
+        if (o->history && hlen <= o->max_iters) o->history[hlen++] = hb.ss / fs;
         break;
       }
       if (c.use_M) {
@@ -420,7 +422,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
         stopped = true;
         break;
       }
-      if (o->history && hlen <= o->max_iters) o->history[hlen++] = hb.rr / fn;
+      if (o->history && hlen <= o->max_iters) o->history[hlen++] = hb.rr / fs;
       if (!std::isfinite(hb.rr)) {
         status = HELM_E_NONFINITE;
         stopped = true;
@@ -440,7 +442,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
   out->iters = count;
   out->matvecs = matvecs;
   out->precond_apps = papps;
-  out->rel_res = fn > 0 ? rn / fn : rn;
+  out->rel_res = rn / fs;
   out->history_len = hlen;
   out->converged = status == HELM_OK;
   return status;
@@ -465,13 +467,14 @@ helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, 
   const int kind = o->kind == META_JACOBI ? HELM_JACOBI : HELM_RBGS;
   double fn;
   if ((s = vec_norm<S>(op, f, &fn, st))) return s;
+  const double fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
   int count = 0, ncorr = 0, hlen = 0, matvecs = 0;
   helm_status status = HELM_NOT_CONVERGED;
   double rn = 0.0, prev = 0.0;
   if (fb) {
     if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
     matvecs++;
-    prev = fn > 0 ? rn / fn : rn;
+    prev = rn / fs;
     copy_vec<S>(n, u, keep, st);
   }
   bool diverged = false;
@@ -490,7 +493,7 @@ helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, 
     }
     if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
     matvecs++;
-    const double rel = fn > 0 ? rn / fn : rn;
+    const double rel = rn / fs;
     if (o->history && hlen <= o->max_iters) o->history[hlen++] = rel;
     if (fb && !(rel <= prev)) {  // grew, or not finite
       diverged = true;
@@ -534,12 +537,12 @@ helm_status relax_meta_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, 
   }
   if (count == 0) {
     if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
-    if (rn <= o->tol * fn) status = HELM_OK;
+    if (rn <= o->tol * fs) status = HELM_OK;
   }
   out->iters = count;
   out->matvecs = matvecs;
   out->precond_apps = ncorr;
-  out->rel_res = fn > 0 ? rn / fn : rn;
+  out->rel_res = rn / fs;
   out->history_len = hlen;
   out->converged = status == HELM_OK;
   return status;

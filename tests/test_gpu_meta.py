@@ -85,6 +85,76 @@ def test_meta_gmres_one_gram_schmidt_pass(restart, iters, dtype):
     _forced_count("gmres", iters, dtype, restart, gs_passes=1)
 
 
+@pytest.mark.parametrize("kind", ["gmres", "bicgstab", "jacobi"])
+def test_zero_source(kind):
+    """f = 0: from u0 = 0 every kind stops with u exactly 0 and a zero residual;
+    from u0 != 0 the relative residual is undefined and both sides measure the
+    residual in absolute terms (Krylov kinds: field parity at a forced count,
+    then the count to an absolute 1e-8 within 2 of the oracle's)."""
+    C, s, op, net, cs = _setup(12, 32)
+    zero = np.zeros_like(C["f"])
+    nt = None if kind == "jacobi" else net
+    kw = dict(kind=kind, n_r=3, omega=0.5, p_used=32, nn_every=5)
+    u = op.field()
+    st, stats = helm.meta_solve(op, nt, op.field(zero), u, tol=1e-8, max_iters=50, **kw)
+    assert st == helm.OK and stats["rel_res"] == 0.0
+    assert not np.any(to_np(u))
+    if kind == "jacobi":
+        return
+    u0 = np.random.default_rng(5).standard_normal(zero.shape) * (1 - C["mask"]) + 0j
+    M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
+    iters = 8 if kind == "gmres" else 4
+    u_or, info = meta_or.krylov_meta(kind, zero, u0, s, C["mask"], 50, 0.0, iters, precond=M)
+    u = op.field(u0)
+    st, stats = helm.meta_solve(op, nt, op.field(zero), u, tol=0.0, max_iters=iters, **kw)
+    assert stats["iters"] == info["iters"] == iters
+    assert np.linalg.norm(to_np(u) - u_or.ravel()) <= 1e-10 * np.linalg.norm(u0)
+    _, info = meta_or.krylov_meta(kind, zero, u0, s, C["mask"], 50, 1e-8, 2000, precond=M)
+    u = op.field(u0)
+    st, stats = helm.meta_solve(op, nt, op.field(zero), u, tol=1e-8, max_iters=2000, **kw)
+    assert st == helm.OK and info["status"] == 0
+    assert abs(stats["iters"] - info["iters"]) <= 2 and stats["rel_res"] <= 1e-8
+
+
+def test_zero_iterations_keep_the_initial_guess():
+    C, s, op, net, cs = _setup(10, 16)
+    u0 = np.random.default_rng(6).standard_normal(C["f"].shape) + 0j
+    for kind in ("gmres", "bicgstab", "jacobi"):
+        u = op.field(u0)
+        st, stats = helm.meta_solve(op, None if kind == "jacobi" else net, op.field(C["f"]), u, kind=kind,
+                                    tol=1e-6, max_iters=0, p_used=16)
+        assert st == helm.NOT_CONVERGED and stats["iters"] == 0
+        assert np.array_equal(to_np(u), u0.ravel())
+
+
+def test_all_masked_domain_has_an_empty_coarse_space():
+    """Every node in the scatterer: the masked trunk is zero, App. C's selection
+    keeps no column (rank 0, M2 = 0) and A = I; DeepONet-GMRES matches the
+    oracle, and no_drop reports the lost columns."""
+    n = 6
+    C = I.config2(0, n=(n, n, n))
+    C["mask"][:] = 1
+    C["f"] = np.random.default_rng(8).standard_normal(C["f"].shape) + 1j
+    s = op_or.coefficient(C["ksq"], C["alpha"])
+    op = make_op(helm, C, helm.C128)
+    net = helm.DeepONet(helm.C128, C["branch"], C["trunk"], C["p"], head="split_output", branch_grid=(16, 16, 16),
+                        k_input=True)
+    T = don_or.trunk_matrix(I.node_points(C["n"]), C["trunk"])
+    cs = co_or.CoarseSpace(T, s, C["mask"], 16)
+    assert cs.rank == 0
+    M = meta_or.krylov_preconditioner(s, C["mask"], "jacobi", 3, 0.5, cs)
+    u_or, info = meta_or.krylov_meta("gmres", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, 0.0, 3, precond=M)
+    u = op.field()
+    st, stats = helm.meta_solve(op, net, op.field(C["f"]), u, kind="gmres", tol=0.0, max_iters=3, n_r=3, omega=0.5,
+                                p_used=16)
+    assert stats["rank_used"] == 0 and stats["iters"] == info["iters"]
+    assert rel_err(to_np(u), u_or) <= 1e-12
+    with pytest.raises(helm.HelmError) as e:
+        helm.meta_solve(op, net, op.field(C["f"]), op.field(), kind="gmres", tol=1e-6, max_iters=3, p_used=16,
+                        no_drop=True)
+    assert e.value.status == helm.E_SINGULAR
+
+
 def test_gs_passes_checked():
     C, s, op, net, cs = _setup(8, 16)
     for bad in (-1, 3):

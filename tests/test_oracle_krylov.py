@@ -155,3 +155,21 @@ def test_golden_bicgstab_counts_match_oracle():
     _, info = meta.krylov_meta("bicgstab", C["f"], np.zeros_like(C["f"]), s, C["mask"], 50, ref["tol"], 5000)
     assert info["iters"] == ref["unperturbed"]
     assert ref["min"] <= ref["unperturbed"] <= ref["max"] and len(ref["counts"]) == 31
+
+
+@pytest.mark.parametrize("kind", ["gmres", "bicgstab"])
+def test_zero_source_uses_the_absolute_residual(kind):
+    """f = 0 (relative residual undefined): from u0 != 0 the solvers drive
+    ||A u|| below tol itself and report it as rel_res; from u0 = 0 they stop
+    at once with u = 0."""
+    P, s, f, A = _small((6, 6, 6), 9)
+    zero = np.zeros(f.size, complex)
+    u0 = np.random.default_rng(3).standard_normal(f.size) * (1 - P["mask"].ravel())
+    solve = (lambda b, x, tol: krylov.gmres(A, b, x, 30, tol, 500)) if kind == "gmres" else \
+        (lambda b, x, tol: krylov.bicgstab(A, b, x, tol, 500))
+    u, info = solve(zero, u0, 1e-9)
+    assert info["status"] == krylov.CONVERGED and info["iters"] > 0
+    res = np.linalg.norm(A(u))
+    assert res <= 1e-9 and info["rel_res"] == pytest.approx(res, rel=1e-12)
+    u, info = solve(zero, np.zeros_like(zero), 1e-9)
+    assert info["status"] == krylov.CONVERGED and info["iters"] == 0 and not np.any(u)
