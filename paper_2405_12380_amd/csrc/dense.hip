@@ -409,39 +409,51 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
 // ---- Gauss-Jordan inverse of a complex r x r matrix (r <= 128), one workgroup ----
 // The matrix lives in registers: thread t owns row t / 8 and the 16 columns
 // [16 (t % 8), 16 (t % 8) + 16).  In-place Gauss-Jordan with partial pivoting
-// (largest modulus, lowest row on ties): per pivot the column is published in
-// LDS, wavefront 0 picks the pivot, the two rows are exchanged through LDS, the
-// pivot row is scaled and broadcast, and every thread updates its 16 entries.
-// The row interchanges are undone at the end as column interchanges in
-// reverse order.  info[0] = 1 if a pivot was zero or non-finite;
+// (largest modulus among the rows not yet used as pivot rows, lowest row on
+// ties), without moving rows: per pivot the column is published in LDS (and
+// zeroed in the registers), every wavefront picks the pivot row p from the
+// published moduli, row p is scaled and broadcast, and every other row is
+// updated.  Row p of the final table is then row k of the inverse where p was
+// column k's pivot row, and its column c is column p_c (the pivot row of
+// column c) of the inverse.  info[0] = 1 if a pivot was zero or non-finite;
 // cond[0] = ||A||_1 ||A^{-1}||_1.
 __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __restrict__ A, double* __restrict__ Ainv,
                                                      int* __restrict__ info, double* __restrict__ cond) {
   // prow holds the pivot row with one pad entry per 16 columns: the eight
   // column blocks a wavefront reads at once then fall in different LDS banks
-  __shared__ double2 pcol[2][128], prow[128 + 8], bufk[128], bufp[128];
+  __shared__ double2 pcol[2][128], prow[128 + 8];
   __shared__ double pabs[2][128], csum[128];
   __shared__ double npart[8][128];
-  __shared__ int perm[128], dest[128];
+  __shared__ int perm[128], rowof[128];
   __shared__ int s_bad;
   const int t = threadIdx.x, lane = t & 63;
   const int i = t >> 3, cb = t & 7, c0 = 16 * cb;
   const bool row_in = i < r;
+  bool used = false;  // row i has been a pivot row
   double2 a[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int c = c0 + q;
     a[q] = (row_in && c < r) ? make_double2(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]) : czero();
   }
-  // pivot column k (its entries and moduli, rows below k only) into buffer k & 1
+  // column k into buffer k & 1 (entries, and the moduli of the rows not yet
+  // pivot rows), and zeroed in the registers: the update of column k then
+  // leaves -f / pivot there
   auto publish = [&](int k) {
-    if (cb == (k >> 4) && row_in) {
-      double2 v = czero();
+    const int qk = k & 15;
+    const bool own = cb == (k >> 4);
+    double2 v = czero();
 #pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q == (k & 15)) v = a[q];
+    for (int q = 0; q < 16; ++q) {
+      const bool hit = q == qk, zap = hit && own;
+      v.x = hit ? a[q].x : v.x;
+      v.y = hit ? a[q].y : v.y;
+      a[q].x = zap ? 0.0 : a[q].x;
+      a[q].y = zap ? 0.0 : a[q].y;
+    }
+    if (own && row_in) {
       pcol[k & 1][i] = v;
-      pabs[k & 1][i] = i >= k ? hypot(v.x, v.y) : -1.0;
+      pabs[k & 1][i] = used ? -1.0 : hypot(v.x, v.y);
     }
   };
   publish(0);
@@ -455,16 +467,16 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     npart[r0][c] = sm;
   }
   if (t == 0) s_bad = 0;
+  if (t < 128) rowof[t] = t;  // every row maps in range even if a failed pivot search repeats a row
   __syncthreads();
   if (t < 128) {
     double sm = 0.0;
     for (int q = 0; q < 8; ++q) sm += npart[q][t];
     csum[t] = sm;
   }
-  // Per pivot: two barriers (four with a row interchange).  Every wavefront
-  // finds the pivot itself from the published moduli (same data, same order,
-  // same result), and the elimination of column k publishes column k + 1 into
-  // the other buffer.
+  // Per pivot: two barriers.  Every wavefront finds the pivot itself from the
+  // published moduli (same data, same order, same result), and the update for
+  // column k publishes column k + 1 into the other buffer.
   for (int k = 0; k < r; ++k) {
     const int buf = k & 1;
     double best = -2.0;
@@ -486,32 +498,13 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     const int p = bi;
     if (t == 0) {
       perm[k] = p;
+      rowof[p] = k;
       if (!(best > 0.0) || !isfinite(best)) s_bad = 1;
     }
-    if (p != k) {
-      if (i == k)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) bufk[c0 + q] = a[q];
-      if (i == p)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) bufp[c0 + q] = a[q];
-      __syncthreads();
-      if (i == k)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) a[q] = bufp[c0 + q];
-      if (i == p)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) a[q] = bufk[c0 + q];
-      if (t == 0) {
-        const double2 tmp = pcol[buf][k];
-        pcol[buf][k] = pcol[buf][p];
-        pcol[buf][p] = tmp;
-      }
-      __syncthreads();
-    }
-    // scale the pivot row: A[k][k] <- 1, row *= 1 / pivot; publish it
-    if (i == k) {
-      const double2 ipiv = cdiv(make_double2(1.0, 0.0), pcol[buf][k]);
+    // pivot row p: entry k <- 1, row *= 1 / pivot; publish it
+    if (i == p) {
+      used = true;
+      const double2 ipiv = cdiv(make_double2(1.0, 0.0), pcol[buf][p]);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const double2 v = (c0 + q == k) ? make_double2(1.0, 0.0) : a[q];
@@ -520,43 +513,28 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
       }
     }
     __syncthreads();
-    // eliminate column k from every other row: A[i][:] <- (A[i][:] with A[i][k] = 0) - f A[k][:]
-    if (i != k && row_in) {
+    // every other row: A[i][:] <- A[i][:] - f A[p][:] (A[i][k] is 0 here)
+    if (i != p && row_in) {
       const double2 f = pcol[buf][i];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const double2 v = (c0 + q == k) ? czero() : a[q];
-        a[q] = csub(v, cmul(f, prow[c0 + q + cb]));
-      }
+      for (int q = 0; q < 16; ++q) a[q] = csub(a[q], cmul(f, prow[c0 + q + cb]));
     }
     if (k + 1 < r) publish(k + 1);
     __syncthreads();
   }
-  // The row interchanges are undone as column interchanges in reverse order:
-  // column c of the result is column idx[c] of the eliminated matrix, so every
-  // entry is written once, straight to its final column.
-  if (t == 0) {
-    for (int c = 0; c < r; ++c) dest[c] = c;  // idx, built in place
-    for (int k = r - 1; k >= 0; --k) {
-      const int p = perm[k];
-      const int tmp = dest[k];
-      dest[k] = dest[p];
-      dest[p] = tmp;
-    }
-  }
-  __syncthreads();
-  if (t < r) pcol[0][dest[t]].x = (double)t;  // inverse map: column idx[c] goes to c
-  __syncthreads();
-  if (row_in)
+  // row i of the table is row rowof[i] of the inverse; its column c is column perm[c]
+  if (row_in) {
+    const int to_row = rowof[i];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int c = c0 + q;
       if (c < r) {
-        const int to = (int)pcol[0][c].x;
-        Ainv[2 * ((size_t)i * r + to)] = a[q].x;
-        Ainv[2 * ((size_t)i * r + to) + 1] = a[q].y;
+        const int to = perm[c];
+        Ainv[2 * ((size_t)to_row * r + to)] = a[q].x;
+        Ainv[2 * ((size_t)to_row * r + to) + 1] = a[q].y;
       }
     }
+  }
   __syncthreads();
   {
     const int c = t & 127, r0 = t >> 7;
