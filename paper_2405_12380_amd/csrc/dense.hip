@@ -287,8 +287,9 @@ __global__ void k_reduce_rows(const double* __restrict__ part, int nparts, size_
 }
 
 // ---- one-workgroup Cholesky with column dropping -------------------------------
-// G: p x p (row-major, fp64) = P^T P, p <= 128, copied into LDS (128 KiB at
-// p = 128; gfx950 gives a workgroup up to 160 KiB).  Right-looking Cholesky
+// G: p x p (row-major, fp64) = P^T P, p <= 128, factored in registers (16
+// entries per thread) and then kept in LDS for the triangular inverse (128 KiB
+// at p = 128; gfx950 gives a workgroup up to 160 KiB).  Right-looking Cholesky
 // G = R^T R on the upper triangle; a column whose Schur-complement diagonal is
 // <= tau2 * max_j G[j][j] is dropped (its remaining norm is at most tau times
 // the largest column norm), which matches Householder QR that skips such
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
                                                     double* __restrict__ S, int* __restrict__ info) {
   extern __shared__ double G[];  // p x p
   __shared__ double xdiag[128];
-  __shared__ double pivs[128];  // sqrt of column j's pivot, or -1 where the column is dropped
+  __shared__ double rowj[2][128];  // row j of the factorization step, double-buffered
   __shared__ int kept[128];
   __shared__ int s_fail;
   __shared__ double s_thr2;
@@ -324,42 +325,73 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
   }
   __syncthreads();
   const double thr2 = s_thr2;
-  // One barrier per column.  Step j reads row j unscaled (R[j][c] = G[j][c] /
-  // piv is formed where it is used, as G[j][c] times the pivot's reciprocal,
-  // the same product the scaled row holds) and scales row j - 1, which no
-  // thread reads in step j.  Every thread takes the drop decision of column j
-  // itself from G[j][j] (final after step j - 1), so all of them count the
-  // kept columns alike.
+  // The matrix lives in registers during the factorization: thread (ty, tx) of
+  // a 32 x 32 grid holds G[ty + 32 u][tx + 32 v], u, v < 4.  Step j: the
+  // holders of row j (final after step j - 1) publish it unscaled in LDS
+  // (double-buffered, so one barrier per step), every thread takes the drop
+  // decision of column j itself from G[j][j] and updates its entries of the
+  // trailing upper triangle with R[j][a] R[j][c], R[j][c] = G[j][c] / piv
+  // formed as G[j][c] times the pivot's reciprocal; the holders of row j scale
+  // it in their registers.
+  const int ty = t >> 5, tx = t & 31;
+  double g[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = ty + 32 * u, c = tx + 32 * v;
+      g[u][v] = (a < p && c < p) ? G[a * p + c] : 0.0;
+    }
   int nk = 0;
   for (int j = 0; j < p; ++j) {
-    if (j > 0) {
-      const double pv = pivs[j - 1];
-      if (pv > 0.0) {
-        const double pinv = 1.0 / pv;
-        for (int c = j - 1 + t; c < p; c += nt) G[(j - 1) * p + c] = (c == j - 1) ? pv : G[(j - 1) * p + c] * pinv;
-      }
-    }
-    const double dj = G[j * p + j];
+    const int uj = j >> 5, buf = j & 1;
+    if (ty == (j & 31))
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u == uj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = tx + 32 * v;
+            if (c < p) rowj[buf][c] = g[u][v];
+          }
+    __syncthreads();
+    const double dj = rowj[buf][j];
     const bool keep = dj > thr2;
     const double piv = keep ? sqrt(dj) : -1.0;
     if (t == 0) {
-      pivs[j] = piv;
       if (keep) kept[nk] = j;
       else if (!allow_drop) s_fail = 1;
     }
     if (keep) {
       ++nk;
       const double pinv = 1.0 / piv;
-      // trailing update of the upper triangle: G[a][c] -= R[j][a] R[j][c], j < a <= c
-      // (a 32 x 32 thread grid: rows a = j + 1 + ty + 32 u, columns c = a + tx + 32 v)
-      for (int a = j + 1 + (t >> 5); a < p; a += nt >> 5) {
-        const double ra = G[j * p + a] * pinv;
-        for (int c = a + (t & 31); c < p; c += 32) G[a * p + c] -= ra * (G[j * p + c] * pinv);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int a = ty + 32 * u;
+        if (a > j && a < p) {
+          const double ra = rowj[buf][a] * pinv;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = tx + 32 * v;
+            if (c >= a && c < p) g[u][v] -= ra * (rowj[buf][c] * pinv);
+          }
+        } else if (a == j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = tx + 32 * v;
+            if (c >= j && c < p) g[u][v] = (c == j) ? piv : g[u][v] * pinv;
+          }
+        }
       }
     }
-    __syncthreads();
   }
-  if (t == 0 && pivs[p - 1] > 0.0) G[(p - 1) * p + (p - 1)] = pivs[p - 1];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = ty + 32 * u, c = tx + 32 * v;
+      if (a < p && c < p) G[a * p + c] = g[u][v];
+    }
   __syncthreads();
   const int r = nk;
   // X = R1^{-1}, R1[a][b] = G[kept[a]][kept[b]] (a <= b).  X[a][b] (a < b) is kept
@@ -371,9 +403,14 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
   {
     const int b = t >> 3, sub = t & 7;
     const bool colb = b < r && (t >> 3) < (nt >> 3);
+    const bool full = r == p;  // no column dropped: kept[c] = c, direct addressing
     for (int a = r - 1; a >= 0; --a) {
       double acc = 0.0;
-      if (colb && b >= a)
+      if (colb && b >= a && full) {
+#pragma unroll 4
+        for (int c = a + 1 + sub; c < b; c += 8) acc += G[a * p + c] * G[b * p + c];
+        if (((b - a - 1) & 7) == sub && b > a) acc += G[a * p + b] * xdiag[b];
+      } else if (colb && b >= a)
         for (int c = a + 1 + sub; c <= b; c += 8) {
           const double xcb = (c == b) ? xdiag[b] : G[kept[b] * p + kept[c]];
           acc += G[kept[a] * p + kept[c]] * xcb;
