@@ -205,11 +205,13 @@ def test_two_rows_per_thread_ragged(dtype):
     assert rel_err(z, ref.ravel()) <= TOL[dtype]
 
 
-def test_residual_and_jacobi_full_size_256():
-    """Residual and one damped Jacobi sweep at 256^3, where the stencil kernels
-    stream their once-read inputs (s, f, code) with non-temporal loads and
-    their outputs with non-temporal stores, against the oracle on every node."""
-    n = (256, 256, 256)
+@pytest.mark.parametrize("N", [256, 384])
+def test_residual_and_jacobi_full_size(N):
+    """Residual and one damped Jacobi sweep at the bandwidth-run sizes (256^3,
+    384^3), where the stencil kernels take two rows per thread and stream their
+    once-read inputs (s, f, code) with non-temporal loads and their outputs
+    with non-temporal stores, against the oracle on every node."""
+    n = (N, N, N)
     P, s = _problem(n, 10, helm.C128)
     op = make_op(helm, P, helm.C128)
     f = op.field(P["f"])
@@ -220,10 +222,11 @@ def test_residual_and_jacobi_full_size_256():
     assert rel_err(to_np(u), op_or.jacobi_sweep(P["x"], P["f"], s, P["mask"], 0.6).ravel()) <= 1e-13
 
 
-def test_rbgs_full_size_256():
-    """One red-black sweep at 256^3, the bandwidth-run size (streaming output
-    stores), against the oracle on every node."""
-    n = (256, 256, 256)
+@pytest.mark.parametrize("N", [256, 384])
+def test_rbgs_full_size(N):
+    """One red-black sweep at the bandwidth-run sizes (streaming output stores),
+    against the oracle on every node."""
+    n = (N, N, N)
     P, s = _problem(n, 9, helm.C128)
     op = make_op(helm, P, helm.C128)
     u = op.field(P["x"])
@@ -268,6 +271,26 @@ def test_full_size_apply_sampled():
     ref = op_or.apply(x, s, P["mask"]).ravel()
     assert rel_err(y[idx], ref[idx]) <= 1e-13
     assert rel_err(y, ref) <= 1e-13
+
+
+def test_max_size_512():
+    """512^3 complex128: each field is 2 GiB, the size from which the red-black
+    sweep takes the pair-exchange kernel (the plane-ring kernel addresses with
+    32-bit offsets) and every offset needs 64 bits.  Apply, one Jacobi sweep
+    and one red-black sweep against the oracle on every node."""
+    n = (512, 512, 512)
+    P, s = _problem(n, 13, helm.C128)
+    op = make_op(helm, P, helm.C128)
+    f = op.field(P["f"])
+    y = to_np(op.apply(op.field(P["x"])))
+    assert rel_err(y, op_or.apply(P["x"], s, P["mask"]).ravel()) <= 1e-13
+    del y
+    u = op.field(P["x"])
+    op.relax(helm.JACOBI, 0.6, 1, f, u)
+    assert rel_err(to_np(u), op_or.jacobi_sweep(P["x"], P["f"], s, P["mask"], 0.6).ravel()) <= 1e-13
+    u = op.field(P["x"])
+    op.relax(helm.RBGS, 1.0, 1, f, u)
+    assert rel_err(to_np(u), op_or.rbgs_sweep(P["x"], P["f"], s, P["mask"], 1.0).ravel()) <= 1e-12
 
 
 def test_invalid_arguments():
