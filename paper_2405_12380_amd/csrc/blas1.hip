@@ -642,8 +642,7 @@ void bicg_update(size_t n, const void* ph, const void* sh, const void* s, const 
 
 __device__ static bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
 
-__global__ void k_bicg_scalar(int step, BiState* bs, const double* red) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void bicg_step(int step, BiState* bs, const double* red) {
   if (step == BI_RHO) {
     const double2 rho = make_double2(red[0], red[1]);
     if (!finite2(rho)) {
@@ -699,8 +698,20 @@ __global__ void k_bicg_scalar(int step, BiState* bs, const double* red) {
   }
 }
 
-void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st) {
-  hipLaunchKernelGGL(k_bicg_scalar, dim3(1), dim3(64), 0, st, step, bs, red);
+// ghost: optional copy of the record in pinned host memory, made visible to
+// the host by the kernel itself (the event the host waits on carries no
+// system-scope release)
+__global__ void k_bicg_scalar(int step, BiState* bs, const double* red, BiState* ghost) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  bicg_step(step, bs, red);
+  if (ghost) {
+    *ghost = *bs;
+    __threadfence_system();
+  }
+}
+
+void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st, BiState* ghost) {
+  hipLaunchKernelGGL(k_bicg_scalar, dim3(1), dim3(64), 0, st, step, bs, red, ghost);
 }
 
 #define HELM_INST(S)                                                                                           \

@@ -134,14 +134,16 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(int j, int m, double* H, 
     gs->gabs = cabs2(gn);
     gs->flag = (isfinite(hn) && isfinite(gs->gabs)) ? 0 : -5;
     gs->step = j;
-    // the host reads this copy (pinned host memory) only after synchronizing on
-    // an event recorded behind the kernel; the kernel's completion makes the
-    // writes visible, so no system-scope fence is needed here
+    // the host reads this copy (pinned host memory) after synchronizing on an
+    // event recorded behind the kernel; that event carries no system-scope
+    // release (one at every Arnoldi step cost several microseconds), so the
+    // kernel makes these writes visible to the host itself
     ghost->gabs = gs->gabs;
     ghost->hn = hn;
     ghost->inv_hn = gs->inv_hn;
     ghost->flag = gs->flag;
     ghost->step = j;
+    __threadfence_system();
   }
   __syncthreads();
   for (int i = l; i <= j + 1; i += 64) H_set(H, m, i, j, make_double2(col[2 * i], col[2 * i + 1]));

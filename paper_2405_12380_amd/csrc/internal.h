@@ -114,7 +114,7 @@ void bicg_update(size_t n, const void* ph, const void* sh, const void* s, const 
 template <typename S>
 void axpy_dev(size_t n, const void* x, void* y, const double* a, hipStream_t st);  // y += a x, a complex on device
 // scalar steps (single thread), reading the reduced values in `red`
-void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st);
+void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st, BiState* ghost = nullptr);
 enum { BI_RHO = 0, BI_ALPHA = 1, BI_SS = 2, BI_OMEGA = 3, BI_RR = 4 };
 
 // ---- GMRES small dense work (gmres.hip) -------------------------------------

@@ -33,11 +33,15 @@ struct Carve {
 };
 
 // Two timing-free events, destroyed with the scope.
+// Status events of the iteration loops.  With system_fence false the event
+// carries no system-scope release: the kernel that writes the status record to
+// pinned host memory must make it visible itself (the GMRES step does).
 struct EventPair {
   hipEvent_t e[2] = {nullptr, nullptr};
-  EventPair() {
+  explicit EventPair(bool system_fence = true) {
+    const unsigned fl = hipEventDisableTiming | (system_fence ? 0u : (unsigned)hipEventDisableSystemFence);
     for (auto& x : e)
-      if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) x = nullptr;
+      if (hipEventCreateWithFlags(&x, fl) != hipSuccess) x = nullptr;
   }
   ~EventPair() {
     for (auto& x : e)
@@ -167,7 +171,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   // status records land directly in pinned host memory (written by the kernel)
   GmState* slot[2] = {(GmState*)(op->host + 64), (GmState*)(op->host + 128)};
   GmState* slot_dev[2] = {(GmState*)(op->host_dev + 64), (GmState*)(op->host_dev + 128)};
-  EventPair ev;
+  EventPair ev(false);
   if (!ev.ok()) return fail(HELM_E_HIP, "gmres: event creation failed");
 
   double fn;
@@ -310,7 +314,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
   BiState* bs = (BiState*)cv.take(sizeof(BiState));
   double* red = (double*)cv.take(64 * sizeof(double));
   const int rdb = red_nblocks(n), stb = stencil_nblocks(op->geom);
-  EventPair ev;
+  EventPair ev(false);
   if (!ev.ok()) return fail(HELM_E_HIP, "bicgstab: event creation failed");
   double* part;
   if ((s = op_part(op, (size_t)(3 * rdb > stb ? 3 * rdb : stb), &part))) return s;
@@ -343,12 +347,14 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
     reduce_cols(part, rdb, 2, red + 8, st);
     // One iteration = half 1 (rho, p, M p, v = A M p, alpha, s, ||s||) and
     // half 2 (M s, t = A M s, omega, the updates of u and r, ||r||).  Each half
-    // ends by copying the state record to pinned memory behind an event.  Half 1
+    // ends by writing the state record to pinned memory behind an event.  Half 1
     // of the next iteration is queued before the host looks at ||r||: if ||r||
     // ends the sweep, that half is discarded (it writes only p, v, s, their
     // preconditioned copies and the scalar record, which a new sweep resets).
     BiState* hS = (BiState*)(op->host + 256);
     BiState* hR = (BiState*)(op->host + 320);
+    BiState* dS = (BiState*)(op->host_dev + 256);  // the same records, as the kernels address them
+    BiState* dR = (BiState*)(op->host_dev + 320);
     auto half1 = [&](bool first_) -> helm_status {
       bicg_scalar(BI_RHO, bs, red + 8, st);
       bicg_p<S>(n, r, v, p, bs, first_ ? 1 : 0, st);
@@ -362,9 +368,8 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       bicg_scalar(BI_ALPHA, bs, red, st);
       bicg_s<S>(n, r, v, sv, bs, part, st);
       reduce_cols(part, rdb, 1, red + 2, st);
-      bicg_scalar(BI_SS, bs, red + 2, st);
-      hipError_t e1 = hipMemcpyAsync(hS, bs, sizeof(BiState), hipMemcpyDeviceToHost, st);
-      if (e1 == hipSuccess) e1 = hipEventRecord(ev[0], st);
+      bicg_scalar(BI_SS, bs, red + 2, st, dS);
+      hipError_t e1 = hipEventRecord(ev[0], st);
       return e1 == hipSuccess ? launch_check("bicgstab: half 1") : hip_fail(e1, "bicgstab: half 1 record");
     };
     bool stopped = false, pending = false;
@@ -406,9 +411,8 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       bicg_scalar(BI_OMEGA, bs, red + 4, st);
       bicg_update<S>(n, ph, sh, sv, t, rh, u, r, bs, part, st);
       reduce_cols(part, rdb, 3, red + 8 - 1, st);  // red[7] = ||r||^2, red[8..9] = r_hat^H r (next rho)
-      bicg_scalar(BI_RR, bs, red + 7, st);
-      e1 = hipMemcpyAsync(hR, bs, sizeof(BiState), hipMemcpyDeviceToHost, st);
-      if (e1 == hipSuccess) e1 = hipEventRecord(ev[1], st);
+      bicg_scalar(BI_RR, bs, red + 7, st, dR);
+      e1 = hipEventRecord(ev[1], st);
       if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: half 2 record");
       if (count < o->max_iters) {  // look ahead: the next half 1
         if ((s = half1(false))) return s;
