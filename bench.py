@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--adjoint-n", type=int, default=128, help="grid nodes per axis of the adjoint workload")
     ap.add_argument("--adjoint-fd", type=int, default=2,
                     help="finite-difference directions checked in the adjoint workload")
+    ap.add_argument("--sponge-check", action="store_true",
+                    help="only: the adjoint workload's forward solve with an 8-cell sponge and with the "
+                         "max(8, n/8) one it uses, as the record of why the wider layer")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter-collection run: one solve plus a device copy of known size, no timing")
     return ap.parse_args()
@@ -188,6 +191,10 @@ def main():
         sts = [step(i, **kw) for i in range(count)]
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / count, sts
+
+    if args.sponge_check:
+        print(json.dumps({"sponge_check": sponge_check(helm, I, torch, args.adjoint_n)}))
+        return
 
     if args.pmc_run:
         st = step(2)
@@ -566,6 +573,28 @@ def training(helm, I, torch, dev, n_samples, epochs):
     tr.close()
     net.close()
     return res
+
+
+def sponge_check(helm, I, torch, N, max_iters=4000):
+    """The adjoint workload's forward solve (DeepONet-BiCGStab to 1e-8, trained
+    trunk) with the sponge 8 cells wide and max(8, N/8) cells wide."""
+    out = []
+    for width in (8, max(8, N // 8)):
+        C = I.config5(n=(N, N, N), sponge_width=width)
+        op = helm.Op(C["n"], helm.C128, C["ksq"], C["alpha"], C["mask"])
+        net = helm.DeepONet(helm.C128, C["branch"], trunk_layers(I), C["p"], head="split_output",
+                            branch_grid=(16, 16, 16), k_input=True)
+        u = op.field()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, stats = helm.meta_solve(op, net, op.field(C["f"]), u, kind="bicgstab", tol=1e-8, max_iters=max_iters,
+                                    n_r=3, omega=0.5, p_used=128, k=C["k"])
+        torch.cuda.synchronize()
+        out.append({"sponge_width": width, "status": st, "iters": stats["iters"], "rel_res": stats["rel_res"],
+                    "ms": round((time.perf_counter() - t0) * 1e3, 1)})
+        log(f"sponge {width}: {out[-1]}")
+        op.close()
+    return {"grid": N, "k": 20.0, "tol": 1e-8, "max_iters": max_iters, "runs": out}
 
 
 def adjoint_gradient(helm, I, torch, dev, N, fd_dirs):

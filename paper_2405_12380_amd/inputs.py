@@ -304,7 +304,7 @@ def config4(count: int = 64, instance: int = 0, n_range=(48, 128), k_range=(5.0,
 
 
 def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: float = 0.05,
-            trunk_gain: float = 30.0) -> dict:
+            trunk_gain: float = 30.0, sponge_width=None) -> dict:
     """Adjoint case: homogeneous k = 20, submarine-like scatterer (capsule
     along x plus sail), plane wave incident from the top.
 
@@ -320,12 +320,14 @@ def config5(n=(128, 128, 128), instance: int = 0, k: float = 20.0, perturb: floa
     * ``ksq_true = k^2 (1 + perturb g)`` with g a GRF (l = 0.2) scaled to
       max |g| = 1: the medium that generates the synthetic data.
     * The network is config 2's (same weights stream).
+    * ``sponge_width`` overrides the width (for the record of what a thinner
+      layer does).
     """
     g = rng_for(5, instance)
     n = tuple(int(v) for v in n)
     shp = field_shape(n)
     mask = capsule_sail_mask(n)
-    width = max(SPONGE_WIDTH, n[-1] // 8)
+    width = max(SPONGE_WIDTH, n[-1] // 8) if sponge_width is None else int(sponge_width)
     alpha = sponge(n, width=width)
     ksq = np.full(shp, k * k)
     f = np.zeros(shp, dtype=np.complex128)
