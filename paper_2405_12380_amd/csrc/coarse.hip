@@ -286,6 +286,16 @@ __global__ void k_mask_cols(size_t n, int p, int pu, const T* __restrict__ Tm, c
   }
 }
 
+// rows of scatterer nodes zeroed in place (T: n x p): the op's cached trunk
+// matrix is kept masked, which the network synthesis (zero on the scatterer)
+// does not see and the coarse space needs
+template <typename T>
+__global__ void k_zero_masked_rows(size_t n, int p, const uint8_t* __restrict__ mask, T* __restrict__ Tm) {
+  const size_t total = n * p;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+    if (mask[e / p]) Tm[e] = T(0);
+}
+
 // Qs = (T) Q and Q <- (double) Qs, so the coarse matrix is built from the basis
 // actually stored.
 template <typename T>
@@ -402,7 +412,10 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
     c.T_serial = don_serial(net);
   }
   const int pu = p_used;
-  if ((s = c.W1.ensure(n * (size_t)pu * sizeof(double)))) return s;
+  // fp64 trunk (C128): P is the masked trunk matrix itself, read with its row
+  // stride p; fp32 trunk (C64): P is widened into W1
+  const bool wide_t = sizeof(TT) == sizeof(double);
+  if (!wide_t && (s = c.W1.ensure(n * (size_t)pu * sizeof(double)))) return s;
   if ((s = c.W2.ensure(n * (size_t)pu * sizeof(double)))) return s;
   const size_t small_doubles = (size_t)gram_nblocks(n) * pu * pu + 10 * (size_t)pu * pu + 4096;
   if ((s = c.small.ensure(small_doubles * sizeof(double)))) return s;
@@ -416,13 +429,23 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   double* gjw = aim + (size_t)pu * pu;  // 4 pu^2
   int* info = (int*)(gjw + 4 * (size_t)pu * pu);
   double* cond = (double*)(info + 8);
-  double* P = (double*)c.W1.ptr;
   double* Q1 = (double*)c.W2.ptr;
-  // P = masked first columns
-  hipLaunchKernelGGL((k_mask_cols<TT>), dim3(ew_grid(n * pu)), dim3(256), 0, st, n, p, pu, (const TT*)c.T.ptr,
-                     op->mask, P);
+  // P = masked first pu columns of T
+  const double* P;
+  size_t ldp;
+  if (wide_t) {
+    hipLaunchKernelGGL((k_zero_masked_rows<TT>), dim3(ew_grid(n * p)), dim3(256), 0, st, n, p, op->mask,
+                       (TT*)c.T.ptr);
+    P = (const double*)c.T.ptr;
+    ldp = (size_t)p;
+  } else {
+    hipLaunchKernelGGL((k_mask_cols<TT>), dim3(ew_grid(n * pu)), dim3(256), 0, st, n, p, pu, (const TT*)c.T.ptr,
+                       op->mask, (double*)c.W1.ptr);
+    P = (const double*)c.W1.ptr;
+    ldp = (size_t)pu;
+  }
   // pass 1: G = P^T P, Cholesky with dropping -> S1 (pu x r)
-  gram(n, pu, P, pu, P, pu, nullptr, part, G, st);
+  gram(n, pu, P, ldp, P, ldp, nullptr, part, G, st);
   const double tau = op->dt == HELM_C128 ? 1e-7 : 1e-5;
   chol_drop(pu, G, tau * tau, 1, X, S1, info, st);
   hipError_t e = hipMemcpyAsync(op->host, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
@@ -439,25 +462,24 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
     return HELM_OK;
   }
   // Q1 = P S1 (n x r)
-  gemm<double>((int)n, r, pu, P, pu, S1, r, nullptr, ACT_NONE, Q1, r, st);
-  // pass 2: G2 = Q1^T Q1, Cholesky without dropping -> S2 (r x r); Q = Q1 S2 into W1
+  gemm<double>((int)n, r, pu, P, ldp, S1, r, nullptr, ACT_NONE, Q1, r, st);
+  // pass 2: G2 = Q1^T Q1, Cholesky without dropping -> S2 (r x r); Q = Q1 S2,
+  // straight into the stored basis when it is fp64, else into W1 for rounding
   gram(n, r, Q1, r, Q1, r, nullptr, part, G2, st);
   chol_drop(r, G2, 0.0, 0, X, S1, info, st);
-  double* Q = P;  // reuse W1
+  c.q_f32 = qf32 || sizeof(TT) == sizeof(float);
+  if (c.q_f32 && (s = c.W1.ensure(n * (size_t)r * sizeof(double)))) return s;
+  if ((s = c.Q.ensure(n * (size_t)r * (c.q_f32 ? sizeof(float) : sizeof(double))))) return s;
+  double* Q = c.q_f32 ? (double*)c.W1.ptr : (double*)c.Q.ptr;
   gemm<double>((int)n, r, r, Q1, r, S1, r, nullptr, ACT_NONE, Q, r, st);
   e = hipMemcpyAsync(op->host, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "coarse: pass 2 readback");
   if ((s = sync_stream(st, "coarse: pass 2"))) return s;
   if (((int*)op->host)[1] != 0 || ((int*)op->host)[0] != r)
     return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", ((int*)op->host)[0], r);
-  // stored basis (fp32 when requested or for C64, else fp64); Q <- stored values
-  c.q_f32 = qf32 || sizeof(TT) == sizeof(float);
-  if ((s = c.Q.ensure(n * (size_t)r * (c.q_f32 ? sizeof(float) : sizeof(double))))) return s;
+  // fp32 stored basis (when requested, or for C64): Q <- its stored values
   if (c.q_f32)
     hipLaunchKernelGGL((k_round_q<float>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (float*)c.Q.ptr);
-  else
-    hipLaunchKernelGGL((k_round_q<double>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q,
-                       (double*)c.Q.ptr);
   // B = (L - diag(Re s)) Q into W2; A_c = Q^T B - i Q^T diag(Im s) Q
   double* Bm = Q1;
   {
