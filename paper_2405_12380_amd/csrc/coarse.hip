@@ -290,10 +290,12 @@ __global__ void k_mask_cols(size_t n, int p, int pu, const T* __restrict__ Tm, c
 // matrix is kept masked, which the network synthesis (zero on the scatterer)
 // does not see and the coarse space needs
 template <typename T>
-__global__ void k_zero_masked_rows(size_t n, int p, const uint8_t* __restrict__ mask, T* __restrict__ Tm) {
-  const size_t total = n * p;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
-    if (mask[e / p]) Tm[e] = T(0);
+__global__ __launch_bounds__(256) void k_zero_masked_rows(size_t n, int p, const uint8_t* __restrict__ mask,
+                                                          T* __restrict__ Tm) {
+  // one row per wavefront step (threadIdx.y), the lanes across its p entries
+  for (size_t i = blockIdx.x * (size_t)blockDim.y + threadIdx.y; i < n; i += (size_t)gridDim.x * blockDim.y)
+    if (mask[i])
+      for (int c = threadIdx.x; c < p; c += 64) Tm[i * p + c] = T(0);
 }
 
 // Qs = (T) Q and Q <- (double) Qs, so the coarse matrix is built from the basis
@@ -434,7 +436,8 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   const double* P;
   size_t ldp;
   if (wide_t) {
-    hipLaunchKernelGGL((k_zero_masked_rows<TT>), dim3(ew_grid(n * p)), dim3(256), 0, st, n, p, op->mask,
+    const size_t nbz = std::min<size_t>((n + 3) / 4, 8192);
+    hipLaunchKernelGGL((k_zero_masked_rows<TT>), dim3((unsigned)nbz), dim3(64, 4), 0, st, n, p, op->mask,
                        (TT*)c.T.ptr);
     P = (const double*)c.T.ptr;
     ldp = (size_t)p;

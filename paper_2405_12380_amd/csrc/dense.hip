@@ -42,10 +42,21 @@ __device__ __forceinline__ T activate(T x, int act) {
 // Workgroup b takes rows [b rpb, (b + 1) rpb) of the output, threads its
 // columns (W and b of a column loaded once); the node indices of the first
 // row come from one division, the next rows by stepping x, then y, then z.
-template <typename T>
+constexpr int CL_TAB = 1024;  // node coordinates tabulated in LDS per axis up to this length
+template <typename T, bool TABBED>
 __global__ __launch_bounds__(256) void k_coord_layer(int dim, int nx, int ny, int nz, size_t row0, size_t nrows,
                                                      size_t rpb, const T* __restrict__ W, const T* __restrict__ b,
                                                      int N, int act, T* __restrict__ out) {
+  // TABBED: coordinate x_i = (i + 1) / (n + 1) of each axis formed once per
+  // workgroup (the same quotients every element would form)
+  __shared__ T tab[3][TABBED ? CL_TAB : 1];
+  constexpr bool tabbed = TABBED;
+  if (tabbed) {
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) tab[0][i] = T(i + 1) / T(nx + 1);
+    for (int i = threadIdx.x; i < ny; i += blockDim.x) tab[1][i] = T(i + 1) / T(ny + 1);
+    for (int i = threadIdx.x; i < nz; i += blockDim.x) tab[2][i] = T(i + 1) / T(nz + 1);
+    __syncthreads();
+  }
   const size_t r0 = (size_t)blockIdx.x * rpb, r1 = min(nrows, r0 + rpb);
   if (r0 >= r1) return;
   const size_t p0 = row0 + r0;
@@ -58,7 +69,8 @@ __global__ __launch_bounds__(256) void k_coord_layer(int dim, int nx, int ny, in
     int jx = ix, jy = iy, jz = iz;
     for (size_t r = r0; r < r1; ++r) {
       if (on) {
-        const T xc[3] = {T(jx + 1) / T(nx + 1), T(jy + 1) / T(ny + 1), T(jz + 1) / T(nz + 1)};
+        const T xc[3] = {tabbed ? tab[0][jx] : T(jx + 1) / T(nx + 1), tabbed ? tab[1][jy] : T(jy + 1) / T(ny + 1),
+                         tabbed ? tab[2][jz] : T(jz + 1) / T(nz + 1)};
         T acc = xc[0] * w0;
         if (dim > 1) acc += xc[1] * w1;
         if (dim > 2) acc += xc[2] * w2;
@@ -608,8 +620,13 @@ void coord_layer(int dim, const int n[3], size_t row0, size_t nrows, const T* W,
   if (rpb < 16) rpb = 16;
   const size_t nb = (nrows + rpb - 1) / rpb;
   if (nb == 0) return;
-  hipLaunchKernelGGL((k_coord_layer<T>), dim3((unsigned)nb), dim3(256), 0, st, dim, n[0], n[1], n[2], row0, nrows, rpb,
-                     W, b, N, act, out);
+  const int ny = dim > 1 ? n[1] : 1, nz = dim > 2 ? n[2] : 1;  // absent axes have one node
+  if (n[0] <= CL_TAB && ny <= CL_TAB && nz <= CL_TAB)
+    hipLaunchKernelGGL((k_coord_layer<T, true>), dim3((unsigned)nb), dim3(256), 0, st, dim, n[0], ny, nz, row0, nrows,
+                       rpb, W, b, N, act, out);
+  else
+    hipLaunchKernelGGL((k_coord_layer<T, false>), dim3((unsigned)nb), dim3(256), 0, st, dim, n[0], ny, nz, row0, nrows,
+                       rpb, W, b, N, act, out);
 }
 
 template <typename T>
