@@ -468,18 +468,15 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   gemm<double>((int)n, r, pu, P, ldp, S1, r, nullptr, ACT_NONE, Q1, r, st);
   // pass 2: G2 = Q1^T Q1, Cholesky without dropping -> S2 (r x r); Q = Q1 S2,
   // straight into the stored basis when it is fp64, else into W1 for rounding
+  // (its rank record goes to info[2..3], read back with the inverse's record:
+  // every kernel below is sized by r alone, so a lost rank only spoils values)
   gram(n, r, Q1, r, Q1, r, nullptr, part, G2, st);
-  chol_drop(r, G2, 0.0, 0, X, S1, info, st);
+  chol_drop(r, G2, 0.0, 0, X, S1, info + 2, st);
   c.q_f32 = qf32 || sizeof(TT) == sizeof(float);
   if (c.q_f32 && (s = c.W1.ensure(n * (size_t)r * sizeof(double)))) return s;
   if ((s = c.Q.ensure(n * (size_t)r * (c.q_f32 ? sizeof(float) : sizeof(double))))) return s;
   double* Q = c.q_f32 ? (double*)c.W1.ptr : (double*)c.Q.ptr;
   gemm<double>((int)n, r, r, Q1, r, S1, r, nullptr, ACT_NONE, Q, r, st);
-  e = hipMemcpyAsync(op->host, info, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return hip_fail(e, "coarse: pass 2 readback");
-  if ((s = sync_stream(st, "coarse: pass 2"))) return s;
-  if (((int*)op->host)[1] != 0 || ((int*)op->host)[0] != r)
-    return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", ((int*)op->host)[0], r);
   // fp32 stored basis (when requested, or for C64): Q <- its stored values
   if (c.q_f32)
     hipLaunchKernelGGL((k_round_q<float>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (float*)c.Q.ptr);
@@ -504,7 +501,10 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   if (e != hipSuccess) return hip_fail(e, "coarse: inverse readback");
   (void)hipEventRecord(e1, st);
   if ((s = sync_stream(st, "coarse: inverse"))) return s;
-  if (((int*)op->host)[0] != 0) return fail(HELM_E_SINGULAR, "coarse: A_c is singular (zero pivot)");
+  const int* rec = (const int*)op->host;
+  if (rec[3] != 0 || rec[2] != r)
+    return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", rec[2], r);
+  if (rec[0] != 0) return fail(HELM_E_SINGULAR, "coarse: A_c is singular (zero pivot)");
   c.cond_est = *(double*)((int*)op->host + 8);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, e0, e1);
