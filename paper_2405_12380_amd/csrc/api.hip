@@ -128,7 +128,7 @@ helm_status helm_setup(const helm_grid* g, helm_dtype dt, const double* ksq, con
   op->geom = make_geom(g->dim, op->n, 0);
   helm_status s;
   if ((s = dalloc(&op->sc, nn * op_esz(op))) || (s = dalloc((void**)&op->mask, nn)) ||
-      (s = dalloc((void**)&op->alpha, nn * sizeof(double))) || (s = dalloc((void**)&op->code, nn)) ||
+      (s = dalloc((void**)&op->alpha, nn * sizeof(double))) || (s = dalloc((void**)&op->code, (nn + 3) & ~(size_t)3)) ||
       (s = dalloc((void**)&op->red, 4096 * sizeof(double)))) {
     helm_destroy(op);
     return s;

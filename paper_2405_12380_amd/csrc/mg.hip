@@ -164,7 +164,7 @@ helm_status coarse_op(const helm_op_s* fine, hipStream_t st, helm_op_s** out) {
   op->geom = make_geom(op->dim, op->n, 0);
   helm_status s;
   if ((s = dalloc(&op->sc, op->nn * op_esz(op))) || (s = dalloc((void**)&op->mask, op->nn)) ||
-      (s = dalloc((void**)&op->alpha, op->nn * sizeof(double))) || (s = dalloc((void**)&op->code, op->nn)) ||
+      (s = dalloc((void**)&op->alpha, op->nn * sizeof(double))) || (s = dalloc((void**)&op->code, (op->nn + 3) & ~(size_t)3)) ||
       (s = dalloc((void**)&op->red, 4096 * sizeof(double)))) {
     helm_destroy(op);
     return s;

@@ -225,7 +225,10 @@ __global__ __launch_bounds__(512) void k_rbgs_fused(StencilGeom g, const cplx_t<
 // old value from LDS.  Black positions in LDS always keep their uin values, which
 // is what the red updates read.  Plane z + 4 is loaded into registers one step
 // ahead and the node data (code byte, s, f) of the next step's updates as well;
-// one barrier per step.  Every global access is a buffer load or store whose
+// one barrier per step.  Stores go through the caches: a colour's stores fill
+// every other 16-byte slot of a line, and the other colour's stores of the same
+// line follow a step later, so they merge in L2 (non-temporal stores of these
+// half lines cost 8% at 256^3 and 13% at 384^3).  Every global access is a buffer load or store whose
 // offset is pushed past the end of the buffer where the node is absent (loads
 // give 0, stores are dropped), so a step issues the same memory operations on
 // every path and waiting for the prefetched data never waits for the step's
@@ -250,22 +253,25 @@ __device__ __forceinline__ double2 rb_ld(__amdgpu_buffer_rsrc_t r, unsigned off,
   const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
   return make_double2((double)v.x, (double)v.y);
 }
-template <bool NT>
 __device__ __forceinline__ void rb_st(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v, double2*) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(rb_u4, v), r, off, 0, NT ? 2 : 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(rb_u4, v), r, off, 0, 0);
 }
-template <bool NT>
 __device__ __forceinline__ void rb_st(__amdgpu_buffer_rsrc_t r, unsigned off, double2 v, float2*) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rb_u2, make_float2((float)v.x, (float)v.y)), r, off, 0,
-                                        NT ? 2 : 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rb_u2, make_float2((float)v.x, (float)v.y)), r, off, 0, 0);
 }
 
+// A node's data for one relaxation update: the aligned 32-bit word that holds
+// its code byte (a word, not the byte, so that a value carried into the next
+// loop iteration needs no conversion, which would make the step wait for its
+// own prefetches), s and f.  Code buffers are padded to a multiple of 4 bytes.
 struct NodeIn {
-  unsigned cd;
+  unsigned cw;
   double2 s, f;
 };
+__device__ __forceinline__ unsigned rb_cw_off(unsigned boff) { return boff & ~3u; }
+__device__ __forceinline__ unsigned rb_cd(unsigned cw, unsigned boff) { return (cw >> (8 * (boff & 3u))) & 0xffu; }
 
-template <typename S, bool NT>
+template <typename S, int DEPTH>
 __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const cplx_t<S>* __restrict__ sc,
                                                    const uint8_t* __restrict__ code,
                                                    const cplx_t<S>* __restrict__ uin, const cplx_t<S>* __restrict__ f,
@@ -280,7 +286,7 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
   const int t = threadIdx.x;
   const size_t nxy = (size_t)g.nx * g.ny, nn = nxy * g.nz;
   const __amdgpu_buffer_rsrc_t r_u = rb_rsrc(uin, nn * sizeof(C)), r_f = rb_rsrc(f, nn * sizeof(C)),
-                               r_s = rb_rsrc(sc, nn * sizeof(C)), r_c = rb_rsrc(code, nn),
+                               r_s = rb_rsrc(sc, nn * sizeof(C)), r_c = rb_rsrc(code, (nn + 3) & ~(size_t)3),
                                r_o = rb_rsrc(uout, nn * sizeof(C));
   auto slot = [](int k) { return (k + RB_NS) % RB_NS; };  // k >= -RB_NS
   // node index of LDS position e in plane k, or -1 where there is no node
@@ -292,15 +298,14 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
   };
   auto boff = [](long p, unsigned esz) { return p >= 0 ? (unsigned)p * esz : RB_OOB; };
   // staged plane k: thread t holds LDS positions t + 256 q (zero where there is no node)
-  double2 pre[4];
-  auto load_plane = [&](int k) {
+  auto load_plane = [&](int k, double2 (&pre)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + 256 * q;
       pre[q] = rb_ld(r_u, boff(e < RB_PL ? node(e, k) : -1L, sizeof(C)), (const C*)nullptr);
     }
   };
-  auto store_plane = [&](int k) {
+  auto store_plane = [&](int k, const double2 (&pre)[4]) {
     double2* P = ring[slot(k)];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     return ly * RB_LX + lx;
   };
   auto load_node = [&](long p, NodeIn& in) {
-    in.cd = __builtin_amdgcn_raw_buffer_load_b8(r_c, boff(p, 1), 0, 0);
+    in.cw = __builtin_amdgcn_raw_buffer_load_b32(r_c, rb_cw_off(boff(p, 1)), 0, 0);
     in.s = rb_ld(r_s, boff(p, sizeof(C)), (const C*)nullptr);
     in.f = rb_ld(r_f, boff(p, sizeof(C)), (const C*)nullptr);
   };
@@ -329,8 +334,8 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     e = red_pos(r < RB_NRED ? r : RB_NRED - 1, k);
     return r < RB_NRED ? node(e, k) : -1L;
   };
-  NodeIn rn[2], bn;  // node data of the next step's red updates and black update
-  auto load_next = [&](int kr, int kb) {
+  // node data of a step's red updates (plane kr) and black update (plane kb)
+  auto load_next = [&](int kr, int kb, NodeIn (&rn)[2], NodeIn& bn) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       int e;
@@ -347,19 +352,30 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     for (int u = 0; u < 2; ++u) {
       int e;
       const long p = red_node(u, k, e);
-      const double2 v = rnd_store<S>(relax_upd<S>(g, in[u].cd, P[e], P[e - 1], P[e + 1], P[e - RB_LX], P[e + RB_LX],
+      const double2 v = rnd_store<S>(relax_upd<S>(g, rb_cd(in[u].cw, boff(p, 1)), P[e], P[e - 1], P[e + 1], P[e - RB_LX], P[e + RB_LX],
                                                   Pm[e], Pp[e], in[u].s, in[u].f, omega, true));
       if (p >= 0) P[e] = v;
       const int lx = e % RB_LX, ly = e / RB_LX;
       const bool tile = lx >= 2 && lx < RB_TX + 2 && ly >= 2 && ly < RB_TY + 2;
-      rb_st<NT>(r_o, boff(own && tile ? p : -1L, sizeof(C)), v, (C*)nullptr);
+      rb_st(r_o, boff(own && tile ? p : -1L, sizeof(C)), v, (C*)nullptr);
     }
   };
   // prologue: planes z0 - 2 .. z0 + 2 staged, plane z0 + 3 in flight, red of z0 - 1 and z0
+  // Prefetch depth DEPTH: step z reads the register set loaded DEPTH - 1 steps
+  // earlier (plane z + 3, node data of its updates) and loads the set of step
+  // z + DEPTH - 1 into the set step z - 1 used.  The loop is unrolled by DEPTH so
+  // that every set keeps its registers (a set carried into differently named
+  // registers at the loop's back-edge would make each step wait for its own
+  // loads).  The kernel runs with DEPTH = 2; depths 3 and 4 measured no faster.
+  struct Pre {
+    double2 pl[4];
+    NodeIn rn[2], bn;
+  };
+  Pre S_[DEPTH];
   NodeIn r0[2], r1[2];
   for (int k = z0 - 2; k <= z0 + 2; ++k) {
-    load_plane(k);
-    store_plane(k);
+    load_plane(k, S_[0].pl);
+    store_plane(k, S_[0].pl);
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -367,25 +383,33 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     load_node(red_node(u, z0 - 1, e), r0[u]);
     load_node(red_node(u, z0, e), r1[u]);
   }
-  load_plane(z0 + 3);
+#pragma unroll
+  for (int j = 0; j < DEPTH - 1; ++j) {
+    load_plane(z0 + 3 + j, S_[j].pl);
+    load_next(z0 + 1 + j, z0 + j, S_[j].rn, S_[j].bn);
+  }
   __syncthreads();
   red(z0 - 1, r0, false);
   red(z0, r1, true);
-  load_next(z0 + 1, z0);
-  for (int z = z0; z < z1; ++z) {
-    const NodeIn rc[2] = {rn[0], rn[1]};
-    const NodeIn bc = bn;
-    store_plane(z + 3);  // loaded one step ago; its slot last held plane z - 3
-    load_plane(z + 4);
-    load_next(z + 2, z + 1);
-    red(z + 1, rc, z + 1 < z1);
+  auto step = [&](int z, const Pre& cur, Pre& nxt) {
+    store_plane(z + 3, cur.pl);  // its slot last held plane z - 3
+    load_plane(z + DEPTH + 2, nxt.pl);
+    load_next(z + DEPTH, z + DEPTH - 1, nxt.rn, nxt.bn);
+    red(z + 1, cur.rn, z + 1 < z1);
     __syncthreads();
     // black half-sweep of plane z on the tile
     const int e = black_pos(z);
     const double2* P = ring[slot(z)];
-    const double2 v = relax_upd<S>(g, bc.cd, P[e], P[e - 1], P[e + 1], P[e - RB_LX], P[e + RB_LX],
-                                   ring[slot(z - 1)][e], ring[slot(z + 1)][e], bc.s, bc.f, omega, true);
-    rb_st<NT>(r_o, boff(node(e, z), sizeof(C)), v, (C*)nullptr);
+    const double2 v = relax_upd<S>(g, rb_cd(cur.bn.cw, boff(node(e, z), 1)), P[e], P[e - 1], P[e + 1],
+                                   P[e - RB_LX], P[e + RB_LX], ring[slot(z - 1)][e], ring[slot(z + 1)][e], cur.bn.s,
+                                   cur.bn.f, omega, true);
+    rb_st(r_o, boff(z < z1 ? node(e, z) : -1L, sizeof(C)), v, (C*)nullptr);
+  };
+  // the march is rounded up to a multiple of DEPTH steps: the steps past z1
+  // store nothing (no branches around them, so the register sets stay put)
+  for (int z = z0; z < z1; z += DEPTH) {
+#pragma unroll
+    for (int i = 0; i < DEPTH; ++i) step(z + i, S_[i], S_[(i + DEPTH - 1) % DEPTH]);
   }
 }
 
@@ -527,19 +551,16 @@ void stencil_rbgs_fused(const StencilGeom& g0, const void* sc, const uint8_t* co
   const double n = (double)g.nx * g.ny * g.nz, esz = 2.0 * sizeof(S);
   kprof_begin(KP_STENCIL, st);
   // the ring kernel addresses each buffer with 32-bit offsets (fields under 2 GiB)
-  const bool ring = g.dim == 3 && (g.rb == 1 || (g.rb == 0 && n * esz < 2147483648.0));
+  const bool small = n * esz < 2147483648.0;
+  const bool ring = g.dim == 3 && (g.rb == 1 || (g.rb == 0 && small));
   if (ring) {
     // planes per workgroup: about 1024 workgroups, marches of 2 .. 32 planes
     const long tiles = (long)((g.nx + RB_TX - 1) / RB_TX) * ((g.ny + RB_TY - 1) / RB_TY);
     int zb = (int)(tiles * g.nz / 1024);
     zb = zb < 2 ? 2 : zb > 32 ? 32 : zb;
     const long nbr = tiles * ((g.nz + zb - 1) / zb);
-    if (g.nt)
-      hipLaunchKernelGGL((k_rbgs_ring<S, true>), dim3((unsigned)nbr), dim3(256), 0, st, g, zb, (const C*)sc, code,
-                         (const C*)uin, (const C*)f, (C*)uout, omega);
-    else
-      hipLaunchKernelGGL((k_rbgs_ring<S, false>), dim3((unsigned)nbr), dim3(256), 0, st, g, zb, (const C*)sc, code,
-                         (const C*)uin, (const C*)f, (C*)uout, omega);
+    hipLaunchKernelGGL((k_rbgs_ring<S, 2>), dim3((unsigned)nbr), dim3(256), 0, st, g, zb, (const C*)sc, code,
+                       (const C*)uin, (const C*)f, (C*)uout, omega);
   } else if (g.dim == 3)
     hipLaunchKernelGGL((k_rbgs_fused<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)uin,
                        (const C*)f, (C*)uout, omega);

@@ -230,9 +230,17 @@ def test_rbgs_full_size(N):
     P, s = _problem(n, 9, helm.C128)
     op = make_op(helm, P, helm.C128)
     u = op.field(P["x"])
-    op.relax(helm.RBGS, 1.0, 1, op.field(P["f"]), u)
+    fd = op.field(P["f"])
+    op.relax(helm.RBGS, 1.0, 1, fd, u)
     ref = op_or.rbgs_sweep(P["x"], P["f"], s, P["mask"], 1.0)
-    assert rel_err(to_np(u), ref) <= 1e-12
+    got = to_np(u)
+    assert rel_err(got, ref) <= 1e-12
+    # the register-pair kernel (the one fields of 2 GiB and more use) gives the
+    # same bits at this size
+    op.set_rbgs_kernel(helm.RB_PAIRS)
+    u = op.field(P["x"])
+    op.relax(helm.RBGS, 1.0, 1, fd, u)
+    assert np.array_equal(to_np(u), got)
 
 
 def test_rbgs_tile_independent_and_deterministic():
