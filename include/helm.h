@@ -359,7 +359,11 @@ helm_status meta_precond(helm_op op, don_net net, const meta_opts* o, const void
 /* Inspect the cached coarse space for (net, o->p_used): rank, and optionally the
  * coarse matrix A_c (host, rank x rank complex128, row-major, interleaved, capacity
  * `ac_cap` complex entries) and Q (device, n x rank, row-major, real in the dtype's
- * precision, capacity `q_cap` elements).  Synchronous. */
+ * precision, capacity `q_cap` elements).  Q is the orthonormal basis (App. C) and
+ * A_c = Q^T A Q.  With an fp64 basis the solves use the first CholeskyQR pass's
+ * basis Q1 = P S1, which spans the same space (the correction depends only on
+ * the span); the second pass, Q = Q1 S2 and A_c = S2^T (Q1^T A Q1) S2, is run
+ * here (HELM_E_SINGULAR if it loses rank).  Synchronous. */
 helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* rank, double* Ac,
                              size_t ac_cap, void* Q, size_t q_cap, void* stream);
 

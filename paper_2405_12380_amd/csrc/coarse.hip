@@ -1,12 +1,15 @@
 // Trunk-basis coarse space of App. C and its per-application correction.
 //
 // Setup (once per network, p_used and k^2): P = first p_used trunk columns with
-// scatterer rows zeroed; CholeskyQR2 with column dropping, Q = P S1 S2 with
-// Q^T Q = I and positive diag(R); B = (L - diag(Re s)) Q by a batched real
-// stencil; A_c = Q^T B - i Q^T diag(Im s) Q (= Q^T A Q); A_c^{-1} by
+// scatterer rows zeroed; Cholesky of P^T P with column dropping, Q1 = P S1.
+// fp64 basis: the solves use Q1 (it spans the space of the orthonormal
+// Q = Q1 S2 of a second CholeskyQR pass, and the correction depends only on
+// that span).  fp32 basis: the second pass is run and Q rounded to fp32.  In
+// either basis X: B = (L - diag(Re s)) X by a batched real stencil; the
+// Galerkin matrix X^T B - i X^T diag(Im s) X (= X^T A X); its inverse by
 // Gauss-Jordan with partial pivoting.
 //
-// Correction z += Q A_c^{-1} Q^T r1 (HBM-bound skinny products):
+// Correction z += X (X^T A X)^{-1} X^T r1 (HBM-bound skinny products):
 //   k_qt_part   per-block partials of Q^T r1: lanes own columns {l, l+64},
 //               the grid's wavefronts sweep Q in four-row groups, one
 //               coalesced 2 x 512 B row read per row;
@@ -318,6 +321,35 @@ __global__ void k_combine_ac(int r2, const double* __restrict__ re, const double
   }
 }
 
+// Ac = S^T M S for real S (r x r, row-major) and complex M (r x r, interleaved,
+// row-major): workgroup i forms row i, first u = S[:, i]^T M (a row, in LDS),
+// then Ac[i][j] = sum_b u_b S[b][j]; sums in index order.
+__global__ __launch_bounds__(128) void k_sandwich(int r, const double* __restrict__ S, const double* __restrict__ M,
+                                                  double* __restrict__ Ac) {
+  __shared__ double2 u[128];
+  const int i = blockIdx.x, t = threadIdx.x;
+  if (t < r) {
+    double2 acc = czero();
+    for (int a = 0; a < r; ++a) {
+      const double sa = S[(size_t)a * r + i];
+      acc.x += sa * M[2 * ((size_t)a * r + t)];
+      acc.y += sa * M[2 * ((size_t)a * r + t) + 1];
+    }
+    u[t] = acc;
+  }
+  __syncthreads();
+  if (t < r) {
+    double2 acc = czero();
+    for (int b = 0; b < r; ++b) {
+      const double sb = S[(size_t)b * r + t];
+      acc.x += u[b].x * sb;
+      acc.y += u[b].y * sb;
+    }
+    Ac[2 * ((size_t)i * r + t)] = acc.x;
+    Ac[2 * ((size_t)i * r + t) + 1] = acc.y;
+  }
+}
+
 static unsigned ew_grid(size_t total) {
   size_t nb = (total + 255) / 256;
   if (nb > 16384) nb = 16384;
@@ -417,8 +449,10 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
   // fp64 trunk (C128): P is the masked trunk matrix itself, read with its row
   // stride p; fp32 trunk (C64): P is widened into W1
   const bool wide_t = sizeof(TT) == sizeof(double);
+  c.q_f32 = qf32 || !wide_t;
+  c.pass1 = !c.q_f32;  // fp64 basis: the first pass's basis is the one used
   if (!wide_t && (s = c.W1.ensure(n * (size_t)pu * sizeof(double)))) return s;
-  if ((s = c.W2.ensure(n * (size_t)pu * sizeof(double)))) return s;
+  if (c.q_f32 && (s = c.W2.ensure(n * (size_t)pu * sizeof(double)))) return s;
   const size_t small_doubles = (size_t)gram_nblocks(n) * pu * pu + 10 * (size_t)pu * pu + 4096;
   if ((s = c.small.ensure(small_doubles * sizeof(double)))) return s;
   double* part = (double*)c.small.ptr;
@@ -464,45 +498,55 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
     (void)hipEventDestroy(e1);
     return HELM_OK;
   }
-  // Q1 = P S1 (n x r)
-  gemm<double>((int)n, r, pu, P, ldp, S1, r, nullptr, ACT_NONE, Q1, r, st);
-  // pass 2: G2 = Q1^T Q1, Cholesky without dropping -> S2 (r x r); Q = Q1 S2,
-  // straight into the stored basis when it is fp64, else into W1 for rounding
-  // (its rank record goes to info[2..3], read back with the inverse's record:
-  // every kernel below is sized by r alone, so a lost rank only spoils values)
-  gram(n, r, Q1, r, Q1, r, nullptr, part, G2, st);
-  chol_drop(r, G2, 0.0, 0, X, S1, info + 2, st);
-  c.q_f32 = qf32 || sizeof(TT) == sizeof(float);
-  if (c.q_f32 && (s = c.W1.ensure(n * (size_t)r * sizeof(double)))) return s;
-  if ((s = c.Q.ensure(n * (size_t)r * (c.q_f32 ? sizeof(float) : sizeof(double))))) return s;
-  double* Q = c.q_f32 ? (double*)c.W1.ptr : (double*)c.Q.ptr;
-  gemm<double>((int)n, r, r, Q1, r, S1, r, nullptr, ACT_NONE, Q, r, st);
-  // fp32 stored basis (when requested, or for C64): Q <- its stored values
-  if (c.q_f32)
-    hipLaunchKernelGGL((k_round_q<float>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (float*)c.Q.ptr);
-  // B = (L - diag(Re s)) Q into W2; A_c = Q^T B - i Q^T diag(Im s) Q
-  double* Bm = Q1;
-  {
-    size_t nbl = (n + 3) / 4;
-    if (nbl > 16384) nbl = 16384;
-    hipLaunchKernelGGL((k_batched_lap<S>), dim3((unsigned)nbl), dim3(64, 4), 0, st, op->geom, r, Q,
-                       (const cplx_t<S>*)op->sc, op->code, Bm);
-  }
-  gram(n, r, Q, r, Bm, r, nullptr, part, are, st);
-  double* wim = Bm;  // B no longer needed: reuse for Im s
-  hipLaunchKernelGGL((k_im_s<S>), dim3(ew_grid(n)), dim3(256), 0, st, n, (const cplx_t<S>*)op->sc, wim);
-  gram(n, r, Q, r, Q, r, wim, part, aim, st);
-  if ((s = c.Ac.ensure(2 * sizeof(double) * r * r)) || (s = c.Ainv.ensure(2 * sizeof(double) * r * r)) ||
+  if ((s = c.Q.ensure(n * (size_t)r * (c.q_f32 ? sizeof(float) : sizeof(double)))) ||
+      (s = c.W1.ensure(n * (size_t)r * sizeof(double))) || (s = c.Ac.ensure(2 * sizeof(double) * r * r)) ||
+      (s = c.Ainv.ensure(2 * sizeof(double) * r * r)) ||
       (s = c.qpart.ensure(sizeof(double) * 2 * (size_t)r * std::max(qt_nblocks(n), qt_nblocks32(n)))))
     return s;
-  hipLaunchKernelGGL(k_combine_ac, dim3((r * r + 255) / 256), dim3(256), 0, st, r * r, are, aim, (double*)c.Ac.ptr);
-  gj_inverse(r, (const double*)c.Ac.ptr, gjw, (double*)c.Ainv.ptr, info, cond, st);
+  // the Galerkin matrix X^T A X = X^T B - i X^T diag(Im s) X of an n x r basis
+  // X into out (complex r x r); B = (L - diag(Re s)) X and then Im s go
+  // through the n x r buffer B
+  auto galerkin = [&](const double* X, double* B, double* out) {
+    size_t nbl = (n + 3) / 4;
+    if (nbl > 16384) nbl = 16384;
+    hipLaunchKernelGGL((k_batched_lap<S>), dim3((unsigned)nbl), dim3(64, 4), 0, st, op->geom, r, X,
+                       (const cplx_t<S>*)op->sc, op->code, B);
+    gram(n, r, X, r, B, r, nullptr, part, are, st);
+    hipLaunchKernelGGL((k_im_s<S>), dim3(ew_grid(n)), dim3(256), 0, st, n, (const cplx_t<S>*)op->sc, B);
+    gram(n, r, X, r, X, r, B, part, aim, st);
+    hipLaunchKernelGGL(k_combine_ac, dim3((r * r + 255) / 256), dim3(256), 0, st, r * r, are, aim, out);
+  };
+  double* Ac = (double*)c.Ac.ptr;
+  if (c.pass1) {
+    // fp64 basis: the solves use Q1 = P S1 itself.  The correction
+    // Q (Q^T A Q)^{-1} Q^T depends only on the span of the basis, and Q1 spans
+    // what Q = Q1 S2 spans (Q1^T Q1 = I up to about cond(P)^2 eps <= 1e-2 at
+    // the drop threshold, so Q1^T A Q1 is as well conditioned as A_c); the
+    // second pass is run only when the orthonormal basis is inspected.
+    gemm<double>((int)n, r, pu, P, ldp, S1, r, nullptr, ACT_NONE, (double*)c.Q.ptr, r, st);
+    galerkin((const double*)c.Q.ptr, (double*)c.W1.ptr, Ac);
+  } else {
+    // fp32 stored basis (when requested, or for C64): CholeskyQR2, Q rounded
+    // to its stored values, A_c formed from the rounded basis.  Pass 2:
+    // G2 = Q1^T Q1, Cholesky without dropping -> S2 (r x r, into S1); its rank
+    // record goes to info[2..3], read back with the inverse's record (every
+    // kernel below is sized by r alone, so a lost rank only spoils values).
+    gemm<double>((int)n, r, pu, P, ldp, S1, r, nullptr, ACT_NONE, Q1, r, st);
+    gram(n, r, Q1, r, Q1, r, nullptr, part, G2, st);
+    chol_drop(r, G2, 0.0, 0, X, S1, info + 2, st);
+    double* Q = (double*)c.W1.ptr;
+    gemm<double>((int)n, r, r, Q1, r, S1, r, nullptr, ACT_NONE, Q, r, st);
+    // Q <- its stored values (rounded in place), then B in Q1
+    hipLaunchKernelGGL((k_round_q<float>), dim3(ew_grid(n * r)), dim3(256), 0, st, n * (size_t)r, Q, (float*)c.Q.ptr);
+    galerkin(Q, Q1, Ac);
+  }
+  gj_inverse(r, Ac, nullptr, (double*)c.Ainv.ptr, info, cond, st);
   e = hipMemcpyAsync(op->host, info, sizeof(int) * 8 + sizeof(double), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "coarse: inverse readback");
   (void)hipEventRecord(e1, st);
   if ((s = sync_stream(st, "coarse: inverse"))) return s;
   const int* rec = (const int*)op->host;
-  if (rec[3] != 0 || rec[2] != r)
+  if (!c.pass1 && (rec[3] != 0 || rec[2] != r))
     return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", rec[2], r);
   if (rec[0] != 0) return fail(HELM_E_SINGULAR, "coarse: A_c is singular (zero pivot)");
   c.cond_est = *(double*)((int*)op->host + 8);
@@ -532,6 +576,42 @@ helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bo
     return fail(HELM_E_SINGULAR, "coarse: %d of the %d trunk columns are numerically dependent and no_drop is set",
                 p_used - c.rank, p_used);
   return HELM_OK;
+}
+
+helm_status coarse_orthonormal(helm_op_s* op, double* Qout, double* Acout, hipStream_t st) {
+  Coarse& c = op->coarse;
+  if (!c.valid || !c.pass1) return fail(HELM_E_INVAL, "coarse: no first-pass basis to orthonormalize");
+  const size_t n = op->nn;
+  const int r = c.rank, pu = c.p_used;
+  if (r == 0) return HELM_OK;
+  // the regions of the set-up's small buffer (laid out as in coarse_build)
+  double* part = (double*)c.small.ptr;
+  double* G = part + (size_t)gram_nblocks(n) * pu * pu;
+  double* X = G + (size_t)pu * pu;
+  double* S2 = X + (size_t)pu * pu;
+  double* G2 = S2 + (size_t)pu * pu;
+  double* gjw = G2 + 3 * (size_t)pu * pu;
+  int* info = (int*)(gjw + 4 * (size_t)pu * pu);
+  const double* Q1 = (const double*)c.Q.ptr;
+  // second CholeskyQR pass: G2 = Q1^T Q1 = S2^-T S2^-1
+  gram(n, r, Q1, r, Q1, r, nullptr, part, G2, st);
+  chol_drop(r, G2, 0.0, 0, X, S2, info + 2, st);
+  if (Qout) gemm<double>((int)n, r, r, Q1, r, S2, r, nullptr, ACT_NONE, Qout, r, st);
+  hipError_t e;
+  if (Acout) {
+    // A_c = Q^T A Q = S2^T (Q1^T A Q1) S2, formed in the work region, copied out
+    hipLaunchKernelGGL(k_sandwich, dim3(r), dim3(128), 0, st, r, (const double*)S2, (const double*)c.Ac.ptr, gjw);
+    e = hipMemcpyAsync(Acout, gjw, sizeof(double) * 2 * r * r, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "coarse: A_c readback");
+  }
+  e = hipMemcpyAsync(op->host, info + 2, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "coarse: second pass readback");
+  helm_status s = sync_stream(st, "coarse: second pass");
+  if (s) return s;
+  const int* rec = (const int*)op->host;
+  if (rec[1] != 0 || rec[0] != r)
+    return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", rec[0], r);
+  return launch_check("coarse: orthonormal basis");
 }
 
 template <typename S>

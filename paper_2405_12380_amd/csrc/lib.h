@@ -41,12 +41,13 @@ struct Coarse {
   int ksq_version = -1;
   bool valid = false;
   bool q_f32 = false;  // basis stored in fp32
+  bool pass1 = false;  // stored basis is the first CholeskyQR pass's Q1 (fp64 path)
   int rank = 0;
   double cond_est = 0.0;
   double setup_ms = 0.0;
-  Buffer Q;      // n x rank, real (dtype's precision), row-major
-  Buffer Ainv;   // rank x rank complex128, row-major
-  Buffer Ac;     // rank x rank complex128, row-major (kept for inspection)
+  Buffer Q;      // n x rank, real (dtype's precision), row-major: the basis the solves use
+  Buffer Ainv;   // rank x rank complex128, row-major: inverse of the Galerkin matrix in that basis
+  Buffer Ac;     // rank x rank complex128, row-major: that Galerkin matrix
   Buffer T;      // trunk matrix at the op's nodes, n x p (dtype's precision)
   int T_serial = -1;
   Buffer W1, W2;  // setup work (n x p_used fp64 each)
@@ -120,6 +121,11 @@ helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bo
 template <typename S>
 helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st);  // z += Q A_c^-1 Q^T r1
 void coarse_release(helm_op_s* op);
+// The orthonormal basis Q (device, n x r fp64, may be NULL) and its Galerkin
+// matrix A_c = Q^T A Q (host, complex r x r, may be NULL) of a built coarse
+// space whose stored basis is the first CholeskyQR pass's: the second pass is
+// run here, for inspection.  Synchronous.
+helm_status coarse_orthonormal(helm_op_s* op, double* Q, double* Ac, hipStream_t st);
 // Free the setup work buffers and the cached trunk matrix, keeping Q and A_c^{-1}.
 void coarse_trim(helm_op_s* op);
 // Validation of meta_opts against an op and a network (meta.hip).

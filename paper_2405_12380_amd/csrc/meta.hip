@@ -693,6 +693,12 @@ helm_status meta_coarse_info(helm_op op, don_net net, const meta_opts* o, int* r
   if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, hs))) return s;
   const int r = op->coarse.rank;
   *rank = r;
+  if (op->coarse.pass1 && r > 0) {
+    // the solves use the first-pass basis; the orthonormal one is formed here
+    if (Ac && ac_cap < (size_t)r * r) return fail(HELM_E_INVAL, "meta_coarse_info: Ac capacity %zu < %d", ac_cap, r * r);
+    if (Q && q_cap < op->nn * (size_t)r) return fail(HELM_E_INVAL, "meta_coarse_info: Q capacity too small");
+    return coarse_orthonormal(op, (double*)Q, Ac, hs);
+  }
   if (Ac) {
     if (ac_cap < (size_t)r * r) return fail(HELM_E_INVAL, "meta_coarse_info: Ac capacity %zu < %d", ac_cap, r * r);
     hipError_t e = hipMemcpyAsync(Ac, op->coarse.Ac.ptr, sizeof(double) * 2 * r * r, hipMemcpyDeviceToHost, hs);
