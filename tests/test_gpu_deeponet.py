@@ -36,6 +36,25 @@ def test_trunk_3d_config_shape(n):
     assert rel_err(T, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("widths", [[3, 38, 22, 10], [3, 37, 29, 12]])
+def test_trunk_ragged_widths(widths):
+    """Layer widths that are not multiples of the GEMM tiles or of the 16-deep
+    k chunk: even widths (rows 16-byte aligned) take the register-A product
+    with a partial last k chunk and partial column tiles, odd widths the
+    LDS-staged one; nonzero biases.  Against the oracle's trunk matrix."""
+    n = (21, 13, 11)
+    C = I.config2(0, n=n)
+    g = np.random.default_rng(11)
+    trunk = [(W, g.standard_normal(W.shape[1]) * 0.1) for W, _ in I.glorot_mlp(widths, g, first_gain=3.0)]
+    p = widths[-1]
+    branch = I.glorot_mlp([2 * 16 ** 3 + 1, 24, 2 * p], g)
+    op = make_op(helm, C, helm.C128)
+    net = helm.DeepONet(helm.C128, branch, trunk, p, head="split_output", branch_grid=(16, 16, 16), k_input=True)
+    T = to_np(net.trunk(op)).reshape(-1, p)
+    ref = don_or.trunk_matrix(I.node_points(C["n"]), trunk)
+    assert rel_err(T, ref) <= 1e-13
+
+
 @pytest.mark.parametrize("dtype", [helm.C128, helm.C64])
 def test_full_split_input_c1(dtype):
     C = I.config1()
