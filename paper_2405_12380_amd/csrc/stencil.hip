@@ -238,7 +238,12 @@ __global__ __launch_bounds__(512) void k_rbgs_fused(StencilGeom g, const cplx_t<
 constexpr int RB_TX = 64, RB_TY = 8, RB_LX = RB_TX + 4, RB_LY = RB_TY + 4, RB_PL = RB_LX * RB_LY, RB_NS = 6;
 constexpr int RB_RROW = (RB_TX + 2) / 2, RB_NRED = RB_RROW * (RB_TY + 2);  // red nodes of the tile and its rim (330)
 constexpr unsigned RB_OOB = 0x80000000u;  // byte offset past the end of every buffer the kernel is given
-static_assert(RB_PL <= 4 * 256 && RB_NRED <= 2 * 256 && RB_TX * RB_TY == 2 * 256, "ring tile sizes");
+// 384 threads: one red update per thread and step (330 on the tile and its
+// rim), one black update on the first 256 (the tile's 256 black nodes), the
+// staged plane three positions per thread
+constexpr int RB_NT = 384, RB_NB = RB_TX * RB_TY / 2;
+constexpr int RB_QP = (RB_PL + RB_NT - 1) / RB_NT, RB_RU = (RB_NRED + RB_NT - 1) / RB_NT;
+static_assert(RB_NB <= RB_NT && RB_RU == 1, "ring tile sizes");
 
 typedef unsigned int rb_u4 __attribute__((ext_vector_type(4)));
 typedef unsigned int rb_u2 __attribute__((ext_vector_type(2)));
@@ -272,7 +277,7 @@ __device__ __forceinline__ unsigned rb_cw_off(unsigned boff) { return boff & ~3u
 __device__ __forceinline__ unsigned rb_cd(unsigned cw, unsigned boff) { return (cw >> (8 * (boff & 3u))) & 0xffu; }
 
 template <typename S, int DEPTH>
-__global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const cplx_t<S>* __restrict__ sc,
+__global__ __launch_bounds__(RB_NT) void k_rbgs_ring(StencilGeom g, int zb, const cplx_t<S>* __restrict__ sc,
                                                    const uint8_t* __restrict__ code,
                                                    const cplx_t<S>* __restrict__ uin, const cplx_t<S>* __restrict__ f,
                                                    cplx_t<S>* __restrict__ uout, double omega) {
@@ -297,19 +302,19 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
                : -1L;
   };
   auto boff = [](long p, unsigned esz) { return p >= 0 ? (unsigned)p * esz : RB_OOB; };
-  // staged plane k: thread t holds LDS positions t + 256 q (zero where there is no node)
-  auto load_plane = [&](int k, double2 (&pre)[4]) {
+  // staged plane k: thread t holds LDS positions t + RB_NT q (zero where there is no node)
+  auto load_plane = [&](int k, double2 (&pre)[RB_QP]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q;
+    for (int q = 0; q < RB_QP; ++q) {
+      const int e = t + RB_NT * q;
       pre[q] = rb_ld(r_u, boff(e < RB_PL ? node(e, k) : -1L, sizeof(C)), (const C*)nullptr);
     }
   };
-  auto store_plane = [&](int k, const double2 (&pre)[4]) {
+  auto store_plane = [&](int k, const double2 (&pre)[RB_QP]) {
     double2* P = ring[slot(k)];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (t + 256 * q < RB_PL) P[t + 256 * q] = pre[q];
+    for (int q = 0; q < RB_QP; ++q)
+      if (t + RB_NT * q < RB_PL) P[t + RB_NT * q] = pre[q];
   };
   // red node r (< RB_NRED) of plane k: LDS position on the tile or its one-node rim
   auto red_pos = [&](int r, int k) {
@@ -317,9 +322,12 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     const int lx = 1 + ((gx0 + 1 + gy0 + ly + k) & 1) + 2 * c;
     return ly * RB_LX + lx;
   };
-  // black node of plane k owned by thread t (32 per row, 8 rows)
+  // black node of plane k owned by thread t < RB_NB (32 per row, 8 rows); the
+  // other threads address a valid position and store nothing
+  const bool bact = t < RB_NB;
+  const int tb = bact ? t : t - RB_NB;
   auto black_pos = [&](int k) {
-    const int ly = 2 + t / (RB_TX / 2), c = t % (RB_TX / 2);
+    const int ly = 2 + tb / (RB_TX / 2), c = tb % (RB_TX / 2);
     const int lx = 3 - ((gx0 + gy0 + ly + k) & 1) + 2 * c;
     return ly * RB_LX + lx;
   };
@@ -330,18 +338,18 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
   };
   // this thread's u-th red node of plane k: LDS position, node index (-1: none)
   auto red_node = [&](int u, int k, int& e) -> long {
-    const int r = t + 256 * u;
+    const int r = t + RB_NT * u;
     e = red_pos(r < RB_NRED ? r : RB_NRED - 1, k);
     return r < RB_NRED ? node(e, k) : -1L;
   };
   // node data of a step's red updates (plane kr) and black update (plane kb)
-  auto load_next = [&](int kr, int kb, NodeIn (&rn)[2], NodeIn& bn) {
+  auto load_next = [&](int kr, int kb, NodeIn (&rn)[RB_RU], NodeIn& bn) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < RB_RU; ++u) {
       int e;
       load_node(red_node(u, kr, e), rn[u]);
     }
-    load_node(node(black_pos(kb), kb), bn);
+    load_node(bact ? node(black_pos(kb), kb) : -1L, bn);
   };
   // red half-sweep of plane k; the tile's values go to uout when `own`
   auto red = [&](int k, const NodeIn* in, bool own) {
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     const double2* Pm = ring[slot(k - 1)];
     const double2* Pp = ring[slot(k + 1)];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < RB_RU; ++u) {
       int e;
       const long p = red_node(u, k, e);
       const double2 v = rnd_store<S>(relax_upd<S>(g, rb_cd(in[u].cw, boff(p, 1)), P[e], P[e - 1], P[e + 1], P[e - RB_LX], P[e + RB_LX],
@@ -368,17 +376,17 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
   // registers at the loop's back-edge would make each step wait for its own
   // loads).  The kernel runs with DEPTH = 2; depths 3 and 4 measured no faster.
   struct Pre {
-    double2 pl[4];
-    NodeIn rn[2], bn;
+    double2 pl[RB_QP];
+    NodeIn rn[RB_RU], bn;
   };
   Pre S_[DEPTH];
-  NodeIn r0[2], r1[2];
+  NodeIn r0[RB_RU], r1[RB_RU];
   for (int k = z0 - 2; k <= z0 + 2; ++k) {
     load_plane(k, S_[0].pl);
     store_plane(k, S_[0].pl);
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < RB_RU; ++u) {
     int e;
     load_node(red_node(u, z0 - 1, e), r0[u]);
     load_node(red_node(u, z0, e), r1[u]);
@@ -397,13 +405,15 @@ __global__ __launch_bounds__(256) void k_rbgs_ring(StencilGeom g, int zb, const 
     load_next(z + DEPTH, z + DEPTH - 1, nxt.rn, nxt.bn);
     red(z + 1, cur.rn, z + 1 < z1);
     __syncthreads();
-    // black half-sweep of plane z on the tile
-    const int e = black_pos(z);
-    const double2* P = ring[slot(z)];
-    const double2 v = relax_upd<S>(g, rb_cd(cur.bn.cw, boff(node(e, z), 1)), P[e], P[e - 1], P[e + 1],
-                                   P[e - RB_LX], P[e + RB_LX], ring[slot(z - 1)][e], ring[slot(z + 1)][e], cur.bn.s,
-                                   cur.bn.f, omega, true);
-    rb_st(r_o, boff(z < z1 ? node(e, z) : -1L, sizeof(C)), v, (C*)nullptr);
+    // black half-sweep of plane z on the tile (wavefronts of the first 256 threads)
+    if (bact) {
+      const int e = black_pos(z);
+      const double2* P = ring[slot(z)];
+      const double2 v = relax_upd<S>(g, rb_cd(cur.bn.cw, boff(node(e, z), 1)), P[e], P[e - 1], P[e + 1],
+                                     P[e - RB_LX], P[e + RB_LX], ring[slot(z - 1)][e], ring[slot(z + 1)][e],
+                                     cur.bn.s, cur.bn.f, omega, true);
+      rb_st(r_o, boff(z < z1 ? node(e, z) : -1L, sizeof(C)), v, (C*)nullptr);
+    }
   };
   // the march is rounded up to a multiple of DEPTH steps: the steps past z1
   // store nothing (no branches around them, so the register sets stay put)
@@ -559,7 +569,7 @@ void stencil_rbgs_fused(const StencilGeom& g0, const void* sc, const uint8_t* co
     int zb = (int)(tiles * g.nz / 1024);
     zb = zb < 2 ? 2 : zb > 32 ? 32 : zb;
     const long nbr = tiles * ((g.nz + zb - 1) / zb);
-    hipLaunchKernelGGL((k_rbgs_ring<S, 2>), dim3((unsigned)nbr), dim3(256), 0, st, g, zb, (const C*)sc, code,
+    hipLaunchKernelGGL((k_rbgs_ring<S, 2>), dim3((unsigned)nbr), dim3(RB_NT), 0, st, g, zb, (const C*)sc, code,
                        (const C*)uin, (const C*)f, (C*)uout, omega);
   } else if (g.dim == 3)
     hipLaunchKernelGGL((k_rbgs_fused<S, 3>), dim3(nb), dim3(64, g.ty), 0, st, g, (const C*)sc, code, (const C*)uin,
