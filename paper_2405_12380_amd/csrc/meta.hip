@@ -242,18 +242,31 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
       if (e1 != hipSuccess) return hip_fail(e1, "gmres: status event");
       return launch_check("gmres: arnoldi step");
     };
-    int k = 0;
-    if ((s = enqueue_step(0))) return s;
+    int k = 0, queued = 0;  // steps 0 .. queued-1 are enqueued
+    double g1 = -1.0, g2 = -1.0;  // the cycle's last two residual estimates
     for (int j = 0; j < m; ++j) {
+      if (queued == j) {
+        if ((s = enqueue_step(j))) return s;
+        queued = j + 1;
+      }
       // look ahead: queue step j+1 before waiting for step j's status; if step j
       // ends the cycle the queued step is discarded (it only touches V_{j+1}, W,
       // column j+1 of H and g[j+1..j+2], none of which the back-solve and the
-      // update u += M(V_{0..j} y) read)
-      if (j + 1 < m && count + 1 < o->max_iters)
+      // update u += M(V_{0..j} y) read).  When the last two estimates, extended
+      // at their ratio, put step j at or below the tolerance, step j+1 would
+      // most likely be discarded and is not queued ahead (a wrong guess costs
+      // one wait for step j before step j+1 starts).
+      bool ahead = j + 1 < m && count + 1 < o->max_iters;
+      if (ahead && g1 > 0.0 && g2 > 0.0 && g1 * (g1 / g2) <= thr) ahead = false;
+      if (ahead) {
         if ((s = enqueue_step(j + 1))) return s;
+        queued = j + 2;
+      }
       hipError_t e1 = hipEventSynchronize(ev[j & 1]);
       if (e1 != hipSuccess) return hip_fail(e1, "gmres: status wait");
       const GmState hs = *slot[j & 1];
+      g2 = g1;
+      g1 = hs.gabs;
       count++;
       matvecs++;
       if (c.use_M) papps++;
