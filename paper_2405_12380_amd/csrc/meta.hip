@@ -386,6 +386,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       return e1 == hipSuccess ? launch_check("bicgstab: half 1") : hip_fail(e1, "bicgstab: half 1 record");
     };
     bool stopped = false, pending = false;
+    double half2_ratio = -1.0;  // ||r|| / ||s|| of the last iteration's second half
     if (count < o->max_iters) {
       if ((s = half1(true))) return s;
       pending = true;
@@ -395,6 +396,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       hipError_t e1 = hipEventSynchronize(ev[0]);
       if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: s");
       BiState hb = *hS;
+      const double ss_now = hb.ss;
       matvecs++;
       if (c.use_M) papps++;
       count++;
@@ -427,13 +429,18 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       bicg_scalar(BI_RR, bs, red + 7, st, dR);
       e1 = hipEventRecord(ev[1], st);
       if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: half 2 record");
-      if (count < o->max_iters) {  // look ahead: the next half 1
+      // look ahead: the next half 1, unless ||s|| scaled by the last second
+      // half's reduction predicts ||r|| at or below the tolerance (then the
+      // queued half would most likely be discarded)
+      const bool near = half2_ratio > 0.0 && ss_now * half2_ratio <= thr;
+      if (count < o->max_iters && !near) {
         if ((s = half1(false))) return s;
         pending = true;
       }
       e1 = hipEventSynchronize(ev[1]);
       if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: r");
       hb = *hR;
+      if (ss_now > 0.0) half2_ratio = hb.rr / ss_now;
       if (hb.flag) {
         status = hb.flag == -4 ? HELM_E_BREAKDOWN : HELM_E_NONFINITE;
         stopped = true;
@@ -446,6 +453,10 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
         break;
       }
       if (hb.rr <= thr) break;
+      if (!pending && count < o->max_iters) {  // the guess was wrong: queue the next half 1 now
+        if ((s = half1(false))) return s;
+        pending = true;
+      }
     }
     if (stopped) break;
     if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
