@@ -425,12 +425,54 @@ void coarse_release(helm_op_s* op) {
   c.W2.release();
   c.small.release();
   c.qpart.release();
+  if (c.pending) {
+    (void)hipEventSynchronize(c.ev1);
+    (void)hipEventDestroy(c.ev0);
+    (void)hipEventDestroy(c.ev1);
+    c.pending = false;
+  }
   c.valid = false;
   c.T_serial = -1;
 }
 
+// Checks the inverse's record (8 ints, then the condition estimate) that the
+// set-up copied to host memory, and settles the space: valid with its
+// condition estimate and set-up time, or invalid with the error.
+static helm_status coarse_settle(helm_op_s* op, const void* rec_host) {
+  Coarse& c = op->coarse;
+  const int* rec = (const int*)rec_host;
+  helm_status s = HELM_OK;
+  if (!c.pass1 && (rec[3] != 0 || rec[2] != c.rank))
+    s = fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", rec[2], c.rank);
+  else if (rec[0] != 0)
+    s = fail(HELM_E_SINGULAR, "coarse: A_c is singular (zero pivot)");
+  c.cond_est = *(const double*)(rec + 8);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, c.ev0, c.ev1);
+  c.setup_ms = ms;
+  (void)hipEventDestroy(c.ev0);
+  (void)hipEventDestroy(c.ev1);
+  c.pending = false;
+  c.valid = s == HELM_OK;
+  return s;
+}
+
+helm_status coarse_finish(helm_op_s* op) {
+  Coarse& c = op->coarse;
+  if (!c.pending) return HELM_OK;
+  hipError_t e = hipEventSynchronize(c.ev1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(c.ev0);
+    (void)hipEventDestroy(c.ev1);
+    c.pending = false;
+    c.valid = false;
+    return hip_fail(e, "coarse: inverse wait");
+  }
+  return coarse_settle(op, op->host + COARSE_REC);
+}
+
 template <typename TT, typename S>
-static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32, hipStream_t st) {
+static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32, bool defer, hipStream_t st) {
   Coarse& c = op->coarse;
   const size_t n = op->nn;
   helm_status s;
@@ -541,32 +583,31 @@ static helm_status coarse_build(helm_op_s* op, don_s* net, int p_used, bool qf32
     galerkin(Q, Q1, Ac);
   }
   gj_inverse(r, Ac, nullptr, (double*)c.Ainv.ptr, info, cond, st);
-  e = hipMemcpyAsync(op->host, info, sizeof(int) * 8 + sizeof(double), hipMemcpyDeviceToHost, st);
+  // the inverse's record goes to its own pinned slot; with defer set the
+  // space is returned pending and the record is checked by coarse_finish
+  // (a caller that waits on later work in the stream finds it complete)
+  e = hipMemcpyAsync(op->host + COARSE_REC, info, sizeof(int) * 8 + sizeof(double), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "coarse: inverse readback");
   (void)hipEventRecord(e1, st);
-  if ((s = sync_stream(st, "coarse: inverse"))) return s;
-  const int* rec = (const int*)op->host;
-  if (!c.pass1 && (rec[3] != 0 || rec[2] != r))
-    return fail(HELM_E_SINGULAR, "coarse: second CholeskyQR pass lost rank (%d of %d)", rec[2], r);
-  if (rec[0] != 0) return fail(HELM_E_SINGULAR, "coarse: A_c is singular (zero pivot)");
-  c.cond_est = *(double*)((int*)op->host + 8);
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  c.setup_ms = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  c.ev0 = e0;
+  c.ev1 = e1;
+  c.pending = true;
   c.valid = true;
-  return launch_check("coarse setup");
+  if ((s = launch_check("coarse setup"))) return s;
+  return defer ? HELM_OK : coarse_finish(op);
 }
 
-helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bool no_drop, hipStream_t st) {
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bool no_drop, hipStream_t st,
+                          bool defer) {
   Coarse& c = op->coarse;
+  helm_status s0 = coarse_finish(op);  // a space left pending by an earlier call
+  if (s0) return s0;
   const bool want_f32 = q_fp32 || op->dt == HELM_C64;
   if (!(c.valid && c.net_serial == don_serial(net) && c.p_used == p_used && c.ksq_version == op->ksq_version &&
         c.q_f32 == want_f32)) {
     c.valid = false;
-    helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, q_fp32, st)
-                                        : coarse_build<float, float>(op, net, p_used, true, st);
+    helm_status s = op->dt == HELM_C128 ? coarse_build<double, double>(op, net, p_used, q_fp32, defer, st)
+                                        : coarse_build<float, float>(op, net, p_used, true, defer, st);
     if (s) return s;
     c.net_serial = don_serial(net);
     c.ksq_version = op->ksq_version;

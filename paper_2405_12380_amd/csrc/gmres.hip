@@ -208,10 +208,20 @@ __global__ __launch_bounds__(64) void k_backsolve(int k, int m, const double* H,
   }
 }
 
-__global__ void k_gmres_init(double beta, double* g, int m) {
-  for (int i = threadIdx.x; i < 2 * (m + 1); i += blockDim.x) g[i] = 0.0;
-  __syncthreads();
-  if (threadIdx.x == 0) g[0] = beta;
+// cycle start from the reduced ||r||^2 in nrm[0]: g = beta e_1 and
+// nrm[2] = 1 / beta (0 when beta is 0 or not finite; the host then abandons
+// the cycle); ||r||^2 and nrm[1] go to the host record rec (pinned host
+// memory, made visible by the kernel itself as in k_arnoldi_finish)
+__global__ void k_gmres_start(double* nrm, double* g, int m, double* rec) {
+  const double b2 = nrm[0];
+  const double beta = sqrt(b2);
+  for (int i = threadIdx.x; i < 2 * (m + 1); i += blockDim.x) g[i] = i == 0 ? beta : 0.0;
+  if (threadIdx.x == 0) {
+    nrm[2] = (beta > 0.0 && isfinite(beta)) ? 1.0 / beta : 0.0;
+    rec[0] = b2;
+    rec[1] = nrm[1];
+    __threadfence_system();
+  }
 }
 
 void arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1, const double* h2,
@@ -222,8 +232,8 @@ void gmres_backsolve(int k, int m, const double* H, const double* g, double* y, 
   const size_t lds = sizeof(double) * 2 * ((size_t)k + (k <= BS_LDS_MAX ? (size_t)k * (k + 1) / 2 : 0));
   hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), lds, st, k, m, H, g, y);
 }
-void gmres_init(double beta, double* g, int m, hipStream_t st) {
-  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(256), 0, st, beta, g, m);
+void gmres_start(double* nrm, double* g, int m, double* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(256), 0, st, nrm, g, m, rec);
 }
 
 }  // namespace helm

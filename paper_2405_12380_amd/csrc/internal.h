@@ -132,7 +132,9 @@ struct GmState {
 void arnoldi_finish(int j, int m, double* H, double* g, double* cs, double* sn, const double* h1, const double* h2,
                     const double* npart, int nparts, GmState* gs, GmState* ghost, hipStream_t st);
 void gmres_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t st);
-void gmres_init(double beta, double* g, int m, hipStream_t st);
+// g = sqrt(nrm[0]) e_1 (m+1 complex), nrm[2] = 1/sqrt(nrm[0]) (0 if that is 0 or
+// not finite), rec[0..1] = nrm[0..1] (rec: device address of pinned host memory)
+void gmres_start(double* nrm, double* g, int m, double* rec, hipStream_t st);
 
 // ---- skinny products with the basis (coarse.hip) -----------------------------
 // y_i = sum_j Q_ij c_j for Q (n x r, r <= 128) and complex c (2r doubles, device);

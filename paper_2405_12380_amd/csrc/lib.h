@@ -42,6 +42,8 @@ struct Coarse {
   bool valid = false;
   bool q_f32 = false;  // basis stored in fp32
   bool pass1 = false;  // stored basis is the first CholeskyQR pass's Q1 (fp64 path)
+  bool pending = false;  // built, but the inverse's record is not yet checked (coarse_finish)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // set-up start and end while pending
   int rank = 0;
   double cond_est = 0.0;
   double setup_ms = 0.0;
@@ -117,7 +119,18 @@ helm_status don_trunk(don_s* net, helm_op_s* op, void* out, hipStream_t st);
 
 // ---- coarse space (coarse.hip) ----
 // Build or reuse the coarse space; HELM_E_SINGULAR if no_drop and a column was dropped.
-helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bool no_drop, hipStream_t st);
+// Builds (or reuses) the trunk-basis coarse space.  With defer set, a fresh
+// build returns without waiting for the Galerkin inverse: the space is then
+// pending and must be settled by coarse_finish before its results are trusted
+// (the solver does so at its first wait on later work).
+helm_status coarse_ensure(helm_op_s* op, don_s* net, int p_used, bool q_fp32, bool no_drop, hipStream_t st,
+                          bool defer = false);
+// Settles a pending space: waits for the set-up, checks the inverse's record
+// (HELM_E_SINGULAR on a zero pivot or a lost rank), sets cond_est and
+// setup_ms.  A no-op when nothing is pending.
+helm_status coarse_finish(helm_op_s* op);
+// doubles into the op's pinned host buffer where the set-up's inverse record lands
+constexpr size_t COARSE_REC = 1024;
 template <typename S>
 helm_status coarse_correct(helm_op_s* op, const void* r1, void* z, hipStream_t st);  // z += Q A_c^-1 Q^T r1
 void coarse_release(helm_op_s* op);

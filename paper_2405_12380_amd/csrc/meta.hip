@@ -174,33 +174,72 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
   EventPair ev(false);
   if (!ev.ok()) return fail(HELM_E_HIP, "gmres: event creation failed");
 
-  double fn;
-  if ((s = vec_norm<S>(op, f, &fn, st))) return s;
-  if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "gmres: ||f|| is not finite");
-  const double fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
-  const double thr = o->tol * fs;
+  // No host round trip at a cycle start that follows a restart (or opens
+  // the solve): ||f||^2 (once) and ||r||^2 are reduced on the device, the
+  // start kernel sets g = beta e_1 and 1/beta and copies both squares to the
+  // pinned record crec, and the cycle's first Arnoldi steps are queued behind
+  // it.  The host reads the record at its first wait in the cycle; if the
+  // cycle should not have started (beta at or below the tolerance, or not
+  // finite) the queued steps are discarded: they touch V, W, H, g and the
+  // status slots, never u.  After a cycle whose estimate met the tolerance
+  // the true residual most likely does too, so that start waits for its
+  // record before queueing anything.
+  double* crec = op->host + 192;
+  double* crec_dev = op->host_dev + 192;
+  nrm2_part<S>(n, f, part, st);
+  reduce_cols(part, rdb, 1, nrm + 1, st);
+  bool first = true;
+  double fs = 1.0, thr = 0.0;
   int count = 0, matvecs = 0, papps = 0, hlen = 0;
   helm_status status = HELM_NOT_CONVERGED;
   double beta = 0.0;
-  for (;;) {
-    // r = f - A u into V_0, beta = ||r||
-    stencil_resid<S>(op->geom, op->sc, op->code, f, u, Vj(0), part, st);
-    matvecs++;
-    reduce_cols(part, stb, 1, nrm, st);
-    if ((s = read_host(op, nrm, sizeof(double), st, "gmres: residual"))) return s;
-    beta = std::sqrt(op->host[0]);
+  bool est_met = false;  // the last cycle ended on its residual estimate
+  // reads the cycle-start record once the work behind it has completed; true
+  // when the solve ends at this cycle start (status set, or *err on failure)
+  auto start_ends = [&](helm_status* err) -> bool {
+    *err = HELM_OK;
+    beta = std::sqrt(crec[0]);
+    if (first) {
+      first = false;
+      const double fn = std::sqrt(crec[1]);
+      if (!std::isfinite(fn)) {
+        *err = fail(HELM_E_NONFINITE, "gmres: ||f|| is not finite");
+        return true;
+      }
+      fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
+      thr = o->tol * fs;
+      if ((*err = coarse_finish(op))) return true;
+    }
     if (o->history && hlen == 0) o->history[hlen++] = beta / fs;
     if (!std::isfinite(beta)) {
       status = HELM_E_NONFINITE;
-      break;
+      return true;
     }
     if (beta <= thr) {
       status = HELM_OK;
-      break;
+      return true;
     }
-    if (count >= o->max_iters) break;
-    scale_host<S>(n, Vj(0), 1.0 / beta, Vj(0), st);
-    gmres_init(beta, g, m, st);
+    return false;
+  };
+  for (;;) {
+    // r = f - A u into V_0, beta = ||r||, V_0 = r / beta
+    stencil_resid<S>(op->geom, op->sc, op->code, f, u, Vj(0), part, st);
+    matvecs++;
+    reduce_cols(part, stb, 1, nrm, st);
+    gmres_start(nrm, g, m, crec_dev, st);
+    scale_dev<S>(n, Vj(0), nrm + 2, Vj(0), st);
+    bool checked = false;  // the start record has been read
+    if (count >= o->max_iters || est_met) {
+      // no Arnoldi step will run, or the cycle most likely ends here: read the record now
+      if ((s = sync_stream(st, "gmres: residual"))) return s;
+      helm_status e2;
+      if (start_ends(&e2)) {
+        if (e2) return e2;
+        break;
+      }
+      if (count >= o->max_iters) break;
+      checked = true;
+    }
     // One Arnoldi step: z = M v_j, w = A z into W, CGS2 (or one classical
     // Gram-Schmidt pass with gs_passes = 1), Givens.  W stays
     // unnormalized; the next step forms v_{j+1} = W / ||W|| as its first kernel
@@ -244,6 +283,7 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
     };
     int k = 0, queued = 0;  // steps 0 .. queued-1 are enqueued
     double g1 = -1.0, g2 = -1.0;  // the cycle's last two residual estimates
+    bool ended = false;           // the solve ended at this cycle's start
     for (int j = 0; j < m; ++j) {
       if (queued == j) {
         if ((s = enqueue_step(j))) return s;
@@ -264,6 +304,14 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
       }
       hipError_t e1 = hipEventSynchronize(ev[j & 1]);
       if (e1 != hipSuccess) return hip_fail(e1, "gmres: status wait");
+      if (j == 0 && !checked) {
+        helm_status e2;
+        if (start_ends(&e2)) {
+          if (e2) return e2;
+          ended = true;
+          break;
+        }
+      }
       const GmState hs = *slot[j & 1];
       g2 = g1;
       g1 = hs.gabs;
@@ -276,9 +324,10 @@ helm_status gmres_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, meta_
         status = HELM_E_NONFINITE;
         break;
       }
-      if (hs.gabs <= thr || count >= o->max_iters || hs.hn == 0.0) break;
+      est_met = hs.gabs <= thr;
+      if (est_met || count >= o->max_iters || hs.hn == 0.0) break;
     }
-    if (status == HELM_E_NONFINITE) break;
+    if (ended || status == HELM_E_NONFINITE) break;
     // u += M (V_k y)
     gmres_backsolve(k, m, H, g, y, st);
     multi_axpy<S>(n, V, ldv, k, y, 1.0, nullptr, t, nullptr, st);
@@ -587,7 +636,10 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
   (void)hipEventCreate(&e2);
   (void)hipEventRecord(e0, st);
   if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
-    if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, st))) {
+    // GMRES settles the space at its first wait, so the set-up's last
+    // read-back does not stall the queue ahead of the first Arnoldi steps
+    const bool defer = o->kind == META_GMRES;
+    if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, st, defer))) {
       if (op->coarse.valid) st_out->rank_used = op->coarse.rank;
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
@@ -595,7 +647,6 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
       return s;
     }
     st_out->rank_used = op->coarse.rank;
-    st_out->cond_Ac_est = op->coarse.cond_est;
   }
   if (o->mg_levels > 0 && (s = mg_ensure(op, net, o, st))) {
     (void)hipEventDestroy(e0);
@@ -610,6 +661,11 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
   else s = relax_meta_drive<S>(op, c, f, u, st_out, st);
   (void)hipEventRecord(e2, st);
   (void)hipEventSynchronize(e2);
+  if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
+    const helm_status s2 = coarse_finish(op);  // still pending only if the solve ended early
+    if (!s) s = s2;
+    st_out->cond_Ac_est = op->coarse.cond_est;
+  }
   float a = 0.f, b = 0.f;
   (void)hipEventElapsedTime(&a, e0, e1);
   (void)hipEventElapsedTime(&b, e1, e2);
