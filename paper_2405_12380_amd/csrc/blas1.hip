@@ -695,6 +695,17 @@ __device__ void bicg_step(int step, BiState* bs, const double* red) {
     bs->rr = sqrt(red[0]);
     bs->rho0[0] = bs->rho[0];
     bs->rho0[1] = bs->rho[1];
+  } else if (step == BI_INIT) {
+    for (int q = 0; q < 2; ++q) {
+      bs->rho[q] = 0.0;
+      bs->beta[q] = 0.0;
+      bs->rho0[q] = bs->alpha[q] = bs->omega[q] = q == 0 ? 1.0 : 0.0;
+    }
+    bs->ss = 0.0;
+    bs->fn = red[0];
+    bs->rr = red[1];
+    bs->flag = 0;
+    bs->pad = 0;
   }
 }
 

@@ -115,7 +115,9 @@ template <typename S>
 void axpy_dev(size_t n, const void* x, void* y, const double* a, hipStream_t st);  // y += a x, a complex on device
 // scalar steps (single thread), reading the reduced values in `red`
 void bicg_scalar(int step, BiState* bs, const double* red, hipStream_t st, BiState* ghost = nullptr);
-enum { BI_RHO = 0, BI_ALPHA = 1, BI_SS = 2, BI_OMEGA = 3, BI_RR = 4 };
+// BI_INIT starts a sweep: rho0 = alpha = omega = 1, the rest 0, flag 0, and
+// red[0], red[1] (||f||^2 and ||r||^2 of the sweep's start) left in fn and rr
+enum { BI_RHO = 0, BI_ALPHA = 1, BI_SS = 2, BI_OMEGA = 3, BI_RR = 4, BI_INIT = 5 };
 
 // ---- GMRES small dense work (gmres.hip) -------------------------------------
 struct GmState {

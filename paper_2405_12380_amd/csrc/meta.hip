@@ -385,25 +385,46 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
     sh = sv;
   }
 
-  double fn;
-  if ((s = vec_norm<S>(op, f, &fn, st))) return s;
-  if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "bicgstab: ||f|| is not finite");
-  const double fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
-  const double thr = o->tol * fs;
-  int count = 0, matvecs = 0, papps = 0, hlen = 0;
+  // ||f||^2 and the first ||r||^2 are reduced on the device and reach the
+  // host in the first sweep's start record (pinned memory), read at the first
+  // wait: the first half 1 is queued behind them without a round trip, and
+  // is discarded if the solve should not have started (it touches neither u
+  // nor r).
+  BiState* hI = (BiState*)(op->host + 384);
+  BiState* dI = (BiState*)(op->host_dev + 384);
+  nrm2_part<S>(n, f, part, st);
+  reduce_cols(part, rdb, 1, red + 12, st);
+  stencil_resid<S>(op->geom, op->sc, op->code, f, u, r, part, st);
+  reduce_cols(part, stb, 1, red + 13, st);
+  int count = 0, matvecs = 1, papps = 0, hlen = 0;
   helm_status status = HELM_NOT_CONVERGED;
-  double rn;
-  if ((s = residual_norm<S>(op, f, u, r, &rn, st))) return s;
-  matvecs++;
-  if (o->history) o->history[hlen++] = rn / fs;
-  if (!std::isfinite(rn)) status = HELM_E_NONFINITE;
-  else if (rn <= thr) status = HELM_OK;
-  while (status == HELM_NOT_CONVERGED) {
+  double fs = 1.0, thr = 0.0, rn = 0.0;
+  bool start_read = false;
+  // reads the start record (once the work behind it has completed): the
+  // residual scale, the tolerance and the status at the start
+  auto read_start = [&]() -> helm_status {
+    start_read = true;
+    const double fn = std::sqrt(hI->fn);
+    if (!std::isfinite(fn)) return fail(HELM_E_NONFINITE, "bicgstab: ||f|| is not finite");
+    fs = fn > 0 ? fn : 1.0;  // residual scale: absolute residual when f = 0
+    thr = o->tol * fs;
+    rn = std::sqrt(hI->rr);
+    if (o->history) o->history[hlen++] = rn / fs;
+    if (!std::isfinite(rn)) status = HELM_E_NONFINITE;
+    else if (rn <= thr) status = HELM_OK;
+    return coarse_finish(op);
+  };
+  bool first_sweep = true;
+  for (;;) {
     copy_vec<S>(n, r, rh, st);
-    BiState init{};
-    init.rho0[0] = init.alpha[0] = init.omega[0] = 1.0;
-    hipError_t e = hipMemcpyAsync(bs, &init, sizeof init, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "bicgstab: state");
+    bicg_scalar(BI_INIT, bs, red + 12, st, first_sweep ? dI : nullptr);
+    if (first_sweep && count >= o->max_iters) {
+      // no iteration will run: read the record now
+      if ((s = sync_stream(st, "bicgstab: residual"))) return s;
+      if ((s = read_start())) return s;
+    }
+    first_sweep = false;
+    if (status != HELM_NOT_CONVERGED) break;
     // rho for the first iteration of this sweep
     dot_part<S>(n, rh, r, part, st);
     reduce_cols(part, rdb, 2, red + 8, st);
@@ -444,6 +465,13 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
       pending = false;
       hipError_t e1 = hipEventSynchronize(ev[0]);
       if (e1 != hipSuccess) return hip_fail(e1, "bicgstab: s");
+      if (!start_read) {
+        if ((s = read_start())) return s;
+        if (status != HELM_NOT_CONVERGED) {
+          stopped = true;
+          break;
+        }
+      }
       BiState hb = *hS;
       const double ss_now = hb.ss;
       matvecs++;
@@ -513,6 +541,7 @@ helm_status bicgstab_drive(helm_op_s* op, MetaCtx& c, const void* f, void* u, me
     if (!std::isfinite(rn)) status = HELM_E_NONFINITE;
     else if (rn <= thr) status = HELM_OK;
     else if (count >= o->max_iters) break;
+    if (status != HELM_NOT_CONVERGED) break;
   }
   if ((s = launch_check("bicgstab"))) return s;
   if ((s = residual_norm<S>(op, f, u, c.r1, &rn, st))) return s;
@@ -636,9 +665,9 @@ helm_status meta_dispatch(helm_op_s* op, don_s* net, const meta_opts* o, const v
   (void)hipEventCreate(&e2);
   (void)hipEventRecord(e0, st);
   if (net && (o->kind == META_GMRES || o->kind == META_BICGSTAB)) {
-    // GMRES settles the space at its first wait, so the set-up's last
+    // the Krylov drivers settle the space at their first wait, so the set-up's last
     // read-back does not stall the queue ahead of the first Arnoldi steps
-    const bool defer = o->kind == META_GMRES;
+    const bool defer = o->kind == META_GMRES || o->kind == META_BICGSTAB;
     if ((s = coarse_ensure(op, net, o->p_used, o->q_fp32 != 0, o->no_drop != 0, st, defer))) {
       if (op->coarse.valid) st_out->rank_used = op->coarse.rank;
       (void)hipEventDestroy(e0);
