@@ -569,7 +569,10 @@ __global__ __launch_bounds__(1024) void k_chol_drop(int p, const double* __restr
 
 // ---- Gauss-Jordan inverse of a complex r x r matrix (r <= 128), one workgroup ----
 // The matrix lives in registers: thread t owns row t / 8 and the 16 columns
-// [16 (t % 8), 16 (t % 8) + 16).  In-place Gauss-Jordan with partial pivoting
+// [16 (t % 8), 16 (t % 8) + 16), rotated by one register after every pivot
+// (before pivot k, a[q] holds column 16 (t % 8) + ((q + k) & 15)), so that the
+// pivot column is always a[0] of the threads that own it and every register
+// index is static.  In-place Gauss-Jordan with partial pivoting
 // (largest modulus among the rows not yet used as pivot rows, lowest row on
 // ties), without moving rows: per pivot the column is published in LDS (and
 // zeroed in the registers), every wavefront picks the pivot row p from the
@@ -597,24 +600,17 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     const int c = c0 + q;
     a[q] = (row_in && c < r) ? make_double2(A[2 * ((size_t)i * r + c)], A[2 * ((size_t)i * r + c) + 1]) : czero();
   }
-  // column k into buffer k & 1 (entries, and the moduli of the rows not yet
-  // pivot rows), and zeroed in the registers: the update of column k then
-  // leaves -f / pivot there
+  // column k (a[0] of its owners) into buffer k & 1 (entries, and the moduli
+  // of the rows not yet pivot rows), and zeroed in the registers: the update
+  // of column k then leaves -f / pivot there
   auto publish = [&](int k) {
-    const int qk = k & 15;
-    const bool own = cb == (k >> 4);
-    double2 v = czero();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const bool hit = q == qk, zap = hit && own;
-      v.x = hit ? a[q].x : v.x;
-      v.y = hit ? a[q].y : v.y;
-      a[q].x = zap ? 0.0 : a[q].x;
-      a[q].y = zap ? 0.0 : a[q].y;
-    }
-    if (own && row_in) {
-      pcol[k & 1][i] = v;
-      pabs[k & 1][i] = used ? -1.0 : hypot(v.x, v.y);
+    if (cb == (k >> 4)) {
+      const double2 v = a[0];
+      a[0] = czero();
+      if (row_in) {
+        pcol[k & 1][i] = v;
+        pabs[k & 1][i] = used ? -1.0 : hypot(v.x, v.y);
+      }
     }
   };
   publish(0);
@@ -666,29 +662,43 @@ __global__ __launch_bounds__(1024) void k_gj_inverse(int r, const double* __rest
     if (i == p) {
       used = true;
       const double2 ipiv = cdiv(make_double2(1.0, 0.0), pcol[buf][p]);
+      const bool ownk = cb == (k >> 4);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const double2 v = (c0 + q == k) ? make_double2(1.0, 0.0) : a[q];
+        const double2 v = (q == 0 && ownk) ? make_double2(1.0, 0.0) : a[q];
         a[q] = cmul(v, ipiv);
-        prow[c0 + q + cb] = a[q];
+        prow[c0 + q + cb] = a[q];  // slot (cb, q) holds the same column for every thread
       }
     }
     __syncthreads();
-    // every other row: A[i][:] <- A[i][:] - f A[p][:] (A[i][k] is 0 here)
+    // every other row: A[i][:] <- A[i][:] - f A[p][:] (A[i][k] is 0 here), two
+    // fused multiply-adds per component
     if (i != p && row_in) {
       const double2 f = pcol[buf][i];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) a[q] = csub(a[q], cmul(f, prow[c0 + q + cb]));
+      for (int q = 0; q < 16; ++q) {
+        const double2 pv = prow[c0 + q + cb];
+        a[q].x = fma(-f.x, pv.x, fma(f.y, pv.y, a[q].x));
+        a[q].y = fma(-f.x, pv.y, fma(-f.y, pv.x, a[q].y));
+      }
+    }
+    // rotate: a[q] <- a[q + 1], so a[0] holds column 16 cb + ((k + 1) & 15)
+    {
+      const double2 a0 = a[0];
+#pragma unroll
+      for (int q = 0; q < 15; ++q) a[q] = a[q + 1];
+      a[15] = a0;
     }
     if (k + 1 < r) publish(k + 1);
     __syncthreads();
   }
-  // row i of the table is row rowof[i] of the inverse; its column c is column perm[c]
+  // row i of the table is row rowof[i] of the inverse; its column c is column
+  // perm[c]; after r rotations a[q] holds column 16 cb + ((q + r) & 15)
   if (row_in) {
     const int to_row = rowof[i];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int c = c0 + q;
+      const int c = c0 + ((q + r) & 15);
       if (c < r) {
         const int to = perm[c];
         Ainv[2 * ((size_t)to_row * r + to)] = a[q].x;
