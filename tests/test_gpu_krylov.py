@@ -101,14 +101,19 @@ def test_not_converged_keeps_iterate():
     assert 0 < stats["rel_res"] < 1
 
 
-def test_nonfinite_input_reported():
+@pytest.mark.parametrize("kind", ["bicgstab", "gmres"])
+def test_nonfinite_input_reported(kind):
+    """A NaN in f: the solve reports HELM_E_NONFINITE (the norms are read at the
+    first wait, after the first step is queued) and leaves u as it was."""
     C = _c2(8)
     op = make_op(helm, C, helm.C128)
     f = C["f"].copy()
     f.ravel()[5] = np.nan
-    u = op.field()
-    st, stats = helm.meta_solve(op, None, op.field(f), u, kind="bicgstab", tol=1e-6, max_iters=10)
+    u0 = np.random.default_rng(3).standard_normal(f.size) + 0j
+    u = op.field(u0)
+    st, stats = helm.meta_solve(op, None, op.field(f), u, kind=kind, tol=1e-6, max_iters=10)
     assert st == helm.E_NONFINITE
+    assert np.array_equal(to_np(u), u0)
 
 
 # complex64 on the seeded-network config 1 relaxation: the iteration diverges
