@@ -121,12 +121,6 @@ helm_status precond_apply(helm_op_s* op, const MetaCtx& c, const void* v, void* 
   return launch_check("precond");
 }
 
-static helm_status read_host(helm_op_s* op, const void* dev, size_t bytes, hipStream_t st, const char* what) {
-  hipError_t e = hipMemcpyAsync(op->host, dev, bytes, hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return hip_fail(e, what);
-  return sync_stream(st, what);
-}
-
 // ---------------------------------------------------------------------------
 // GMRES(m), CGS2, right preconditioning
 // ---------------------------------------------------------------------------
