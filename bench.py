@@ -243,7 +243,7 @@ def main():
                for k, v in kp.items()}
     if dom == "mfma_setup":
         achieved = (tot / max(cnt, 1)) / (per_launch_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "kernel": "k_gemm_ra + k_gram (fp64 MFMA set-up products)",
+        roofline = {"bound": "mfma", "kernel": "k_gemm + k_gram (fp64 MFMA set-up products)",
                     "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom, n[0]),
                     "flops_per_launch": tot / max(cnt, 1), "avg_launch_us": round(per_launch_ms * 1e3, 2),

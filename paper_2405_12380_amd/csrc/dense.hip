@@ -165,118 +165,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       }
 }
 
-// ---- MFMA GEMM, A operand straight into registers (fp64) -----------------------
-// Same product as k_gemm, for row-major A with 16-byte aligned rows (lda even,
-// A 16-byte aligned).  256 x 64 tile per workgroup of four wavefronts, each
-// 64 x 64 (4 x 4 MFMA tiles).  Within each 16-deep k chunk the k index is
-// permuted so that a lane's A values are contiguous: at k-step s lane group
-// g = lane / 16 supplies k0 + 4 g + s (W is read with the same permutation, so
-// the product is unchanged; only the order of the partial sums inside a chunk
-// differs from k_gemm).  Each lane then loads its four A values of a tile as
-// two 16-byte loads and the four lane groups together read whole rows of the
-// chunk: A never passes through LDS.  W chunks (16 x 64) are staged in LDS,
-// double-buffered, one barrier per chunk; the next chunk's A values are in
-// flight while the current one is multiplied (two register sets, the chunk
-// loop unrolled by two).  Measured 48-53 TFLOP/s on the 262144 x 256 x 256
-// trunk layer against 45-46 for k_gemm.
-constexpr int GR_M = 256, GR_N = 64, GR_K = 16, GR_PAD = 4;
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_ra(
-    int M, int N, int K, const double* __restrict__ A, size_t lda, const double* __restrict__ W, size_t ldw,
-    const double* __restrict__ bias, int act, double* __restrict__ C, size_t ldc) {
-  typedef double d2v __attribute__((ext_vector_type(2)));
-  __shared__ double Ws[2][GR_K][GR_N + GR_PAD];
-  const int nbn = (N + GR_N - 1) / GR_N;
-  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int bm = (int)(lb / nbn) * GR_M, bn = (int)(lb % nbn) * GR_N;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = lane >> 4, r16 = lane & 15;
-  const int wm = wave * 64;
-  d4 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  // this lane's A values of chunk k0: ar[a][s] = A[bm + wm + 16 a + r16][k0 + 4 g + s]
-  auto loadA = [&](int k0, d4 (&ar)[4]) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int row = bm + wm + 16 * a + r16, k = k0 + 4 * g;
-      const double* p = A + (size_t)row * lda + k;
-      if (row < M && k + 3 < K) {
-        const d2v x = reinterpret_cast<const d2v*>(p)[0], y = reinterpret_cast<const d2v*>(p)[1];
-        ar[a] = d4{x.x, x.y, y.x, y.y};
-      } else {
-        const bool r_ok = row < M;
-        ar[a] = d4{r_ok && k < K ? p[0] : 0.0, r_ok && k + 1 < K ? p[1] : 0.0, r_ok && k + 2 < K ? p[2] : 0.0,
-                   r_ok && k + 3 < K ? p[3] : 0.0};
-      }
-    }
-  };
-  constexpr int WQ = GR_K * GR_N / 256;  // W values per thread per chunk
-  double wv[WQ];
-  auto loadW = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < WQ; ++q) {
-      const int e = t + 256 * q, kk = e / GR_N, c = e % GR_N, gk = k0 + kk, gn = bn + c;
-      wv[q] = (gk < K && gn < N) ? W[(size_t)gk * ldw + gn] : 0.0;
-    }
-  };
-  auto storeW = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < WQ; ++q) {
-      const int e = t + 256 * q;
-      Ws[buf][e / GR_N][e % GR_N] = wv[q];
-    }
-  };
-  auto mult = [&](const d4 (&ar)[4], int buf) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double bv[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Ws[buf][4 * g + s][b * 16 + r16];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(ar[a][s], bv[b], acc[a][b]);
-    }
-  };
-  d4 A0[4], A1[4];
-  loadW(0);
-  storeW(0);
-  loadW(GR_K);
-  loadA(0, A0);
-  const int nc = (K + GR_K - 1) / GR_K;
-  // chunk c: barrier; W of chunk c + 1 (registers) into its LDS buffer; loads of
-  // W (c + 2) and A (c + 1); multiply chunk c.  A chunk past K multiplies zeros.
-  for (int c = 0; c < nc; c += 2) {
-    __syncthreads();
-    storeW(1);
-    loadW((c + 2) * GR_K);
-    loadA((c + 1) * GR_K, A1);
-    mult(A0, 0);
-    __syncthreads();
-    storeW(0);
-    loadW((c + 3) * GR_K);
-    loadA((c + 2) * GR_K, A0);
-    mult(A1, 1);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gr = bm + wm + a * 16 + acc_row(lane, i);
-        const int gc = bn + b * 16 + r16;
-        if (gr < M && gc < N) {
-          double v = acc[a][b][i];
-          if (bias) v += bias[gc];
-          C[(size_t)gr * ldc + gc] = activate<double>(v, act);
-        }
-      }
-}
-
 // ---- small-batch dense layer (GEMV class), split over K ------------------------
 // part[ks][b][n] = sum_{k in split ks} x[b][k] W[k][n]; then finalize adds the
 // splits in order, the bias and the activation.
@@ -755,15 +643,8 @@ template <typename T>
 void gemm(int M, int N, int K, const T* A, size_t lda, const T* W, size_t ldw, const T* bias, int act, T* C,
           size_t ldc, hipStream_t st) {
   kprof_begin(KP_MFMA, st);
-  if (sizeof(T) == sizeof(double) && lda % 2 == 0 && ((uintptr_t)A & 15) == 0) {
-    // fp64 with 16-byte aligned rows: A straight into registers
-    const int nb = ((M + GR_M - 1) / GR_M) * ((N + GR_N - 1) / GR_N);
-    hipLaunchKernelGGL(k_gemm_ra, dim3(nb), dim3(256), 0, st, M, N, K, (const double*)A, lda, (const double*)W, ldw,
-                       (const double*)bias, act, (double*)C, ldc);
-  } else {
-    const int nb = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
-    hipLaunchKernelGGL((k_gemm<T>), dim3(nb), dim3(256), 0, st, M, N, K, A, lda, W, ldw, bias, act, C, ldc);
-  }
+  const int nb = ((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N);
+  hipLaunchKernelGGL((k_gemm<T>), dim3(nb), dim3(256), 0, st, M, N, K, A, lda, W, ldw, bias, act, C, ldc);
   kprof_end(KP_MFMA, 2.0 * M * N * K, st);
 }
 
