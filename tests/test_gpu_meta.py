@@ -287,3 +287,22 @@ def test_no_drop_reports_singular():
     st, stats = helm.meta_solve(op, net2, op.field(C["f"]), u2, kind="gmres", restart=20, tol=0.0, max_iters=2,
                                 p_used=64, no_drop=True)
     assert stats["rank_used"] == 64
+
+
+def test_settled_setup_reports_condition():
+    """GMRES and BiCGStab settle the coarse set-up's last check at their first
+    wait; the condition number and set-up time they report are those of the
+    finished set-up: ||A_c||_1 ||A_c^{-1}||_1 against the oracle's Galerkin
+    matrix (App. C; the 1-norm condition does not see the sign of a basis
+    column), and the same figure again when the cached space is reused."""
+    C, s, op, net, cs = _setup(12, 32)
+    ref = np.linalg.cond(cs.Ac, 1)
+    for kind in ("gmres", "bicgstab"):
+        op2 = make_op(helm, C, helm.C128)
+        kw = dict(kind=kind, tol=1e-6, max_iters=50, n_r=3, omega=0.5, p_used=32)
+        st, stats = helm.meta_solve(op2, net, op2.field(C["f"]), op2.field(), **kw)
+        assert stats["rank_used"] == cs.rank
+        assert stats["setup_ms"] > 0
+        assert abs(stats["cond_Ac_est"] - ref) <= 1e-6 * ref
+        st, again = helm.meta_solve(op2, net, op2.field(C["f"]), op2.field(), **kw)
+        assert again["cond_Ac_est"] == stats["cond_Ac_est"]
